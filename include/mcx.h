@@ -1,0 +1,197 @@
+/*
+ * mcx.h -- C ABI of the MI355X (gfx950) Monte-Carlo electron-photon dose
+ * transport library (libmcx.so).
+ *
+ * The library runs the independent particle-history loop of PenRed
+ * (arXiv:2003.00796): JUMP (distance to the next interaction), STEP (move
+ * through the voxel geometry, stopping at interfaces) and KNOCK (simulate the
+ * interaction, create secondaries), Sec. 4.1; constant voxel geometry, Sec.
+ * 4.2.2 and Sec. 4.3; Class II electron/positron transport with parameters
+ * C1, C2, Wcc, Wcr, Eabs (Sec. 5.2, Sec. 6.1); the history-by-history
+ * estimators of Sec. 4.3, Eq. (1)-(3), with the square root of Eq. (2)
+ * restored; dose in eV/g per history (Fig. 8 caption).  Every step of the
+ * path runs in HIP kernels on the device; the host only validates, sizes
+ * memory and schedules launches.
+ *
+ * Conventions
+ *  - Every function returns an int status: MCX_OK (0) or a negative MCX_E_*
+ *    code.  mcx_last_error() returns a context-owned message describing the
+ *    last failure; it stays valid until the next call on that context.
+ *  - No exception, exit or abort crosses the ABI.
+ *  - Units: MeV, cm, g/cm^3.  Voxel arrays are x-fastest: index
+ *    (iz * ny + iy) * nx + ix.
+ *  - A context is used by one host thread at a time; contexts are
+ *    independent of each other.
+ *  - Stream arguments are hipStream_t values passed as void* (NULL = the
+ *    context's own stream).
+ */
+#ifndef MCX_H
+#define MCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCX_OK 0
+#define MCX_E_INVALID (-1)     /* bad argument value */
+#define MCX_E_STATE (-2)       /* call order (e.g. run before phantom) */
+#define MCX_E_NOMEM (-3)       /* device or host allocation failed */
+#define MCX_E_DEVICE (-4)      /* HIP runtime error or device fault */
+#define MCX_E_RANGE (-5)       /* a capacity or energy range exceeded */
+#define MCX_E_CANCELLED (-6)   /* reserved: run stopped on request */
+#define MCX_E_UNSUPPORTED (-7) /* feature not available in this build */
+
+#define MCX_FP64 0   /* all physics and sampling in FP64 */
+#define MCX_MIXED 1  /* FP32 physics and sampling; FP64 positions, boundary
+                        distances and tallies */
+
+#define MCX_PHOTON 0
+#define MCX_ELECTRON 1
+#define MCX_POSITRON 2
+
+#define MCX_SRC_PENCIL 0       /* all histories start at pos along dir */
+#define MCX_SRC_RECT 1         /* uniform over a width[0] x width[1] rectangle
+                                  centred on pos in the x-y plane, along dir */
+
+/* Model channel switches (mcx_transport.flags).  A switched-off hard channel
+ * behaves as if its cutoff were infinite (its stopping contribution becomes
+ * soft).  Used for analytic checks; production runs use 0. */
+#define MCX_NO_COMPTON (1u << 0)
+#define MCX_NO_PHOTO (1u << 1)
+#define MCX_NO_RAYLEIGH (1u << 2)
+#define MCX_NO_PAIR (1u << 3)
+#define MCX_NO_HARD_ELASTIC (1u << 4)
+#define MCX_NO_HARD_INELASTIC (1u << 5)
+#define MCX_NO_HARD_BREMS (1u << 6)
+
+typedef struct mcx_ctx mcx_ctx;
+
+/* Parameters of the synthetic analytic material models (one material, scaled
+ * per voxel by its mass density).  The library tabulates every cross section
+ * from these on the log grid of mcx_transport.  Photon: free-electron Klein-Nishina Compton; photoelectric
+ * pe_coef*(E/pe_eref)^-pe_exp; Rayleigh form factor
+ * ray_f0*(1+ray_a x^2)^-2; pair pp_coef*ln(E/2mc^2)^2.  Electron/positron:
+ * Bethe stopping power with mean excitation energy i_exc, Moller/Bhabha
+ * hard collisions, bremsstrahlung DCS brems_b/W, screened Rutherford
+ * elastic scattering (Z(Z+1) sum zz1_mol, screening charge z_screen). */
+typedef struct {
+  double z_mol, a_mol, zz1_mol, z_screen, i_exc;
+  double pe_coef, pe_eref, pe_exp;
+  double pp_coef;
+  double ray_f0, ray_a;
+  double brems_b;
+} mcx_material_desc;
+
+/* Transport parameters: the table grid (log-spaced, n_grid nodes between
+ * e_min and e_max), absorption energies Eabs per particle type, and the
+ * Class II parameters C1, C2, Wcc, Wcr of Sec. 5.2.  Validation: 16 <=
+ * n_grid <= 512, 0 < e_min < e_max, 0 < c1, c2 <= 0.2, wcc, wcr > 0,
+ * eabs[i] >= e_min. */
+typedef struct {
+  int n_grid;
+  double e_min, e_max;
+  double eabs[3];
+  double c1, c2;
+  double wcc, wcr;
+  uint32_t flags;
+} mcx_transport;
+
+/* Voxel phantom.  nx, ny, nz <= 1024; voxel sizes > 0; rho > 0 everywhere
+ * (MCX_E_INVALID otherwise).  rho is FP64, x-fastest; if rho_on_device is
+ * nonzero it is a device pointer that is copied on the device (the caller
+ * may free it after the call returns). */
+typedef struct {
+  int nx, ny, nz;
+  double voxel_cm[3];
+  double origin_cm[3];
+  const double* rho;
+  int rho_on_device;
+} mcx_phantom_desc;
+
+/* One source (a beamlet).  Histories are numbered by concatenating the
+ * sources in order: source s owns ids [sum_{r<s} n_hist_r, ... + n_hist_s).
+ * energy must lie in (eabs[particle], e_max]; dir must be a unit vector;
+ * start points must lie inside the phantom. */
+typedef struct {
+  int particle;
+  int kind;
+  double energy;
+  double pos[3];
+  double dir[3];
+  double width[2];
+  uint64_t n_hist;
+} mcx_source;
+
+/* Counters of the transport since the last mcx_reset_tallies. */
+typedef struct {
+  uint64_t histories;
+  uint64_t flights, compton, photo, rayleigh, pair;
+  uint64_t esteps, hard_el, hard_in, hard_br, delta, annih;
+  uint64_t crossings, secondaries, deposits;
+  uint64_t absorbed, escaped;
+  double e_dep, e_esc;
+  uint64_t pos_esc;
+  uint64_t iterations, chunks, tally_pairs;
+  double ms_transport, ms_flush;
+} mcx_stats;
+
+/* Create a context on HIP device `hip_device` computing in `precision`
+ * (MCX_FP64 or MCX_MIXED).  *out receives the context (NULL on failure). */
+int mcx_create(mcx_ctx** out, int hip_device, int precision);
+/* Release every device and host resource of the context (NULL is allowed). */
+void mcx_destroy(mcx_ctx* ctx);
+/* Message of the last failure on ctx (never NULL). */
+const char* mcx_last_error(mcx_ctx* ctx);
+
+/* Transport parameters; must precede mcx_load_material.  Copied. */
+int mcx_set_transport(mcx_ctx* ctx, const mcx_transport* t);
+/* Tabulate the material on the transport grid and copy the tables to the
+ * device.  Only mat_id 0 is supported (MCX_E_UNSUPPORTED otherwise). */
+int mcx_load_material(mcx_ctx* ctx, int mat_id, const mcx_material_desc* m);
+/* Copy the phantom densities to the device (converted to FP32 in MIXED
+ * precision).  Resets the tallies. */
+int mcx_load_phantom(mcx_ctx* ctx, const mcx_phantom_desc* p);
+/* Copy n >= 1 sources; history ids are their concatenation. */
+int mcx_set_sources(mcx_ctx* ctx, const mcx_source* s, int n);
+
+/* Tuning knobs (0 keeps the current value): bank = particles in flight per
+ * queue (capacity of each event queue), block = threads per block (multiple
+ * of 64, <= 1024), steps = Class II steps per visit of the e+- kernel. */
+int mcx_set_launch(mcx_ctx* ctx, uint32_t bank, uint32_t block, uint32_t steps);
+/* Enable (1) or disable (0) the per-history event hash and energy ledger
+ * used by the parity tests (costs extra device traffic). */
+int mcx_set_test_mode(mcx_ctx* ctx, int on);
+
+/* Transport histories [first_hist, first_hist + n_hist) with the counter
+ * RNG keyed by seed (< 2^32), ACCUMULATING into the tallies.  The run is
+ * complete when the call returns (kernels are queued on `stream`, the call
+ * waits for them).  Deterministic event content for a given
+ * (seed, history range).  first_hist + n_hist must not exceed the total of
+ * the sources nor 2^32. */
+int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, void* stream);
+
+/* Dose (eV/g per history) and its standard error per voxel from the
+ * accumulated counters, Eq. (1)-(3).  dose and sigma are caller-owned arrays
+ * of nx*ny*nz doubles, on the device if dst_on_device, else on the host;
+ * sigma may be NULL. */
+int mcx_get_dose(mcx_ctx* ctx, double* dose, double* sigma, int dst_on_device, void* stream);
+/* Raw counters Sum q and Sum q^2 (MeV) per voxel, same placement rules. */
+int mcx_get_tally(mcx_ctx* ctx, double* sum_q, double* sum_q2, int dst_on_device, void* stream);
+/* Zero the tallies, the history count and the statistics. */
+int mcx_reset_tallies(mcx_ctx* ctx);
+/* Statistics since the last reset. */
+int mcx_get_stats(mcx_ctx* ctx, mcx_stats* out);
+
+/* Per-history results of the LAST mcx_run (test mode only, else
+ * MCX_E_STATE): hashes[n_hist] = order-independent hash of the history's
+ * events; ledger[n_hist * 3] = {energy deposited, energy escaped, positrons
+ * escaped}.  Host arrays; either may be NULL. */
+int mcx_get_history_results(mcx_ctx* ctx, uint64_t* hashes, double* ledger);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,253 @@
+"""Python binding of libmcx: MI355X (gfx950) Monte-Carlo electron-photon dose
+transport behind a C ABI (include/mcx.h).
+
+The binding only marshals arguments (ctypes); every step of the particle-
+history loop runs in the library's HIP kernels.  PyTorch supplies device
+memory and streams where a caller passes tensors.  If the compiled library is
+missing, importing works but creating a Simulator raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcx.so")
+
+FP64, MIXED = 0, 1
+PHOTON, ELECTRON, POSITRON = 0, 1, 2
+SRC_PENCIL, SRC_RECT = 0, 1
+NO_COMPTON, NO_PHOTO, NO_RAYLEIGH, NO_PAIR = 1, 2, 4, 8
+NO_HARD_ELASTIC, NO_HARD_INELASTIC, NO_HARD_BREMS = 16, 32, 64
+
+ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM", -4: "MCX_E_DEVICE",
+          -5: "MCX_E_RANGE", -6: "MCX_E_CANCELLED", -7: "MCX_E_UNSUPPORTED"}
+
+# every symbol the C ABI exports (include/mcx.h)
+ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport", "mcx_load_material",
+               "mcx_load_phantom", "mcx_set_sources", "mcx_set_launch", "mcx_set_test_mode", "mcx_run",
+               "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
+               "mcx_get_history_results")
+
+
+class MaterialDesc(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "z_mol", "a_mol", "zz1_mol", "z_screen", "i_exc", "pe_coef", "pe_eref", "pe_exp", "pp_coef",
+        "ray_f0", "ray_a", "brems_b")]
+
+
+class Transport(C.Structure):
+    _fields_ = [("n_grid", C.c_int), ("e_min", C.c_double), ("e_max", C.c_double),
+                ("eabs", C.c_double * 3), ("c1", C.c_double), ("c2", C.c_double),
+                ("wcc", C.c_double), ("wcr", C.c_double), ("flags", C.c_uint32)]
+
+
+class PhantomDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("voxel_cm", C.c_double * 3),
+                ("origin_cm", C.c_double * 3), ("rho", C.c_void_p), ("rho_on_device", C.c_int)]
+
+
+class Source(C.Structure):
+    _fields_ = [("particle", C.c_int), ("kind", C.c_int), ("energy", C.c_double),
+                ("pos", C.c_double * 3), ("dir", C.c_double * 3), ("width", C.c_double * 2),
+                ("n_hist", C.c_uint64)]
+
+
+_STATS_U64_A = ("histories", "flights", "compton", "photo", "rayleigh", "pair", "esteps", "hard_el", "hard_in",
+                "hard_br", "delta", "annih", "crossings", "secondaries", "deposits", "absorbed", "escaped")
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in _STATS_U64_A] + [
+        ("e_dep", C.c_double), ("e_esc", C.c_double), ("pos_esc", C.c_uint64), ("iterations", C.c_uint64),
+        ("chunks", C.c_uint64), ("tally_pairs", C.c_uint64), ("ms_transport", C.c_double),
+        ("ms_flush", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class MCXError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libmcx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MCXError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.mcx_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int]
+        L.mcx_destroy.argtypes = [vp]
+        L.mcx_destroy.restype = None
+        L.mcx_last_error.argtypes = [vp]
+        L.mcx_last_error.restype = C.c_char_p
+        L.mcx_set_transport.argtypes = [vp, C.POINTER(Transport)]
+        L.mcx_load_material.argtypes = [vp, C.c_int, C.POINTER(MaterialDesc)]
+        L.mcx_load_phantom.argtypes = [vp, C.POINTER(PhantomDesc)]
+        L.mcx_set_sources.argtypes = [vp, C.POINTER(Source), C.c_int]
+        L.mcx_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.mcx_set_test_mode.argtypes = [vp, C.c_int]
+        L.mcx_run.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp]
+        L.mcx_get_dose.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.mcx_get_tally.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.mcx_reset_tallies.argtypes = [vp]
+        L.mcx_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.mcx_get_history_results.argtypes = [vp, vp, vp]
+        for f in ABI_SYMBOLS:
+            if f not in ("mcx_destroy", "mcx_last_error"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data)
+
+
+class Simulator:
+    """One library context: material, phantom, sources, tallies.
+
+    material: dict of MaterialDesc fields; transport: dict with n_grid, e_min,
+    e_max, eabs (3), c1, c2, wcc, wcr, flags; phantom: dict with shape
+    (nz, ny, nx), voxel (dx, dy, dz), origin, rho (numpy array or torch
+    tensor, float64); sources: list of dicts (particle, kind, energy, pos, dir,
+    width, n_hist).
+    """
+
+    def __init__(self, precision: int = FP64, device: int = 0):
+        self._L = lib()
+        self._h = C.c_void_p()
+        rc = self._L.mcx_create(C.byref(self._h), device, precision)
+        if rc != 0:
+            raise MCXError(f"mcx_create failed: {ERRORS.get(rc, rc)}")
+        self.precision = precision
+        self.shape = None
+        self.n_hist_total = 0
+
+    def close(self):
+        if self._h:
+            self._L.mcx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != 0:
+            msg = self._L.mcx_last_error(self._h).decode(errors="replace")
+            raise MCXError(f"{what}: {ERRORS.get(rc, rc)}: {msg}")
+
+    def set_transport(self, t: dict):
+        s = Transport()
+        s.n_grid = int(t["n_grid"])
+        s.e_min, s.e_max = float(t["e_min"]), float(t["e_max"])
+        for i in range(3):
+            s.eabs[i] = float(t["eabs"][i])
+        s.c1, s.c2, s.wcc, s.wcr = (float(t[k]) for k in ("c1", "c2", "wcc", "wcr"))
+        s.flags = int(t.get("flags", 0))
+        self._check(self._L.mcx_set_transport(self._h, C.byref(s)), "set_transport")
+
+    def load_material(self, m: dict, mat_id: int = 0):
+        d = MaterialDesc(**{k: float(m[k]) for k, _ in MaterialDesc._fields_})
+        self._check(self._L.mcx_load_material(self._h, mat_id, C.byref(d)), "load_material")
+
+    def load_phantom(self, ph: dict):
+        nz, ny, nx = ph["shape"]
+        rho = ph["rho"]
+        d = PhantomDesc(nx=nx, ny=ny, nz=nz)
+        for k in range(3):
+            d.voxel_cm[k] = float(ph["voxel"][k])
+            d.origin_cm[k] = float(ph["origin"][k])
+        keep = None
+        if hasattr(rho, "data_ptr") and getattr(rho, "is_cuda", False):
+            keep = rho.contiguous().double()
+            d.rho = C.c_void_p(keep.data_ptr())
+            d.rho_on_device = 1
+        else:
+            keep = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
+            d.rho = C.c_void_p(keep.ctypes.data)
+            d.rho_on_device = 0
+        self._check(self._L.mcx_load_phantom(self._h, C.byref(d)), "load_phantom")
+        self.shape = (nz, ny, nx)
+
+    def set_sources(self, sources):
+        arr = (Source * len(sources))()
+        for i, s in enumerate(sources):
+            arr[i].particle = int(s["particle"])
+            arr[i].kind = int(s["kind"])
+            arr[i].energy = float(s["energy"])
+            for k in range(3):
+                arr[i].pos[k] = float(s["pos"][k])
+                arr[i].dir[k] = float(s["dir"][k])
+            w = s.get("width", (0.0, 0.0))
+            arr[i].width[0], arr[i].width[1] = float(w[0]), float(w[1])
+            arr[i].n_hist = int(s["n_hist"])
+        self._check(self._L.mcx_set_sources(self._h, arr, len(sources)), "set_sources")
+        self.n_hist_total = sum(int(s["n_hist"]) for s in sources)
+
+    def set_launch(self, bank: int = 0, block: int = 0, steps: int = 0):
+        self._check(self._L.mcx_set_launch(self._h, bank, block, steps), "set_launch")
+
+    def set_test_mode(self, on: bool):
+        self._check(self._L.mcx_set_test_mode(self._h, 1 if on else 0), "set_test_mode")
+
+    def setup(self, workload: dict):
+        """material + transport + phantom + sources from a workload dict."""
+        self.set_transport(workload["transport"])
+        self.load_material(workload["material"])
+        self.load_phantom(workload["phantom"])
+        self.set_sources(workload["sources"])
+        return self
+
+    def run(self, seed: int, first: int, n: int, stream=None):
+        sp = C.c_void_p(stream) if stream else None
+        self._check(self._L.mcx_run(self._h, seed, first, n, sp), "run")
+
+    def reset(self):
+        self._check(self._L.mcx_reset_tallies(self._h), "reset_tallies")
+
+    def dose(self):
+        """(dose, sigma) in eV/g per history as numpy arrays of the phantom shape."""
+        nv = int(np.prod(self.shape))
+        d = np.zeros(nv)
+        s = np.zeros(nv)
+        self._check(self._L.mcx_get_dose(self._h, _ptr(d), _ptr(s), 0, None), "get_dose")
+        return d.reshape(self.shape), s.reshape(self.shape)
+
+    def dose_into(self, dose_t, sigma_t=None, stream=None):
+        """Write dose (and sigma) into device tensors (float64, contiguous)."""
+        sp = C.c_void_p(stream) if stream else None
+        self._check(self._L.mcx_get_dose(self._h, C.c_void_p(dose_t.data_ptr()),
+                                          C.c_void_p(sigma_t.data_ptr()) if sigma_t is not None else None, 1, sp),
+                    "get_dose")
+
+    def tally(self):
+        nv = int(np.prod(self.shape))
+        q = np.zeros(nv)
+        q2 = np.zeros(nv)
+        self._check(self._L.mcx_get_tally(self._h, _ptr(q), _ptr(q2), 0, None), "get_tally")
+        return q, q2
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._L.mcx_get_stats(self._h, C.byref(s)), "get_stats")
+        return s.as_dict()
+
+    def history_results(self, n: int):
+        h = np.zeros(n, dtype=np.uint64)
+        led = np.zeros((n, 3))
+        self._check(self._L.mcx_get_history_results(self._h, _ptr(h), _ptr(led)), "get_history_results")
+        return h, led

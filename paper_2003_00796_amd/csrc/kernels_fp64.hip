@@ -1,0 +1,53 @@
+// kernels_fp64.hip -- FP64 instantiation of the transport kernels.  Built with
+// -ffp-contract=off: no multiply-add fusion, so the arithmetic follows the
+// order of the source expressions.
+#include "transport_kernels.h"
+
+namespace mcx {
+
+hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s) {
+  const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(double);
+  const size_t sm_e = size_t(T_NCH) * a.tb.n * sizeof(double);
+  hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL(k_flight<double>, dim3(grid), dim3(block), sm_f, s, a, par);
+  hipLaunchKernelGGL(k_knock<double>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL(k_estep<double>, dim3(grid), dim3(block), sm_e, s, a, par);
+  hipLaunchKernelGGL(k_advance<double>, dim3(1), dim3(64), 0, s, a.cnt, par, target, a.cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_init<double>, dim3(1), dim3(64), 0, s, c, first, end, run_first, adm);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2,
+                        Counters* cnt, int test_mode, double* hist_led, uint64_t n_run, hipStream_t s) {
+  const int block = 256;
+  uint64_t g = (nslot + block - 1) / block;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_flush<double>, dim3(unsigned(g)), dim3(block), 0, s, keys, vals, nslot, sum_q, sum_q2, cnt,
+                     test_mode, hist_led, n_run);
+  return hipGetLastError();
+}
+
+hipError_t launch_dose(const double* sum_q, const double* sum_q2, const double* rho, uint64_t nvox, double vol,
+                       double nhist, double* dose, double* sigma, hipStream_t s) {
+  const int block = 256;
+  uint64_t g = (nvox + block - 1) / block;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_dose<double>, dim3(unsigned(g)), dim3(block), 0, s, sum_q, sum_q2, rho, nvox, vol, nhist,
+                     dose, sigma);
+  return hipGetLastError();
+}
+
+size_t estep_lds_bytes(int n, bool fp64) { return size_t(T_NCH) * n * (fp64 ? sizeof(double) : sizeof(float)); }
+
+hipError_t configure_fp64(int n_grid) {
+  const int bytes = int(estep_lds_bytes(n_grid, true));
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_estep<double>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace mcx

@@ -1,0 +1,38 @@
+// kernels_mixed.hip -- FP32-physics instantiation of the transport kernels
+// (positions, boundary distances, remaining mass thickness and tallies stay
+// FP64).  Multiply-add contraction is allowed here.
+#include "transport_kernels.h"
+
+namespace mcx {
+
+hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s) {
+  const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(float);
+  const size_t sm_e = size_t(T_NCH) * a.tb.n * sizeof(float);
+  hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL(k_flight<float>, dim3(grid), dim3(block), sm_f, s, a, par);
+  hipLaunchKernelGGL(k_knock<float>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL(k_estep<float>, dim3(grid), dim3(block), sm_e, s, a, par);
+  hipLaunchKernelGGL(k_advance<float>, dim3(1), dim3(64), 0, s, a.cnt, par, target, a.cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_dose(const double* sum_q, const double* sum_q2, const float* rho, uint64_t nvox, double vol,
+                       double nhist, double* dose, double* sigma, hipStream_t s) {
+  const int block = 256;
+  uint64_t g = (nvox + block - 1) / block;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_dose<float>, dim3(unsigned(g)), dim3(block), 0, s, sum_q, sum_q2, rho, nvox, vol, nhist,
+                     dose, sigma);
+  return hipGetLastError();
+}
+
+hipError_t configure_fp64(int n_grid);
+
+hipError_t configure_kernels(int n_grid, bool fp64) {
+  if (fp64) return configure_fp64(n_grid);
+  const int bytes = int(estep_lds_bytes(n_grid, false));
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_estep<float>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace mcx

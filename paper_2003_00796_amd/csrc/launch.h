@@ -1,0 +1,25 @@
+// launch.h -- host entry points of the kernels, one overload per precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mcx_internal.h"
+
+namespace mcx {
+
+// one iteration of the event loop: source, flight, knock, e+- steps, advance
+hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s);
+hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s);
+hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm,
+                             hipStream_t s);
+hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2,
+                        Counters* cnt, int test_mode, double* hist_led, uint64_t n_run, hipStream_t s);
+hipError_t launch_dose(const double* sum_q, const double* sum_q2, const double* rho, uint64_t nvox, double vol,
+                       double nhist, double* dose, double* sigma, hipStream_t s);
+hipError_t launch_dose(const double* sum_q, const double* sum_q2, const float* rho, uint64_t nvox, double vol,
+                       double nhist, double* dose, double* sigma, hipStream_t s);
+// LDS bytes the e+- kernel stages for a grid of n nodes
+size_t estep_lds_bytes(int n, bool fp64);
+hipError_t configure_kernels(int n_grid, bool fp64);
+
+}  // namespace mcx

@@ -1,0 +1,140 @@
+// mcx_internal.h -- data layout shared by the host runtime and the HIP
+// kernels of libmcx (not part of the public ABI).
+//
+// Layout in HBM (per context):
+//  - table block: n_grid x T_NCH values of the compute type T, channel-major
+//    (channel c occupies [c*n, (c+1)*n)), staged into LDS by the kernels;
+//  - phantom: rho[nz][ny][nx] in T (FP64 or FP32);
+//  - particle queues: Q_NQ structure-of-arrays banks of `cap` records each
+//    (positions f64 x3, direction T x3, energy T, uid u64, history u32, draw
+//    counter u32, packed voxel u32, type/child-count u32, event hash u64);
+//  - tally: open-addressing table of (history-in-chunk, voxel) keys with an
+//    FP64 score each, flushed per chunk into Sum q / Sum q^2 (FP64, one per
+//    voxel) -- the per-history estimator of Eq. (1)-(3) of the paper.
+#pragma once
+
+#include <stdint.h>
+
+namespace mcx {
+
+constexpr double kMc2 = 0.51099895000;       // MeV
+constexpr double kRe = 2.8179403262e-13;     // cm
+constexpr double kNa = 6.02214076e23;        // 1/mol
+constexpr double kAlpha = 1.0 / 137.035999084;
+constexpr double kHc = 1.23984198e-2;        // MeV Angstrom
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr int kMaxGrid = 512;
+constexpr uint64_t kEmptyKey = ~0ull;
+
+enum Particle : uint32_t { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
+
+// Table channels.  Photon: ln of mass attenuation per process.  Per lepton
+// type p (0 = e-, 1 = e+) at T_E + p*T_ES: ln soft stopping power, soft
+// stopping power, range, range-segment exponent q = 1 - dlnS/dlnE, ln hard
+// elastic, ln hard inelastic, ln hard bremsstrahlung, ln soft transport
+// coefficient, node sum of the three hard coefficients.  Zero values are
+// stored as ln 0 = -inf.
+enum TabChannel : int {
+  T_ENODE = 0,  // node energies
+  T_LMU_C = 1, T_LMU_PE = 2, T_LMU_R = 3, T_LMU_PP = 4,
+  T_PHOTON_END = 5,  // channels [0, 5) serve the photon kernels
+  T_E = 5,
+  O_LS = 0, O_S = 1, O_R = 2, O_Q = 3, O_LEL = 4, O_LIN = 5, O_LBR = 6, O_LT1S = 7, O_HSUM = 8,
+  T_ES = 9,
+  T_NCH = T_E + 2 * T_ES
+};
+
+// Event queues: photons waiting for a flight (ping-pong pair), electrons and
+// positrons waiting for Class II steps (ping-pong pair), photons waiting for
+// one interaction type each (Compton, photoelectric, Rayleigh, pair).
+enum Queue : int { Q_G0 = 0, Q_G1, Q_E0, Q_E1, Q_KC, Q_KP, Q_KR, Q_KX, Q_NQ };
+
+enum Stat : int {
+  S_FLIGHTS = 0, S_COMPTON, S_PHOTO, S_RAYLEIGH, S_PAIR, S_ESTEPS, S_HARD_EL, S_HARD_IN,
+  S_HARD_BR, S_DELTA, S_ANNIH, S_CROSSINGS, S_SECONDARIES, S_DEPOSITS, S_ABSORBED,
+  S_ESCAPED, S_POSESC, S_NSTAT
+};
+
+enum Overflow : uint32_t { OVF_QUEUE = 1u, OVF_TALLY = 2u, OVF_SOURCE = 4u, OVF_LOST = 8u };
+
+// bound on rejection-sampling attempts (acceptance is >= 0.3 for every sampler)
+constexpr int kMaxTries = 1000;
+
+struct Counters {
+  uint32_t n[Q_NQ];        // queue occupancy
+  uint32_t overflow;       // Overflow bits
+  uint32_t done;           // chunk finished
+  uint32_t adm;            // histories admitted by the next source launch
+  uint32_t iter;
+  uint64_t cursor;         // next history id to admit
+  uint64_t chunk_end;      // end of the current chunk (exclusive)
+  uint64_t run_first;      // first history id of the current mcx_run call
+  uint64_t stat[S_NSTAT];
+  double e_dep, e_esc;
+  uint64_t occupied;       // tally pairs seen by the last flush
+};
+
+template <typename T>
+struct Bank {
+  double* x; double* y; double* z;
+  T* u; T* v; T* w;
+  T* e;
+  uint64_t* uid;
+  uint32_t* hist;
+  uint32_t* ctr;
+  uint32_t* vox;    // ix | iy << 10 | iz << 20
+  uint32_t* flags;  // type | nchild << 2
+  uint64_t* hash;
+};
+
+struct SourceDev {
+  int particle, kind;
+  double energy;
+  double pos[3], dir[3], width[2];
+  uint64_t end;  // exclusive end of this source's history ids
+};
+
+template <typename T>
+struct Tab {
+  const T* t;        // channel-major block, T_NCH * n
+  int n;
+  T lemin, inv_dl;   // ln of the first node, 1 / log spacing
+  T emin;
+  T thr_pp, thr_in[2], thr_br;
+  T k_coef;          // n_mol pi r_e^2 sum Z(Z+1): K(E) = k_coef (mc^2 / pv)^2
+  T eta_a, eta_b;    // eta(E) = eta_a (mc^2)^2 / p^2c^2 * (1.13 + eta_b / beta^2)
+  T ray_a;
+};
+
+template <typename T>
+struct KArgs {
+  Tab<T> tb;
+  // geometry
+  int nx, ny, nz;
+  double dx, dy, dz, ox, oy, oz;
+  const T* rho;
+  // transport
+  T eabs[3];
+  T c2, wcc, wcr;
+  // run
+  uint32_t seed;
+  const SourceDev* src;
+  int nsrc;
+  // tally hash table, key = history id << 32 | voxel index
+  uint64_t* hkeys;
+  double* hvals;
+  uint64_t hmask;
+  double* sum_q;
+  double* sum_q2;
+  // test mode per-history outputs (indexed by history - cnt->run_first)
+  int test_mode;
+  uint64_t* hist_hash;
+  double* hist_led;      // 3 per history: deposited, escaped, positrons escaped
+  Counters* cnt;
+  Bank<T> q[Q_NQ];
+  uint32_t cap;          // records per queue
+  uint32_t steps;        // Class II steps per visit
+};
+
+}  // namespace mcx

@@ -1,0 +1,631 @@
+// runtime.hip -- host runtime and C ABI of libmcx (see include/mcx.h).
+//
+// The host validates input, tabulates the material, sizes the device memory
+// and drives the event loop: each chunk of histories runs as repeated
+// iterations {source, flight, knock, e+- steps, advance}; the host checks the
+// device-side completion flag after every batch of iterations, then flushes
+// the per-history tally of the chunk into Sum q / Sum q^2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "mcx.h"
+#include "mcx_internal.h"
+#include "tables.h"
+
+using namespace mcx;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct mcx_ctx {
+  int device = 0;
+  int precision = MCX_FP64;
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool have_transport = false, have_material = false, have_phantom = false, have_sources = false;
+  mcx_transport tr{};
+  mcx_material_desc mat{};
+  BuiltTables tabs;
+  DevBuf d_tab;
+  // phantom
+  int nx = 0, ny = 0, nz = 0;
+  double vox[3] = {0, 0, 0}, org[3] = {0, 0, 0};
+  DevBuf d_rho;
+  // sources
+  std::vector<SourceDev> src;
+  DevBuf d_src;
+  uint64_t total_hist = 0;
+  // tallies
+  DevBuf d_sumq, d_sumq2;
+  uint64_t n_done = 0;
+  // event queues
+  uint32_t cap = 1u << 21, block = 256, steps = 32;
+  DevBuf d_queues;
+  size_t queue_cap_built = 0;
+  DevBuf d_cnt;
+  Counters* h_cnt = nullptr;  // pinned
+  // tally table
+  uint64_t hslots = 1ull << 27;
+  DevBuf d_hkeys, d_hvals;
+  double pairs_per_hist = 0.0;
+  bool table_dirty = false;  // a failed run may have left entries behind
+  // test mode
+  int test_mode = 0;
+  DevBuf d_hhash, d_hled;
+  uint64_t last_n = 0;
+  bool last_valid = false;
+  // stats
+  uint64_t iterations = 0, chunks = 0, tally_pairs = 0;
+  double ms_transport = 0.0, ms_flush = 0.0;
+};
+
+namespace {
+
+int fail(mcx_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+int hip_fail(mcx_ctx* c, hipError_t e, const char* what) {
+  return fail(c, MCX_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void dfree(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+int dalloc(mcx_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+  if (b.p && b.bytes >= bytes) return MCX_OK;
+  dfree(b);
+  if (bytes == 0) return MCX_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, MCX_E_NOMEM, "hipMalloc of %zu bytes for %s failed: %s", bytes, what, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return MCX_OK;
+}
+
+bool fp64(const mcx_ctx* c) { return c->precision == MCX_FP64; }
+size_t tsize(const mcx_ctx* c) { return fp64(c) ? sizeof(double) : sizeof(float); }
+uint64_t nvox(const mcx_ctx* c) { return uint64_t(c->nx) * c->ny * c->nz; }
+
+// bytes of one queue record (structure of arrays)
+size_t record_bytes(const mcx_ctx* c) {
+  return 3 * sizeof(double) + 4 * tsize(c) + sizeof(uint64_t) * 2 + sizeof(uint32_t) * 4;
+}
+
+template <typename T>
+void carve_banks(mcx_ctx* c, KArgs<T>& a) {
+  char* p = static_cast<char*>(c->d_queues.p);
+  const size_t n = c->cap;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  for (int q = 0; q < Q_NQ; ++q) {
+    Bank<T>& b = a.q[q];
+    b.x = reinterpret_cast<double*>(take(n * sizeof(double)));
+    b.y = reinterpret_cast<double*>(take(n * sizeof(double)));
+    b.z = reinterpret_cast<double*>(take(n * sizeof(double)));
+    b.u = reinterpret_cast<T*>(take(n * sizeof(T)));
+    b.v = reinterpret_cast<T*>(take(n * sizeof(T)));
+    b.w = reinterpret_cast<T*>(take(n * sizeof(T)));
+    b.e = reinterpret_cast<T*>(take(n * sizeof(T)));
+    b.uid = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
+    b.hist = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
+    b.ctr = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
+    b.vox = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
+    b.flags = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
+    b.hash = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
+  }
+}
+
+size_t queue_bytes(const mcx_ctx* c) {
+  const size_t n = c->cap;
+  const size_t per = (n * sizeof(double) + 255) / 256 * 256 * 3 + (n * tsize(c) + 255) / 256 * 256 * 4 +
+                     (n * 8 + 255) / 256 * 256 * 2 + (n * 4 + 255) / 256 * 256 * 4;
+  return per * Q_NQ;
+}
+
+int ensure_workspace(mcx_ctx* c) {
+  int rc;
+  if (c->queue_cap_built != c->cap || !c->d_queues.p) {
+    dfree(c->d_queues);
+    if ((rc = dalloc(c, c->d_queues, queue_bytes(c), "event queues"))) return rc;
+    c->queue_cap_built = c->cap;
+  }
+  if (!c->d_cnt.p) {
+    if ((rc = dalloc(c, c->d_cnt, sizeof(Counters), "counters"))) return rc;
+    hipError_t e = hipMemset(c->d_cnt.p, 0, sizeof(Counters));
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemset counters");
+  }
+  if (!c->h_cnt) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->h_cnt), sizeof(Counters), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc counters");
+  }
+  if (!c->d_hkeys.p) {
+    if ((rc = dalloc(c, c->d_hkeys, c->hslots * sizeof(uint64_t), "tally keys"))) return rc;
+    if ((rc = dalloc(c, c->d_hvals, c->hslots * sizeof(double), "tally values"))) return rc;
+    hipError_t e = hipMemset(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(c->d_hvals.p, 0, c->hslots * sizeof(double));
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemset tally table");
+  }
+  return MCX_OK;
+}
+
+template <typename T>
+void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed) {
+  std::memset(&a, 0, sizeof(a));
+  const BuiltTables& b = c->tabs;
+  a.tb.t = static_cast<const T*>(c->d_tab.p);
+  a.tb.n = b.n;
+  a.tb.lemin = T(b.lemin);
+  a.tb.inv_dl = T(1.0 / b.dl);
+  a.tb.emin = T(c->tr.e_min);
+  a.tb.thr_pp = T(b.thr_pp);
+  a.tb.thr_in[0] = T(b.thr_in[0]);
+  a.tb.thr_in[1] = T(b.thr_in[1]);
+  a.tb.thr_br = T(b.thr_br);
+  a.tb.k_coef = T(b.k_coef);
+  a.tb.eta_a = T(b.eta_a);
+  a.tb.eta_b = T(b.eta_b);
+  a.tb.ray_a = T(b.ray_a);
+  a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
+  a.dx = c->vox[0]; a.dy = c->vox[1]; a.dz = c->vox[2];
+  a.ox = c->org[0]; a.oy = c->org[1]; a.oz = c->org[2];
+  a.rho = static_cast<const T*>(c->d_rho.p);
+  for (int i = 0; i < 3; ++i) a.eabs[i] = T(c->tr.eabs[i]);
+  a.c2 = T(c->tr.c2);
+  a.wcc = T(c->tr.wcc);
+  a.wcr = T(c->tr.wcr);
+  a.seed = seed;
+  a.src = static_cast<const SourceDev*>(c->d_src.p);
+  a.nsrc = int(c->src.size());
+  a.hkeys = static_cast<uint64_t*>(c->d_hkeys.p);
+  a.hvals = static_cast<double*>(c->d_hvals.p);
+  a.hmask = c->hslots - 1;
+  a.sum_q = static_cast<double*>(c->d_sumq.p);
+  a.sum_q2 = static_cast<double*>(c->d_sumq2.p);
+  a.test_mode = c->test_mode;
+  a.hist_hash = static_cast<uint64_t*>(c->d_hhash.p);
+  a.hist_led = static_cast<double*>(c->d_hled.p);
+  a.cnt = static_cast<Counters*>(c->d_cnt.p);
+  carve_banks(c, a);
+  a.cap = c->cap;
+  a.steps = c->steps;
+}
+
+template <typename T>
+int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t s) {
+  KArgs<T> a;
+  fill_args(c, a, seed);
+  const uint32_t target = c->cap / 4;
+  int grid = int((std::min<uint64_t>(c->cap, 2ull * target) + c->block - 1) / c->block);
+  grid = std::max(grid, 1);
+  const uint64_t table_budget = c->hslots / 2;  // keep the load factor <= 1/2
+  uint64_t done = 0;
+  auto t0 = std::chrono::steady_clock::now();
+  double flush_ms = 0.0;
+  int par = 0;
+  while (done < n) {
+    uint64_t chunk;
+    if (c->pairs_per_hist > 0.0) chunk = uint64_t(double(table_budget) / (1.25 * c->pairs_per_hist));
+    else chunk = 1ull << 16;
+    chunk = std::max<uint64_t>(chunk, 1024);
+    chunk = std::min<uint64_t>(chunk, n - done);
+    const uint64_t cf = first + done, ce = cf + chunk;
+    hipError_t e = launch_chunk_init(a.cnt, cf, ce, first, uint32_t(std::min<uint64_t>(chunk, target)), s);
+    if (e != hipSuccess) return hip_fail(c, e, "chunk init launch");
+    for (;;) {
+      for (int k = 0; k < 8; ++k) {
+        e = launch_iteration(a, par, target, grid, int(c->block), s);
+        if (e != hipSuccess) return hip_fail(c, e, "iteration launch");
+        par ^= 1;
+        c->iterations++;
+      }
+      e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(c, e, "transport iterations");
+      if (c->h_cnt->overflow & OVF_QUEUE)
+        return fail(c, MCX_E_RANGE, "event queue overflow (capacity %u records); raise the bank size", c->cap);
+      if (c->h_cnt->overflow & OVF_TALLY)
+        return fail(c, MCX_E_RANGE, "tally table overflow (%llu slots)", (unsigned long long)c->hslots);
+      if (c->h_cnt->overflow & OVF_SOURCE) return fail(c, MCX_E_INVALID, "a source point lies outside the phantom");
+      if (c->h_cnt->overflow & OVF_LOST) return fail(c, MCX_E_DEVICE, "a particle lost its direction (no exit face)");
+      if (c->h_cnt->done) break;
+    }
+    auto tf = std::chrono::steady_clock::now();
+    e = launch_flush(a.hkeys, a.hvals, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "tally flush");
+    flush_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
+    const double pairs = double(c->h_cnt->occupied);
+    c->tally_pairs += c->h_cnt->occupied;
+    const double pph = pairs / double(chunk);
+    c->pairs_per_hist = std::max(c->pairs_per_hist * 0.5, pph);
+    if (c->pairs_per_hist < 1.0) c->pairs_per_hist = 1.0;
+    c->chunks++;
+    done += chunk;
+  }
+  const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  c->ms_transport += total_ms - flush_ms;
+  c->ms_flush += flush_ms;
+  return MCX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcx_create(mcx_ctx** out, int hip_device, int precision) {
+  if (!out) return MCX_E_INVALID;
+  *out = nullptr;
+  if (precision != MCX_FP64 && precision != MCX_MIXED) return MCX_E_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    (void)hipGetLastError();
+    return MCX_E_DEVICE;
+  }
+  mcx_ctx* c = new (std::nothrow) mcx_ctx();
+  if (!c) return MCX_E_NOMEM;
+  c->device = hip_device;
+  c->precision = precision;
+  if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return MCX_E_DEVICE;
+  }
+  *out = c;
+  return MCX_OK;
+}
+
+void mcx_destroy(mcx_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
+                    &c->d_hvals, &c->d_hhash, &c->d_hled})
+    dfree(*b);
+  if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* mcx_last_error(mcx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mcx_set_transport(mcx_ctx* c, const mcx_transport* t) {
+  if (!c) return MCX_E_INVALID;
+  if (!t) return fail(c, MCX_E_INVALID, "null transport");
+  if (t->n_grid < 16 || t->n_grid > kMaxGrid) return fail(c, MCX_E_INVALID, "n_grid must be in [16, %d]", kMaxGrid);
+  if (!(t->e_min > 0.0) || !(t->e_max > t->e_min)) return fail(c, MCX_E_INVALID, "need 0 < e_min < e_max");
+  if (!(t->c1 > 0.0 && t->c1 <= 0.2 && t->c2 > 0.0 && t->c2 <= 0.2))
+    return fail(c, MCX_E_INVALID, "C1 and C2 must lie in (0, 0.2]");
+  if (!(t->wcc > 0.0) || !(t->wcr > 0.0)) return fail(c, MCX_E_INVALID, "Wcc and Wcr must be positive");
+  for (int i = 0; i < 3; ++i)
+    if (!(t->eabs[i] >= t->e_min)) return fail(c, MCX_E_INVALID, "Eabs must be >= e_min");
+  c->tr = *t;
+  c->have_transport = true;
+  c->have_material = false;
+  return MCX_OK;
+}
+
+int mcx_load_material(mcx_ctx* c, int mat_id, const mcx_material_desc* m) {
+  if (!c) return MCX_E_INVALID;
+  if (!m) return fail(c, MCX_E_INVALID, "null material");
+  if (mat_id != 0) return fail(c, MCX_E_UNSUPPORTED, "only material 0 is supported");
+  if (!c->have_transport) return fail(c, MCX_E_STATE, "set the transport parameters first");
+  const double pos[] = {m->z_mol, m->a_mol, m->zz1_mol, m->z_screen, m->i_exc, m->pe_eref, m->ray_a};
+  for (double v : pos)
+    if (!(v > 0.0)) return fail(c, MCX_E_INVALID, "material parameters must be positive");
+  if (!(m->pe_coef >= 0.0) || !(m->pp_coef >= 0.0) || !(m->ray_f0 >= 0.0) || !(m->brems_b >= 0.0))
+    return fail(c, MCX_E_INVALID, "material coefficients must be non-negative");
+  std::string err;
+  BuiltTables b;
+  if (!build_tables(*m, c->tr, &b, &err)) return fail(c, MCX_E_INVALID, "%s", err.c_str());
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  int rc;
+  const size_t bytes = b.block.size() * tsize(c);
+  if ((rc = dalloc(c, c->d_tab, bytes, "tables"))) return rc;
+  hipError_t e;
+  if (fp64(c)) {
+    e = hipMemcpy(c->d_tab.p, b.block.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> f(b.block.begin(), b.block.end());
+    e = hipMemcpy(c->d_tab.p, f.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "copy tables");
+  e = configure_kernels(b.n, fp64(c));
+  if (e != hipSuccess) return hip_fail(c, e, "configure kernels");
+  c->tabs = std::move(b);
+  c->mat = *m;
+  c->have_material = true;
+  return MCX_OK;
+}
+
+int mcx_reset_tallies(mcx_ctx* c) {
+  if (!c) return MCX_E_INVALID;
+  if (!c->have_phantom) return fail(c, MCX_E_STATE, "no phantom");
+  (void)hipSetDevice(c->device);
+  const size_t bytes = nvox(c) * sizeof(double);
+  hipError_t e = hipMemsetAsync(c->d_sumq.p, 0, bytes, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_sumq2.p, 0, bytes, c->stream);
+  if (e == hipSuccess && c->d_cnt.p) e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reset tallies");
+  c->n_done = 0;
+  c->iterations = c->chunks = c->tally_pairs = 0;
+  c->ms_transport = c->ms_flush = 0.0;
+  return MCX_OK;
+}
+
+int mcx_load_phantom(mcx_ctx* c, const mcx_phantom_desc* p) {
+  if (!c) return MCX_E_INVALID;
+  if (!p || !p->rho) return fail(c, MCX_E_INVALID, "null phantom");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nx > 1024 || p->ny > 1024 || p->nz > 1024)
+    return fail(c, MCX_E_INVALID, "grid dimensions must be in [1, 1024]");
+  for (int k = 0; k < 3; ++k)
+    if (!(p->voxel_cm[k] > 0.0) || !std::isfinite(p->origin_cm[k]))
+      return fail(c, MCX_E_INVALID, "voxel sizes must be positive and origins finite");
+  (void)hipSetDevice(c->device);
+  const uint64_t nv = uint64_t(p->nx) * p->ny * p->nz;
+  std::vector<double> h(nv);
+  hipError_t e = hipMemcpy(h.data(), p->rho, nv * sizeof(double),
+                           p->rho_on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "read densities");
+  for (uint64_t v = 0; v < nv; ++v)
+    if (!(h[v] > 0.0) || !std::isfinite(h[v])) return fail(c, MCX_E_INVALID, "density must be > 0 (voxel %llu)", (unsigned long long)v);
+  int rc;
+  if ((rc = dalloc(c, c->d_rho, nv * tsize(c), "densities"))) return rc;
+  if (fp64(c)) {
+    e = hipMemcpy(c->d_rho.p, h.data(), nv * sizeof(double), hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> f(h.begin(), h.end());
+    e = hipMemcpy(c->d_rho.p, f.data(), nv * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "copy densities");
+  if ((rc = dalloc(c, c->d_sumq, nv * sizeof(double), "Sum q"))) return rc;
+  if ((rc = dalloc(c, c->d_sumq2, nv * sizeof(double), "Sum q^2"))) return rc;
+  c->nx = p->nx; c->ny = p->ny; c->nz = p->nz;
+  for (int k = 0; k < 3; ++k) {
+    c->vox[k] = p->voxel_cm[k];
+    c->org[k] = p->origin_cm[k];
+  }
+  c->have_phantom = true;
+  return mcx_reset_tallies(c);
+}
+
+static bool inside(const mcx_ctx* c, double x, double y, double z) {
+  const double p[3] = {x, y, z};
+  const int n[3] = {c->nx, c->ny, c->nz};
+  for (int k = 0; k < 3; ++k) {
+    const double f = std::floor((p[k] - c->org[k]) / c->vox[k]);
+    if (!(f >= 0.0) || !(f < double(n[k]))) return false;
+  }
+  return true;
+}
+
+int mcx_set_sources(mcx_ctx* c, const mcx_source* s, int n) {
+  if (!c) return MCX_E_INVALID;
+  if (!s || n < 1) return fail(c, MCX_E_INVALID, "need at least one source");
+  if (!c->have_phantom || !c->have_material) return fail(c, MCX_E_STATE, "load the material and phantom first");
+  std::vector<SourceDev> v(n);
+  uint64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const mcx_source& q = s[i];
+    if (q.particle < 0 || q.particle > 2) return fail(c, MCX_E_INVALID, "source %d: bad particle", i);
+    if (q.kind != MCX_SRC_PENCIL && q.kind != MCX_SRC_RECT) return fail(c, MCX_E_INVALID, "source %d: bad kind", i);
+    if (!(q.energy > c->tr.eabs[q.particle]) || !(q.energy <= c->tr.e_max))
+      return fail(c, MCX_E_RANGE, "source %d: energy must lie in (Eabs, e_max]", i);
+    const double nn = std::sqrt(q.dir[0] * q.dir[0] + q.dir[1] * q.dir[1] + q.dir[2] * q.dir[2]);
+    if (!(std::fabs(nn - 1.0) < 1e-9)) return fail(c, MCX_E_INVALID, "source %d: direction is not a unit vector", i);
+    if (q.kind == MCX_SRC_PENCIL) {
+      if (!inside(c, q.pos[0], q.pos[1], q.pos[2])) return fail(c, MCX_E_INVALID, "source %d: start outside the phantom", i);
+    } else {
+      if (!(q.width[0] >= 0.0) || !(q.width[1] >= 0.0)) return fail(c, MCX_E_INVALID, "source %d: bad width", i);
+      const double hx = 0.5 * q.width[0], hy = 0.5 * q.width[1];
+      for (int sx = -1; sx <= 1; sx += 2)
+        for (int sy = -1; sy <= 1; sy += 2)
+          if (!inside(c, q.pos[0] + sx * hx, q.pos[1] + sy * hy, q.pos[2]))
+            return fail(c, MCX_E_INVALID, "source %d: rectangle leaves the phantom", i);
+    }
+    SourceDev& d = v[i];
+    d.particle = q.particle;
+    d.kind = q.kind;
+    d.energy = q.energy;
+    for (int k = 0; k < 3; ++k) {
+      d.pos[k] = q.pos[k];
+      d.dir[k] = q.dir[k];
+    }
+    d.width[0] = q.width[0];
+    d.width[1] = q.width[1];
+    total += q.n_hist;
+    d.end = total;
+  }
+  if (total > 0xFFFFFFFFull) return fail(c, MCX_E_RANGE, "more than 2^32 histories");
+  (void)hipSetDevice(c->device);
+  int rc;
+  if ((rc = dalloc(c, c->d_src, v.size() * sizeof(SourceDev), "sources"))) return rc;
+  hipError_t e = hipMemcpy(c->d_src.p, v.data(), v.size() * sizeof(SourceDev), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "copy sources");
+  c->src = std::move(v);
+  c->total_hist = total;
+  c->have_sources = true;
+  return MCX_OK;
+}
+
+int mcx_set_launch(mcx_ctx* c, uint32_t bank, uint32_t block, uint32_t steps) {
+  if (!c) return MCX_E_INVALID;
+  if (bank) {
+    if (bank < 1024 || bank > (1u << 26)) return fail(c, MCX_E_INVALID, "bank must lie in [1024, 2^26]");
+    c->cap = bank;
+  }
+  if (block) {
+    if (block % 64 || block > 1024) return fail(c, MCX_E_INVALID, "block must be a multiple of 64, <= 1024");
+    c->block = block;
+  }
+  if (steps) {
+    if (steps > 4096) return fail(c, MCX_E_INVALID, "steps must be <= 4096");
+    c->steps = steps;
+  }
+  return MCX_OK;
+}
+
+int mcx_set_test_mode(mcx_ctx* c, int on) {
+  if (!c) return MCX_E_INVALID;
+  c->test_mode = on ? 1 : 0;
+  return MCX_OK;
+}
+
+int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream) {
+  if (!c) return MCX_E_INVALID;
+  if (!c->have_sources || !c->have_material || !c->have_phantom)
+    return fail(c, MCX_E_STATE, "set transport, material, phantom and sources first");
+  if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
+  if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  c->last_valid = false;
+  if (n == 0) return MCX_OK;
+  int rc = ensure_workspace(c);
+  if (rc) return rc;
+  if (c->table_dirty) {
+    hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, c->hslots * sizeof(double), s);
+    if (e != hipSuccess) return hip_fail(c, e, "clear tally table");
+  }
+  c->table_dirty = true;
+  if (c->test_mode) {
+    if ((rc = dalloc(c, c->d_hhash, n * sizeof(uint64_t), "history hashes"))) return rc;
+    if ((rc = dalloc(c, c->d_hled, 3 * n * sizeof(double), "history ledger"))) return rc;
+    hipError_t e = hipMemsetAsync(c->d_hhash.p, 0, n * sizeof(uint64_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_hled.p, 0, 3 * n * sizeof(double), s);
+    if (e != hipSuccess) return hip_fail(c, e, "clear history results");
+  }
+  rc = fp64(c) ? run_impl<double>(c, uint32_t(seed), first, n, s) : run_impl<float>(c, uint32_t(seed), first, n, s);
+  if (rc) return rc;
+  c->table_dirty = false;
+  c->n_done += n;
+  c->last_n = n;
+  c->last_valid = c->test_mode != 0;
+  return MCX_OK;
+}
+
+int mcx_get_tally(mcx_ctx* c, double* sum_q, double* sum_q2, int dst_on_device, void* stream) {
+  if (!c) return MCX_E_INVALID;
+  if (!c->have_phantom) return fail(c, MCX_E_STATE, "no phantom");
+  (void)hipSetDevice(c->device);
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const size_t bytes = nvox(c) * sizeof(double);
+  const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  hipError_t e = hipSuccess;
+  if (sum_q) e = hipMemcpyAsync(sum_q, c->d_sumq.p, bytes, k, s);
+  if (e == hipSuccess && sum_q2) e = hipMemcpyAsync(sum_q2, c->d_sumq2.p, bytes, k, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "copy tally");
+  return MCX_OK;
+}
+
+int mcx_get_dose(mcx_ctx* c, double* dose, double* sigma, int dst_on_device, void* stream) {
+  if (!c) return MCX_E_INVALID;
+  if (!dose) return fail(c, MCX_E_INVALID, "null dose");
+  if (!c->have_phantom) return fail(c, MCX_E_STATE, "no phantom");
+  if (c->n_done == 0) return fail(c, MCX_E_STATE, "no histories have been run");
+  (void)hipSetDevice(c->device);
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const uint64_t nv = nvox(c);
+  double* dd = dose;
+  double* ds = sigma;
+  DevBuf tmp;
+  if (!dst_on_device) {
+    int rc = dalloc(c, tmp, 2 * nv * sizeof(double), "dose staging");
+    if (rc) return rc;
+    dd = static_cast<double*>(tmp.p);
+    ds = sigma ? dd + nv : nullptr;
+  }
+  const double vol = c->vox[0] * c->vox[1] * c->vox[2];
+  hipError_t e = fp64(c) ? launch_dose(static_cast<double*>(c->d_sumq.p), static_cast<double*>(c->d_sumq2.p),
+                                       static_cast<const double*>(c->d_rho.p), nv, vol, double(c->n_done), dd, ds, s)
+                         : launch_dose(static_cast<double*>(c->d_sumq.p), static_cast<double*>(c->d_sumq2.p),
+                                       static_cast<const float*>(c->d_rho.p), nv, vol, double(c->n_done), dd, ds, s);
+  if (e == hipSuccess && !dst_on_device) {
+    e = hipMemcpyAsync(dose, dd, nv * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && sigma) e = hipMemcpyAsync(sigma, ds, nv * sizeof(double), hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(tmp);
+  if (e != hipSuccess) return hip_fail(c, e, "dose");
+  return MCX_OK;
+}
+
+int mcx_get_stats(mcx_ctx* c, mcx_stats* out) {
+  if (!c || !out) return MCX_E_INVALID;
+  std::memset(out, 0, sizeof(*out));
+  out->histories = c->n_done;
+  out->iterations = c->iterations;
+  out->chunks = c->chunks;
+  out->tally_pairs = c->tally_pairs;
+  out->ms_transport = c->ms_transport;
+  out->ms_flush = c->ms_flush;
+  if (!c->d_cnt.p) return MCX_OK;
+  (void)hipSetDevice(c->device);
+  Counters h;
+  hipError_t e = hipMemcpy(&h, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "read statistics");
+  out->flights = h.stat[S_FLIGHTS];
+  out->compton = h.stat[S_COMPTON];
+  out->photo = h.stat[S_PHOTO];
+  out->rayleigh = h.stat[S_RAYLEIGH];
+  out->pair = h.stat[S_PAIR];
+  out->esteps = h.stat[S_ESTEPS];
+  out->hard_el = h.stat[S_HARD_EL];
+  out->hard_in = h.stat[S_HARD_IN];
+  out->hard_br = h.stat[S_HARD_BR];
+  out->delta = h.stat[S_DELTA];
+  out->annih = h.stat[S_ANNIH];
+  out->crossings = h.stat[S_CROSSINGS];
+  out->secondaries = h.stat[S_SECONDARIES];
+  out->deposits = h.stat[S_DEPOSITS];
+  out->absorbed = h.stat[S_ABSORBED];
+  out->escaped = h.stat[S_ESCAPED];
+  out->pos_esc = h.stat[S_POSESC];
+  out->e_dep = h.e_dep;
+  out->e_esc = h.e_esc;
+  return MCX_OK;
+}
+
+int mcx_get_history_results(mcx_ctx* c, uint64_t* hashes, double* ledger) {
+  if (!c) return MCX_E_INVALID;
+  if (!c->last_valid) return fail(c, MCX_E_STATE, "the last run was not in test mode");
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipSuccess;
+  if (hashes) e = hipMemcpy(hashes, c->d_hhash.p, c->last_n * sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && ledger) e = hipMemcpy(ledger, c->d_hled.p, 3 * c->last_n * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "read history results");
+  return MCX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,21 @@
+// tables.h -- host tabulation of the material models (see tables.cpp).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "mcx.h"
+
+namespace mcx {
+
+struct BuiltTables {
+  int n = 0;
+  double lemin = 0, dl = 0;
+  std::vector<double> block;  // T_NCH * n, channel-major
+  double thr_pp = 0, thr_in[2] = {0, 0}, thr_br = 0;
+  double k_coef = 0, eta_a = 0, eta_b = 0, ray_a = 0;
+};
+
+bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTables* out, std::string* err);
+
+}  // namespace mcx

@@ -1,0 +1,594 @@
+// transport_device.h -- device side of the particle-history loop, templated
+// on the compute type T (double: FP64 path; float: mixed path with FP64
+// positions, boundary distances and tallies).
+//
+// Event-based organisation of the loop of Sec. 4.1 of the paper (JUMP, STEP,
+// KNOCK): particles live in structure-of-arrays queues, one queue per event
+// type, so that each wavefront runs one kind of event:
+//   k_source  new primaries for history ids taken from a global cursor
+//   k_flight  photon JUMP + STEP (free path in mass thickness, voxel DDA);
+//             sorts each photon into the queue of its interaction
+//   k_knock   photon KNOCK, one interaction type per queue
+//   k_estep   electron/positron Class II steps (up to `steps` per visit),
+//             hard events inline
+//   k_advance queue bookkeeping and admission of the next histories
+// Energy deposits are coalesced per particle and voxel in registers and added
+// to an open-addressing (history, voxel) table; k_flush turns each history's
+// per-voxel score q into Sum q and Sum q^2 (Eq. (1)-(3)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "mcx_internal.h"
+
+namespace mcx {
+
+// ---------------------------------------------------------------------------
+// math in the compute type
+// ---------------------------------------------------------------------------
+template <typename T>
+struct M;
+
+template <>
+struct M<double> {
+  static __device__ __forceinline__ double log(double x) { return ::log(x); }
+  static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double pow(double a, double b) { return ::pow(a, b); }
+  static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
+  static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
+  static __device__ __forceinline__ double floor(double x) { return ::floor(x); }
+  static __device__ __forceinline__ void sincos(double x, double* s, double* c) { ::sincos(x, s, c); }
+  static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+};
+
+template <>
+struct M<float> {
+  static __device__ __forceinline__ float log(float x) { return __logf(x); }
+  static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return ::sqrtf(x); }
+  static __device__ __forceinline__ float pow(float a, float b) { return __powf(a, b); }
+  static __device__ __forceinline__ float log1p(float x) { return ::log1pf(x); }
+  static __device__ __forceinline__ float expm1(float x) { return ::expm1f(x); }
+  static __device__ __forceinline__ float floor(float x) { return ::floorf(x); }
+  static __device__ __forceinline__ void sincos(float x, float* s, float* c) { __sincosf(x, s, c); }
+  static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+};
+
+template <typename T>
+constexpr bool is_fp64() { return std::is_same<T, double>::value; }
+
+// ---------------------------------------------------------------------------
+// counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11)
+// key = (seed, history id); counter = (draw / 2, uid_lo, uid_hi, 0);
+// draw d is 64-bit word d % 2 of the call.  One call is cached per particle.
+// ---------------------------------------------------------------------------
+struct Rng {
+  uint32_t k0, k1, u0, u1;
+  uint32_t ctr;     // next draw index
+  uint32_t cpair;   // Philox call held in w[] (~0u: none)
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                         uint32_t k1, uint32_t* o) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  o[0] = c0; o[1] = c1; o[2] = c2; o[3] = c3;
+}
+
+__device__ __forceinline__ uint64_t rng_word(Rng& r) {
+  const uint32_t pair = r.ctr >> 1;
+  if (pair != r.cpair) {
+    uint32_t o[4];
+    philox10(pair, r.u0, r.u1, 0u, r.k0, r.k1, o);
+    r.w0 = o[0]; r.w1 = o[1]; r.w2 = o[2]; r.w3 = o[3];
+    r.cpair = pair;
+  }
+  const uint64_t w = (r.ctr & 1u) ? ((uint64_t(r.w3) << 32) | r.w2) : ((uint64_t(r.w1) << 32) | r.w0);
+  r.ctr++;
+  return w;
+}
+
+template <typename T>
+__device__ __forceinline__ T uni(Rng& r);
+template <>
+__device__ __forceinline__ double uni<double>(Rng& r) {
+  return (double(rng_word(r) >> 11) + 0.5) * 0x1.0p-53;
+}
+// FP32: top 23 bits of the same word, ((w >> 41) + 1/2) 2^-23, exact in FP32
+template <>
+__device__ __forceinline__ float uni<float>(Rng& r) {
+  return (float(uint32_t(rng_word(r) >> 41)) + 0.5f) * 0x1.0p-23f;
+}
+
+// SplitMix64 finaliser (Steele et al., OOPSLA'14)
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// uid of the k-th secondary of a particle
+__device__ __forceinline__ uint64_t child_uid(uint64_t parent, uint32_t k) {
+  return mix64((parent ^ (uint64_t(k + 1u) * 0x9E3779B97F4A7C15ull)) + 0x9E3779B97F4A7C15ull);
+}
+
+// ---------------------------------------------------------------------------
+// particle state in registers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Part {
+  double x[3];
+  T d[3];
+  T e;
+  int ix[3];
+  uint32_t type, nchild;
+  uint32_t hist;
+  uint64_t uid;
+  uint64_t hash;
+  Rng rng;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_part(const KArgs<T>& a, const Bank<T>& b, uint32_t i, Part<T>& p) {
+  p.x[0] = b.x[i]; p.x[1] = b.y[i]; p.x[2] = b.z[i];
+  p.d[0] = b.u[i]; p.d[1] = b.v[i]; p.d[2] = b.w[i];
+  p.e = b.e[i];
+  p.uid = b.uid[i];
+  p.hist = b.hist[i];
+  const uint32_t vx = b.vox[i];
+  p.ix[0] = int(vx & 1023u); p.ix[1] = int((vx >> 10) & 1023u); p.ix[2] = int(vx >> 20);
+  const uint32_t fl = b.flags[i];
+  p.type = fl & 3u;
+  p.nchild = fl >> 2;
+  p.hash = a.test_mode ? b.hash[i] : 0ull;
+  p.rng.k0 = a.seed; p.rng.k1 = p.hist;
+  p.rng.u0 = uint32_t(p.uid); p.rng.u1 = uint32_t(p.uid >> 32);
+  p.rng.ctr = b.ctr[i];
+  p.rng.cpair = ~0u;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_part(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p) {
+  b.x[i] = p.x[0]; b.y[i] = p.x[1]; b.z[i] = p.x[2];
+  b.u[i] = p.d[0]; b.v[i] = p.d[1]; b.w[i] = p.d[2];
+  b.e[i] = p.e;
+  b.uid[i] = p.uid;
+  b.hist[i] = p.hist;
+  b.ctr[i] = p.rng.ctr;
+  b.vox[i] = uint32_t(p.ix[0]) | (uint32_t(p.ix[1]) << 10) | (uint32_t(p.ix[2]) << 20);
+  b.flags[i] = p.type | (p.nchild << 2);
+  if (a.test_mode) b.hash[i] = p.hash;
+}
+
+// a secondary waiting to be appended: shares position/voxel/history with its parent
+template <typename T>
+struct Child {
+  T d[3];
+  T e;
+  uint32_t type;
+  uint64_t uid;
+  bool on;
+};
+
+template <typename T>
+__device__ __forceinline__ void store_child(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
+                                            const Child<T>& c) {
+  b.x[i] = p.x[0]; b.y[i] = p.x[1]; b.z[i] = p.x[2];
+  b.u[i] = c.d[0]; b.v[i] = c.d[1]; b.w[i] = c.d[2];
+  b.e[i] = c.e;
+  b.uid[i] = c.uid;
+  b.hist[i] = p.hist;
+  b.ctr[i] = 0u;
+  b.vox[i] = uint32_t(p.ix[0]) | (uint32_t(p.ix[1]) << 10) | (uint32_t(p.ix[2]) << 20);
+  b.flags[i] = c.type;
+  if (a.test_mode) b.hash[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// wavefront-aggregated append: one atomic per wave and destination queue
+// (all active lanes of the wave must call it)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0ull) return ~0u;
+  const uint32_t lane = __lane_id();
+  const uint32_t leader = uint32_t(__ffsll((unsigned long long)mask) - 1);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, uint32_t(__popcll(mask)));
+  base = __shfl(base, int(leader));
+  const uint32_t below = uint32_t(__popcll(mask & ((1ull << lane) - 1ull)));
+  return pred ? base + below : ~0u;
+}
+
+// ---------------------------------------------------------------------------
+// statistics: frequent events counted in registers per lane and reduced per
+// wave at the end of a kernel; rare ones through LDS; one global atomic per
+// counter per block
+// ---------------------------------------------------------------------------
+struct BlockStats {
+  unsigned long long c[S_NSTAT];
+  double e_dep, e_esc;
+};
+
+struct LaneStats {
+  uint32_t esteps, deposits, crossings, hard_el, delta, flights;
+  double e_dep;
+};
+
+__device__ __forceinline__ void stats_init(BlockStats* s, LaneStats& l) {
+  for (int i = threadIdx.x; i < S_NSTAT; i += blockDim.x) s->c[i] = 0ull;
+  if (threadIdx.x == 0) { s->e_dep = 0.0; s->e_esc = 0.0; }
+  l.esteps = l.deposits = l.crossings = l.hard_el = l.delta = l.flights = 0u;
+  l.e_dep = 0.0;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// every thread of the block must call this (after its last event)
+__device__ __forceinline__ void stats_flush(BlockStats* s, const LaneStats& l, Counters* cnt) {
+  const uint32_t es = wave_sum(l.esteps), de = wave_sum(l.deposits), cr = wave_sum(l.crossings);
+  const uint32_t he = wave_sum(l.hard_el), dl = wave_sum(l.delta), fl = wave_sum(l.flights);
+  const double ed = wave_sum(l.e_dep);
+  if (__lane_id() == 0) {
+    if (es) atomicAdd(&s->c[S_ESTEPS], (unsigned long long)es);
+    if (de) atomicAdd(&s->c[S_DEPOSITS], (unsigned long long)de);
+    if (cr) atomicAdd(&s->c[S_CROSSINGS], (unsigned long long)cr);
+    if (he) atomicAdd(&s->c[S_HARD_EL], (unsigned long long)he);
+    if (dl) atomicAdd(&s->c[S_DELTA], (unsigned long long)dl);
+    if (fl) atomicAdd(&s->c[S_FLIGHTS], (unsigned long long)fl);
+    if (ed != 0.0) atomicAdd(&s->e_dep, ed);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S_NSTAT; i += blockDim.x)
+    if (s->c[i]) atomicAdd((unsigned long long*)&cnt->stat[i], s->c[i]);
+  if (threadIdx.x == 0) {
+    if (s->e_dep != 0.0) unsafeAtomicAdd(&cnt->e_dep, s->e_dep);
+    if (s->e_esc != 0.0) unsafeAtomicAdd(&cnt->e_esc, s->e_esc);
+  }
+}
+
+__device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long long v = 1ull) {
+  atomicAdd(&s->c[k], v);
+}
+
+// ---------------------------------------------------------------------------
+// tally: (history, voxel) -> score, open addressing with linear probing
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void tally_insert(const KArgs<T>& a, uint64_t key, double q) {
+  uint64_t slot = mix64(key) & a.hmask;
+  for (int probe = 0; probe < 4096; ++probe) {
+    uint64_t k = __hip_atomic_load(&a.hkeys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k == kEmptyKey) {
+      k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
+                    (unsigned long long)key);
+      if (k == kEmptyKey) k = key;
+    }
+    if (k == key) {
+      unsafeAtomicAdd(&a.hvals[slot], q);
+      return;
+    }
+    slot = (slot + 1) & a.hmask;
+  }
+  atomicOr(&a.cnt->overflow, uint32_t(OVF_TALLY));
+}
+
+// deposits of one particle are summed in registers while they stay in one voxel
+struct DepAcc {
+  uint64_t key;
+  double q;
+};
+
+template <typename T>
+__device__ __forceinline__ void dep_flush(const KArgs<T>& a, DepAcc& acc) {
+  if (acc.key != kEmptyKey && acc.q != 0.0) tally_insert(a, acc.key, acc.q);
+  acc.key = kEmptyKey;
+  acc.q = 0.0;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t vlin(const KArgs<T>& a, const int ix[3]) {
+  return (uint32_t(ix[2]) * uint32_t(a.ny) + uint32_t(ix[1])) * uint32_t(a.nx) + uint32_t(ix[0]);
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStats& ls, const Part<T>& p, T e) {
+  if (e == T(0)) return;
+  const uint64_t key = (uint64_t(p.hist) << 32) | vlin(a, p.ix);
+  if (key != acc.key) {
+    dep_flush(a, acc);
+    acc.key = key;
+  }
+  acc.q += double(e);
+  ls.deposits++;
+  ls.e_dep += double(e);
+}
+
+// ---------------------------------------------------------------------------
+// event hash (order independent per history)
+// ---------------------------------------------------------------------------
+enum Ev : uint32_t {
+  EV_COMPTON = 1, EV_PHOTO = 2, EV_RAYLEIGH = 3, EV_PAIR = 4, EV_PH_ESCAPE = 5,
+  EV_CROSS = 6, EV_STEP = 7, EV_HARD_EL = 8, EV_HARD_IN = 9, EV_HARD_BR = 10,
+  EV_ABSORB = 11, EV_E_ESCAPE = 12
+};
+
+template <typename T>
+__device__ __forceinline__ void event(const KArgs<T>& a, Part<T>& p, uint32_t code, uint32_t v) {
+  if (!a.test_mode) return;
+  const uint64_t word = uint64_t(code) | (uint64_t(v) << 8) | (uint64_t(p.nchild & 0xFFFFFFu) << 40);
+  p.hash = mix64(p.hash + word);
+}
+
+template <typename T>
+__device__ __forceinline__ void finish(const KArgs<T>& a, const Part<T>& p) {
+  if (!a.test_mode) return;
+  atomicAdd((unsigned long long*)&a.hist_hash[p.hist - a.cnt->run_first],
+            (unsigned long long)mix64(p.hash ^ p.uid));
+}
+
+template <typename T>
+__device__ __forceinline__ void ledger_escape(const KArgs<T>& a, BlockStats* st, const Part<T>& p) {
+  stat_add(st, S_ESCAPED);
+  atomicAdd(&st->e_esc, double(p.e));
+  if (p.type == POSITRON) stat_add(st, S_POSESC);
+  if (!a.test_mode) return;
+  const uint64_t h = p.hist - a.cnt->run_first;
+  unsafeAtomicAdd(&a.hist_led[3 * h + 1], double(p.e));
+  if (p.type == POSITRON) unsafeAtomicAdd(&a.hist_led[3 * h + 2], 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// geometry: constant LOCATE / STEP on the voxel grid
+// ---------------------------------------------------------------------------
+// distance to the exit face of the current voxel; ties go to x, then y, z
+template <typename T>
+__device__ __forceinline__ double face_dist(const KArgs<T>& a, const Part<T>& p, int* axis) {
+  const double o[3] = {a.ox, a.oy, a.oz};
+  const double dd[3] = {a.dx, a.dy, a.dz};
+  double best = __builtin_huge_val();
+  int ax = -1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dk = double(p.d[k]);
+    double s;
+    if (dk > 0.0) s = (o[k] + double(p.ix[k] + 1) * dd[k] - p.x[k]) / dk;
+    else if (dk < 0.0) s = (o[k] + double(p.ix[k]) * dd[k] - p.x[k]) / dk;
+    else continue;
+    if (s < 0.0) s = 0.0;
+    if (s < best) { best = s; ax = k; }
+  }
+  *axis = ax;
+  return best;
+}
+
+template <typename T>
+__device__ __forceinline__ void move(Part<T>& p, double s) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) p.x[k] = p.x[k] + s * double(p.d[k]);
+}
+
+// move to the face on `ax`, snap onto it and step the voxel index;
+// true if the particle left the grid
+template <typename T>
+__device__ __forceinline__ bool cross(const KArgs<T>& a, Part<T>& p, double s, int ax, LaneStats& ls) {
+  const double o[3] = {a.ox, a.oy, a.oz};
+  const double dd[3] = {a.dx, a.dy, a.dz};
+  const int n[3] = {a.nx, a.ny, a.nz};
+  const bool up = p.d[ax] > T(0);
+  const double fv = up ? o[ax] + double(p.ix[ax] + 1) * dd[ax] : o[ax] + double(p.ix[ax]) * dd[ax];
+  move(p, s);
+  p.x[ax] = fv;
+  p.ix[ax] += up ? 1 : -1;
+  ls.crossings++;
+  return p.ix[ax] < 0 || p.ix[ax] >= n[ax];
+}
+
+// polar deflection by cos_t and azimuth phi, then renormalise
+template <typename T>
+__device__ __forceinline__ void rotate(T d[3], T cost, T phi) {
+  const T s2t = T(1) - cost * cost;
+  const T sint = s2t > T(0) ? M<T>::sqrt(s2t) : T(0);
+  T sp, cp;
+  M<T>::sincos(phi, &sp, &cp);
+  const T u = d[0], v = d[1], w = d[2];
+  const T s2 = T(1) - w * w;
+  T nu, nv, nw;
+  if (s2 > T(1e-10)) {
+    const T s = M<T>::sqrt(s2);
+    nu = u * cost + sint * (u * w * cp - v * sp) / s;
+    nv = v * cost + sint * (v * w * cp + u * sp) / s;
+    nw = w * cost - s * sint * cp;
+  } else {
+    nu = sint * cp;
+    nv = sint * sp;
+    nw = w > T(0) ? cost : -cost;
+  }
+  const T nn = M<T>::sqrt(nu * nu + nv * nv + nw * nw);
+  d[0] = nu / nn;
+  d[1] = nv / nn;
+  d[2] = nw / nn;
+}
+
+// ---------------------------------------------------------------------------
+// table interpolation (tables in LDS, channel-major)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Grid {
+  int i;
+  T f;
+};
+
+template <typename T>
+__device__ __forceinline__ Grid<T> grid_at(const Tab<T>& tb, T le) {
+  const T x = (le - tb.lemin) * tb.inv_dl;
+  const T fl = M<T>::floor(x);
+  int i;
+  if (!(fl >= T(0))) i = 0;  // also catches NaN
+  else if (fl > T(tb.n - 2)) i = tb.n - 2;
+  else i = int(fl);
+  return Grid<T>{i, x - T(i)};
+}
+
+// piecewise power law between positive nodes; linear in E from the
+// threshold on a segment whose lower node is zero
+template <typename T>
+__device__ __forceinline__ T interp(const T* s, int n, int ch, const Grid<T>& g, T e, T thr) {
+  if (thr > T(0) && !(e > thr)) return T(0);
+  const T l0 = s[ch * n + g.i], l1 = s[ch * n + g.i + 1];
+  if (!(l1 > -M<T>::inf())) return T(0);
+  if (!(l0 > -M<T>::inf())) {
+    const T ei = s[T_ENODE * n + g.i], ej = s[T_ENODE * n + g.i + 1];
+    const T lo = thr > ei ? thr : ei;
+    return M<T>::exp(l1) * (e - lo) / (ej - lo);
+  }
+  return M<T>::exp(l0 + g.f * (l1 - l0));
+}
+
+// range R(E): R_i + Int_{E_i}^{E} dE/S on the power-law segment
+template <typename T>
+__device__ __forceinline__ T range_at(const T* s, int n, int base, const Grid<T>& g, T e) {
+  const T ei = s[T_ENODE * n + g.i];
+  const T si = s[(base + O_S) * n + g.i];
+  const T q = s[(base + O_Q) * n + g.i];
+  const T ri = s[(base + O_R) * n + g.i];
+  T seg;
+  if (is_fp64<T>()) {
+    seg = (q > T(-1e-10) && q < T(1e-10)) ? (ei / si) * M<T>::log(e / ei)
+                                          : (ei / si) * (M<T>::pow(e / ei, q) - T(1)) / q;
+  } else {
+    seg = (ei / si) * ((q > T(-1e-10) && q < T(1e-10)) ? M<T>::log(e / ei) : M<T>::expm1(q * M<T>::log(e / ei)) / q);
+  }
+  return ri + seg;
+}
+
+// inverse range: the energy whose range is r (E_min if r <= 0)
+template <typename T>
+__device__ __forceinline__ T range_inv(const T* s, int n, int base, T r) {
+  if (!(r > T(0))) return s[T_ENODE * n];
+  const T* rr = s + (base + O_R) * n;
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rr[mid] <= r) lo = mid;
+    else hi = mid;
+  }
+  const T ei = s[T_ENODE * n + lo];
+  const T si = s[(base + O_S) * n + lo];
+  const T q = s[(base + O_Q) * n + lo];
+  const T d = r - rr[lo];
+  if (q > T(-1e-10) && q < T(1e-10)) return ei * M<T>::exp(d * si / ei);
+  if (is_fp64<T>()) return ei * M<T>::pow(T(1) + d * q * si / ei, T(1) / q);
+  return ei * M<T>::exp(M<T>::log1p(d * q * si / ei) / q);
+}
+
+template <typename T>
+__device__ __forceinline__ T hard_sum(const Tab<T>& tb, const T* s, int base, int lep, const Grid<T>& g, T e) {
+  const int n = tb.n;
+  return interp(s, n, base + O_LEL, g, e, T(0)) + interp(s, n, base + O_LIN, g, e, tb.thr_in[lep]) +
+         interp(s, n, base + O_LBR, g, e, tb.thr_br);
+}
+
+// maximum of the hard cross section over [elo, e]: every channel is convex
+// in ln E on each segment, so the maximum sits at elo, e or a node between
+template <typename T>
+__device__ __forceinline__ T majorant(const Tab<T>& tb, const T* s, int base, int lep, T elo, const Grid<T>& ge,
+                                      T e) {
+  const int n = tb.n;
+  T m = hard_sum(tb, s, base, lep, ge, e);
+  const Grid<T> gl = grid_at(tb, M<T>::log(elo));
+  const T a = hard_sum(tb, s, base, lep, gl, elo);
+  if (a > m) m = a;
+  for (int j = gl.i; j <= ge.i + 1 && j < n; ++j) {
+    const T ej = s[T_ENODE * n + j];
+    if (ej > elo && ej < e) {
+      const T v = s[(base + O_HSUM) * n + j];
+      if (v > m) m = v;
+    }
+  }
+  return m;
+}
+
+// A of the soft angular law p(mu) ~ (mu + A)^-2 on [0,1] whose mean
+// A (1 + A) ln(1 + 1/A) - A equals mbar (clamped to 0.49): safeguarded
+// Newton iteration on ln A
+template <typename T>
+__device__ __forceinline__ T soft_a(T mbar) {
+  if (!(mbar > T(0))) return T(0);
+  if (mbar > T(0.49)) mbar = T(0.49);
+  // all iteration in FP64 for the FP64 path, FP32 otherwise
+  T lo = T(-690.0), hi = M<T>::log(T(1e6));
+  if (!is_fp64<T>()) lo = T(-87.0);
+  // initial guess from the small-A expansion A (ln(1/A) - 1) = mbar, or the
+  // large-A expansion 1/2 - 1/(6A)
+  T s;
+  if (mbar < T(0.2)) {
+    const T a0 = mbar / (-M<T>::log(mbar));
+    const T a1 = mbar / (-M<T>::log(a0) - T(1));
+    s = M<T>::log(a1 > T(0) ? a1 : a0);
+  } else {
+    s = M<T>::log(T(1) / (T(6) * (T(0.5) - mbar)));
+  }
+  const T tol = is_fp64<T>() ? T(1e-14) : T(2e-6);
+  for (int it = 0; it < 60; ++it) {
+    if (!(s > lo) || !(s < hi)) s = T(0.5) * (lo + hi);
+    const T A = M<T>::exp(s);
+    const T L = M<T>::log1p(T(1) / A);
+    const T g = A * ((T(1) + A) * L - T(1)) - mbar;
+    if (g < T(0)) lo = s;
+    else hi = s;
+    const T dg = A * ((T(1) + T(2) * A) * L - T(2));  // d g / d ln A
+    T sn = (dg > T(0)) ? s - g / dg : T(0.5) * (lo + hi);
+    if (!(sn > lo) || !(sn < hi)) sn = T(0.5) * (lo + hi);
+    const T step = sn - s;
+    s = sn;
+    if (step < tol && step > -tol) break;
+    if (hi - lo < tol) break;
+  }
+  return M<T>::exp(s);
+}
+
+// cos theta from p(cos) ~ (1 - beta cos)^-2 on [-1, 1] by inversion
+template <typename T>
+__device__ __forceinline__ T leading_angle(T beta, T xi) {
+  return (T(2) * xi - T(1) + beta) / (T(2) * beta * xi + T(1) - beta);
+}
+
+template <typename T>
+__device__ __forceinline__ T beta_of(T t) {
+  return M<T>::sqrt(t * (t + T(2) * T(kMc2))) / (t + T(kMc2));
+}
+
+// ---------------------------------------------------------------------------
+// LDS staging of table channels [c0, c1)
+// ---------------------------------------------------------------------------
+// channels [0, c1) of the table block into LDS
+template <typename T>
+__device__ __forceinline__ void stage(const Tab<T>& tb, T* lds, int c1) {
+  const int total = c1 * tb.n;
+  for (int k = threadIdx.x; k < total; k += blockDim.x) lds[k] = tb.t[k];
+}
+
+}  // namespace mcx

@@ -1,0 +1,645 @@
+// transport_kernels.h -- the kernels of one iteration of the event loop and
+// of the tally, templated on the compute type.  Included by exactly one
+// translation unit per precision (kernels_fp64.hip, kernels_mixed.hip), which
+// are compiled with different floating-point contraction settings.
+#pragma once
+
+#include "launch.h"
+#include "transport_device.h"
+
+namespace mcx {
+
+// queue roles of an iteration with parity `par`
+__device__ __forceinline__ int q_gin(int par) { return Q_G0 + par; }
+__device__ __forceinline__ int q_gout(int par) { return Q_G0 + 1 - par; }
+__device__ __forceinline__ int q_ein(int par) { return Q_E0 + par; }
+__device__ __forceinline__ int q_eout(int par) { return Q_E0 + 1 - par; }
+
+template <typename T>
+__device__ __forceinline__ uint32_t append(const KArgs<T>& a, int q, bool pred) {
+  const uint32_t slot = wave_append(&a.cnt->n[q], pred);
+  if (pred && slot >= a.cap) {
+    atomicOr(&a.cnt->overflow, uint32_t(OVF_QUEUE));
+    return ~0u;
+  }
+  return slot;
+}
+
+// ---------------------------------------------------------------------------
+// source: primaries for history ids [cursor, cursor + adm)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_source(KArgs<T> a, int par) {
+  const uint32_t adm = a.cnt->adm;
+  const uint64_t first = a.cnt->cursor;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < adm; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    const bool act = i < adm;
+    Part<T> p;
+    bool ok = false;
+    if (act) {
+      const uint64_t h = first + i;
+      int lo = 0, hi = a.nsrc - 1;  // first source whose end exceeds h
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a.src[mid].end > h) hi = mid;
+        else lo = mid + 1;
+      }
+      const SourceDev& s = a.src[lo];
+      p.type = uint32_t(s.particle);
+      p.e = T(s.energy);
+      p.hist = uint32_t(h);
+      p.uid = 1ull;
+      p.nchild = 0u;
+      p.hash = 0ull;
+      p.rng.k0 = a.seed; p.rng.k1 = p.hist; p.rng.u0 = 1u; p.rng.u1 = 0u;
+      p.rng.ctr = 0u; p.rng.cpair = ~0u;
+      p.x[0] = s.pos[0]; p.x[1] = s.pos[1]; p.x[2] = s.pos[2];
+      p.d[0] = T(s.dir[0]); p.d[1] = T(s.dir[1]); p.d[2] = T(s.dir[2]);
+      if (s.kind == 1) {
+        // rectangle: both offsets use FP64 words so that the start point is
+        // the same in both precisions
+        Rng& r = p.rng;
+        const double ux = (double(rng_word(r) >> 11) + 0.5) * 0x1.0p-53;
+        const double uy = (double(rng_word(r) >> 11) + 0.5) * 0x1.0p-53;
+        p.x[0] = s.pos[0] + (ux - 0.5) * s.width[0];
+        p.x[1] = s.pos[1] + (uy - 0.5) * s.width[1];
+      }
+      const double o[3] = {a.ox, a.oy, a.oz};
+      const double dd[3] = {a.dx, a.dy, a.dz};
+      const int n[3] = {a.nx, a.ny, a.nz};
+      ok = true;
+      for (int k = 0; k < 3; ++k) {
+        const double f = floor((p.x[k] - o[k]) / dd[k]);
+        if (!(f >= 0.0) || !(f < double(n[k]))) ok = false;
+        else p.ix[k] = int(f);
+      }
+      if (!ok) atomicOr(&a.cnt->overflow, uint32_t(OVF_SOURCE));
+    }
+    const bool is_g = ok && p.type == PHOTON;
+    const bool is_e = ok && p.type != PHOTON;
+    const uint32_t sg = append(a, q_gin(par), is_g);
+    const uint32_t se = append(a, q_ein(par), is_e);
+    if (is_g && sg != ~0u) store_part(a, a.q[q_gin(par)], sg, p);
+    if (is_e && se != ~0u) store_part(a, a.q[q_ein(par)], se, p);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// photon JUMP + STEP: free path in mass thickness, DDA through the voxels;
+// escaped photons end here, the others are sorted by interaction type
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_flight(KArgs<T> a, int par) {
+  const uint32_t n = min(a.cnt->n[q_gin(par)], a.cap);
+  if (blockIdx.x * blockDim.x >= n) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tab = reinterpret_cast<T*>(smem);
+  __shared__ BlockStats bs;
+  LaneStats ls;
+  stats_init(&bs, ls);
+  stage(a.tb, tab, T_PHOTON_END);
+  __syncthreads();
+  const int nt = a.tb.n;
+  const Bank<T>& in = a.q[q_gin(par)];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    int ch = -1;
+    Part<T> p;
+    if (i < n) {
+      load_part(a, in, i, p);
+      const T e = p.e;
+      const Grid<T> g = grid_at(a.tb, M<T>::log(e));
+      T mu[4];
+      mu[0] = interp(tab, nt, T_LMU_C, g, e, T(0));
+      mu[1] = interp(tab, nt, T_LMU_PE, g, e, T(0));
+      mu[2] = interp(tab, nt, T_LMU_R, g, e, T(0));
+      mu[3] = interp(tab, nt, T_LMU_PP, g, e, a.tb.thr_pp);
+      const T mt = mu[0] + mu[1] + mu[2] + mu[3];
+      ls.flights++;
+      double tau = double(-M<T>::log(uni<T>(p.rng)) / mt);
+      bool escaped = false;
+      for (;;) {
+        int ax;
+        const double s = face_dist(a, p, &ax);
+        const uint32_t v = vlin(a, p.ix);
+        if (ax < 0) {
+          atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+          escaped = true;
+          break;
+        }
+        const double rho = double(a.rho[v]);
+        if (rho * s >= tau) {
+          move(p, tau / rho);
+          break;
+        }
+        tau -= rho * s;
+        if (cross(a, p, s, ax, ls)) {
+          ledger_escape(a, &bs, p);
+          event(a, p, EV_PH_ESCAPE, v);
+          finish(a, p);
+          escaped = true;
+          break;
+        }
+      }
+      if (!escaped) {
+        const T u = uni<T>(p.rng) * mt;
+        T cum = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cum += mu[k];
+          if (ch < 0 && u < cum) ch = k;
+        }
+        if (ch < 0)
+          for (int k = 3; k >= 0; --k)
+            if (ch < 0 && mu[k] > T(0)) ch = k;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t slot = append(a, Q_KC + c, ch == c);
+      if (ch == c && slot != ~0u) store_part(a, a.q[Q_KC + c], slot, p);
+    }
+  }
+  stats_flush(&bs, ls, a.cnt);
+}
+
+// ---------------------------------------------------------------------------
+// photon KNOCK: the four interaction queues are processed as one index space,
+// so that (except at the three boundaries) each wavefront runs one type
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T sample_kn(Rng& r, T e, T* cost) {
+  const T k = e / T(kMc2);
+  const T kmin = T(1) / (T(1) + T(2) * k);
+  const T a1 = M<T>::log(T(1) + T(2) * k);
+  const T a2 = T(0.5) * (T(1) - kmin * kmin);
+  T kap = T(1), ct = T(1);
+  for (int tries = 0; tries < kMaxTries; ++tries) {
+    const T ub = uni<T>(r), ux = uni<T>(r), ua = uni<T>(r);
+    if (ub * (a1 + a2) < a1) kap = M<T>::exp(-ux * a1);
+    else kap = M<T>::sqrt(kmin * kmin + ux * (T(1) - kmin * kmin));
+    ct = T(1) - (T(1) - kap) / (k * kap);
+    ct = ct < T(-1) ? T(-1) : (ct > T(1) ? T(1) : ct);
+    const T g = T(1) - kap * (T(1) - ct * ct) / (T(1) + kap * kap);
+    if (ua <= g) break;
+  }
+  *cost = ct;
+  return kap;
+}
+
+template <typename T>
+__device__ __forceinline__ T sample_rayleigh(Rng& r, T e, T ray_a) {
+  const T U = (e / T(kHc)) * (e / T(kHc));
+  const T c3 = -M<T>::expm1(T(-3) * M<T>::log1p(ray_a * U));
+  T ct = T(1);
+  for (int tries = 0; tries < kMaxTries; ++tries) {
+    const T xi = uni<T>(r), ua = uni<T>(r);
+    const T u = M<T>::expm1(-M<T>::log1p(-xi * c3) / T(3)) / ray_a;
+    ct = T(1) - T(2) * u / U;
+    if (ct < T(-1)) ct = T(-1);
+    if (ua <= T(0.5) * (T(1) + ct * ct)) break;
+  }
+  return ct;
+}
+
+// a new secondary of p: takes the next ordinal; kept if above its absorption
+// energy (positrons always, so that they annihilate), else deposited here
+template <typename T>
+__device__ __forceinline__ void make_child(const KArgs<T>& a, Part<T>& p, Child<T>& c, uint32_t type, T e,
+                                           const T d[3], DepAcc& acc, LaneStats& ls, BlockStats* bs) {
+  const uint32_t k = p.nchild++;
+  stat_add(bs, S_SECONDARIES);
+  c.on = false;
+  if (type != POSITRON && !(e > a.eabs[type])) {
+    deposit(a, acc, ls, p, e);
+    return;
+  }
+  c.on = true;
+  c.type = type;
+  c.e = e;
+  c.d[0] = d[0]; c.d[1] = d[1]; c.d[2] = d[2];
+  c.uid = child_uid(p.uid, k);
+}
+
+template <typename T>
+__global__ void k_knock(KArgs<T> a, int par) {
+  Counters* C = a.cnt;
+  const uint32_t n0 = min(C->n[Q_KC], a.cap), n1 = min(C->n[Q_KP], a.cap);
+  const uint32_t n2 = min(C->n[Q_KR], a.cap), n3 = min(C->n[Q_KX], a.cap);
+  const uint32_t e1 = n0 + n1, e2 = e1 + n2, ntot = e2 + n3;
+  if (blockIdx.x * blockDim.x >= ntot) return;
+  __shared__ BlockStats bs;
+  LaneStats ls;
+  stats_init(&bs, ls);
+  __syncthreads();
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < ntot; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    Part<T> p;
+    Child<T> c1, c2;
+    c1.on = false;
+    c2.on = false;
+    bool keep = false;
+    DepAcc acc{kEmptyKey, 0.0};
+    if (i < ntot) {
+      const int q = i < n0 ? 0 : (i < e1 ? 1 : (i < e2 ? 2 : 3));
+      const uint32_t j = i - (q == 0 ? 0u : (q == 1 ? n0 : (q == 2 ? e1 : e2)));
+      load_part(a, a.q[Q_KC + q], j, p);
+      const uint32_t v = vlin(a, p.ix);
+      if (q == 0) {
+        stat_add(&bs, S_COMPTON);
+        T cost;
+        const T kap = sample_kn(p.rng, p.e, &cost);
+        const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+        const T d0[3] = {p.d[0], p.d[1], p.d[2]};
+        rotate(p.d, cost, phi);
+        const T ep = kap * p.e;
+        const T te = p.e - ep;
+        T pe[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pe[k] = p.e * d0[k] - ep * p.d[k];
+        const T nn = M<T>::sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
+        if (nn > T(0)) { pe[0] /= nn; pe[1] /= nn; pe[2] /= nn; }
+        else { pe[0] = d0[0]; pe[1] = d0[1]; pe[2] = d0[2]; }
+        make_child(a, p, c1, ELECTRON, te, pe, acc, ls, &bs);
+        if (ep > a.eabs[PHOTON]) {
+          p.e = ep;
+          keep = true;
+        } else {
+          deposit(a, acc, ls, p, ep);
+          stat_add(&bs, S_ABSORBED);
+        }
+        event(a, p, EV_COMPTON, v);
+      } else if (q == 1) {
+        stat_add(&bs, S_PHOTO);
+        make_child(a, p, c1, ELECTRON, p.e, p.d, acc, ls, &bs);
+        stat_add(&bs, S_ABSORBED);
+        event(a, p, EV_PHOTO, v);
+      } else if (q == 2) {
+        stat_add(&bs, S_RAYLEIGH);
+        const T ct = sample_rayleigh(p.rng, p.e, a.tb.ray_a);
+        const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+        rotate(p.d, ct, phi);
+        keep = true;
+        event(a, p, EV_RAYLEIGH, v);
+      } else {
+        stat_add(&bs, S_PAIR);
+        const T avail = p.e - T(2.0 * kMc2);
+        const T eps = uni<T>(p.rng);
+        const T tm = eps * avail, tp = (T(1) - eps) * avail;
+        T dm[3] = {p.d[0], p.d[1], p.d[2]};
+        T dp[3] = {p.d[0], p.d[1], p.d[2]};
+        const T cm = leading_angle(beta_of(tm), uni<T>(p.rng));
+        const T fm = T(2.0 * kPi) * uni<T>(p.rng);
+        const T cp = leading_angle(beta_of(tp), uni<T>(p.rng));
+        const T fp = T(2.0 * kPi) * uni<T>(p.rng);
+        rotate(dm, cm, fm);
+        rotate(dp, cp, fp);
+        make_child(a, p, c1, ELECTRON, tm, dm, acc, ls, &bs);
+        make_child(a, p, c2, POSITRON, tp, dp, acc, ls, &bs);
+        stat_add(&bs, S_ABSORBED);
+        event(a, p, EV_PAIR, v);
+      }
+      if (!keep) finish(a, p);
+      dep_flush(a, acc);
+    }
+    const uint32_t sg = append(a, q_gout(par), keep);
+    if (keep && sg != ~0u) store_part(a, a.q[q_gout(par)], sg, p);
+    const uint32_t s1 = append(a, q_eout(par), c1.on);
+    if (c1.on && s1 != ~0u) store_child(a, a.q[q_eout(par)], s1, p, c1);
+    const uint32_t s2 = append(a, q_eout(par), c2.on);
+    if (c2.on && s2 != ~0u) store_child(a, a.q[q_eout(par)], s2, p, c2);
+  }
+  stats_flush(&bs, ls, a.cnt);
+}
+
+// ---------------------------------------------------------------------------
+// electron / positron Class II transport
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void e_absorb(const KArgs<T>& a, Part<T>& p, Child<T>& c1, Child<T>& c2, DepAcc& acc,
+                                         LaneStats& ls, BlockStats* bs) {
+  const uint32_t v = vlin(a, p.ix);
+  deposit(a, acc, ls, p, p.e);
+  stat_add(bs, S_ABSORBED);
+  if (p.type == POSITRON) {
+    // annihilation at rest: two back-to-back photons, isotropic
+    stat_add(bs, S_ANNIH);
+    const T ct = T(2) * uni<T>(p.rng) - T(1);
+    const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+    const T s2 = T(1) - ct * ct;
+    const T st = M<T>::sqrt(s2 > T(0) ? s2 : T(0));
+    T sp, cp;
+    M<T>::sincos(phi, &sp, &cp);
+    const T d1[3] = {st * cp, st * sp, ct};
+    const T d2[3] = {-d1[0], -d1[1], -d1[2]};
+    make_child(a, p, c1, PHOTON, T(kMc2), d1, acc, ls, bs);
+    make_child(a, p, c2, PHOTON, T(kMc2), d2, acc, ls, bs);
+  }
+  p.e = T(0);
+  event(a, p, EV_ABSORB, v);
+  finish(a, p);
+}
+
+template <typename T>
+__device__ __forceinline__ void e_escape(const KArgs<T>& a, Part<T>& p, uint32_t v, BlockStats* bs) {
+  ledger_escape(a, bs, p);
+  event(a, p, EV_E_ESCAPE, v);
+  p.e = T(0);
+  finish(a, p);
+}
+
+template <typename T>
+__device__ __forceinline__ T binary_cos(T e, T w, bool primary) {
+  const T m2 = T(2.0 * kMc2);
+  T c2 = primary ? (e - w) * (e + m2) / (e * (e - w + m2)) : w * (e + m2) / (e * (w + m2));
+  if (c2 > T(1)) c2 = T(1);
+  return M<T>::sqrt(c2);
+}
+
+// one Class II step; returns false when the particle is gone
+template <typename T>
+__device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1, Child<T>& c2, DepAcc& acc,
+                       LaneStats& ls, BlockStats* bs) {
+  const Tab<T>& tb = a.tb;
+  const int nt = tb.n;
+  const int lep = p.type == POSITRON ? 1 : 0;
+  const int base = T_E + lep * T_ES;
+  const T eabs = a.eabs[p.type];
+  if (!(p.e > eabs)) {
+    e_absorb(a, p, c1, c2, acc, ls, bs);
+    return false;
+  }
+  ls.esteps++;
+  const T e = p.e;
+  const uint32_t v = vlin(a, p.ix);
+  const T rho = a.rho[v];
+  // step control: maximum mass step and hard-event majorant over [elo, e]
+  const Grid<T> g = grid_at(tb, M<T>::log(e));
+  const T ss = interp(tab, nt, base + O_LS, g, e, T(0));
+  const T tau_max = a.c2 * e / ss;
+  const T r0 = range_at(tab, nt, base, g, e);
+  T elo = r0 - tau_max > T(0) ? range_inv(tab, nt, base, r0 - tau_max) : tb.emin;
+  if (elo > e) elo = e;
+  const T smaj = majorant(tb, tab, base, lep, elo, g, e);
+  const T u1 = uni<T>(p.rng);
+  const T tau_h = smaj > T(0) ? -M<T>::log(u1) / smaj : M<T>::inf();
+  const bool capped = !(tau_h <= tau_max);
+  const T tau_s = capped ? tau_max : tau_h;
+  const double len = double(tau_s) / double(rho);
+  const double th = double(uni<T>(p.rng)) * len;
+  int ax;
+  const double db = face_dist(a, p, &ax);
+  if (ax < 0) {
+    atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+    return false;
+  }
+  if (db <= th) {
+    // the face comes first: soft loss over db, cross, start a new step
+    T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * db)));
+    if (!(e1 < e)) e1 = e;
+    deposit(a, acc, ls, p, e - e1);
+    p.e = e1;
+    event(a, p, EV_CROSS, v);
+    if (cross(a, p, db, ax, ls)) {
+      e_escape(a, p, v, bs);
+      return false;
+    }
+    return true;
+  }
+  // hinge: the soft energy loss of the whole step is charged here
+  move(p, th);
+  T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * len)));
+  if (!(e1 < e)) e1 = e;
+  deposit(a, acc, ls, p, e - e1);
+  p.e = e1;
+  if (!(e1 > eabs)) {
+    e_absorb(a, p, c1, c2, acc, ls, bs);
+    return false;
+  }
+  const T t1s = interp(tab, nt, base + O_LT1S, g, e, T(0));
+  const T mbar = T(0.5) * (T(1) - M<T>::exp(-T(double(rho) * len) * t1s));
+  const T A = soft_a(mbar);
+  const T u3 = uni<T>(p.rng);
+  const T mu = A * u3 / (T(1) + A - u3);
+  const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+  rotate(p.d, T(1) - T(2) * mu, phi);
+  const double rem = len - th;
+  const double db2 = face_dist(a, p, &ax);
+  if (ax < 0) {
+    atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+    return false;
+  }
+  if (db2 <= rem) {
+    event(a, p, EV_CROSS, v);
+    if (cross(a, p, db2, ax, ls)) {
+      e_escape(a, p, v, bs);
+      return false;
+    }
+    return true;
+  }
+  move(p, rem);
+  if (capped) {
+    event(a, p, EV_STEP, v);
+    return true;
+  }
+  // hard event or delta: elastic, inelastic, bremsstrahlung in this order
+  const T u = uni<T>(p.rng) * smaj;
+  const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
+  const T s_el = interp(tab, nt, base + O_LEL, g1, e1, T(0));
+  const T s_in = interp(tab, nt, base + O_LIN, g1, e1, tb.thr_in[lep]);
+  const T s_br = interp(tab, nt, base + O_LBR, g1, e1, tb.thr_br);
+  if (u < s_el) {
+    ls.hard_el++;
+    // screened Rutherford restricted to [mu_c, 1]
+    const T p2 = e1 * (e1 + T(2.0 * kMc2));
+    const T et = e1 + T(kMc2);
+    const T pv = p2 / et;
+    const T beta2 = p2 / (et * et);
+    const T kk = tb.k_coef * (T(kMc2) / pv) * (T(kMc2) / pv);
+    const T eta = tb.eta_a * (T(kMc2) * T(kMc2) / p2) * (T(1.13) + tb.eta_b / beta2);
+    T muc = T(1) / (s_el / kk + T(1) / (T(1) + eta)) - eta;
+    muc = muc < T(0) ? T(0) : (muc > T(1) ? T(1) : muc);
+    const T ia = T(1) / (muc + eta), ib = T(1) / (T(1) + eta);
+    T m = T(1) / (ia - uni<T>(p.rng) * (ia - ib)) - eta;
+    m = m < T(0) ? T(0) : (m > T(1) ? T(1) : m);
+    const T ph = T(2.0 * kPi) * uni<T>(p.rng);
+    rotate(p.d, T(1) - T(2) * m, ph);
+    event(a, p, EV_HARD_EL, v);
+  } else if (u < s_el + s_in) {
+    stat_add(bs, S_HARD_IN);
+    const T kc = a.wcc / e1;
+    const T gm = T(1) + e1 / T(kMc2);
+    const T aa = ((gm - T(1)) / gm) * ((gm - T(1)) / gm);
+    T k = kc;
+    if (lep == 0) {
+      for (int tries = 0; tries < kMaxTries; ++tries) {
+        const T uu = uni<T>(p.rng), ua = uni<T>(p.rng);
+        k = kc / (T(1) - uu * (T(1) - T(2) * kc));
+        const T f = T(1) / (k * k) + T(1) / ((T(1) - k) * (T(1) - k)) + aa - (T(1) - aa) / (k * (T(1) - k));
+        if (ua * T(2.25) <= k * k * f) break;
+      }
+    } else {
+      const T gp = gm + T(1);
+      const T b1 = aa * (T(2) * gp * gp - T(1)) / (gm * gm - T(1));
+      const T b2 = aa * (T(3) * gp * gp + T(1)) / (gp * gp);
+      const T b3 = aa * T(2) * (gm - T(1)) * gm / (gp * gp);
+      const T b4 = aa * (gm - T(1)) * (gm - T(1)) / (gp * gp);
+      for (int tries = 0; tries < kMaxTries; ++tries) {
+        const T uu = uni<T>(p.rng), ua = uni<T>(p.rng);
+        k = kc / (T(1) - uu * (T(1) - kc));
+        const T gg = T(1) - b1 * k + b2 * k * k - b3 * k * k * k + b4 * k * k * k * k;
+        if (ua <= gg) break;
+      }
+    }
+    const T ph = T(2.0 * kPi) * uni<T>(p.rng);
+    const T w = k * e1;
+    const T cp = binary_cos(e1, w, true), cs = binary_cos(e1, w, false);
+    T ds[3] = {p.d[0], p.d[1], p.d[2]};
+    rotate(ds, cs, ph + T(kPi));
+    rotate(p.d, cp, ph);
+    p.e = e1 - w;
+    make_child(a, p, c1, ELECTRON, w, ds, acc, ls, bs);
+    event(a, p, EV_HARD_IN, v);
+  } else if (u < s_el + s_in + s_br) {
+    stat_add(bs, S_HARD_BR);
+    const T w = a.wcr * M<T>::pow(e1 / a.wcr, uni<T>(p.rng));
+    const T ct = leading_angle(beta_of(e1), uni<T>(p.rng));
+    const T ph = T(2.0 * kPi) * uni<T>(p.rng);
+    T dg[3] = {p.d[0], p.d[1], p.d[2]};
+    rotate(dg, ct, ph);
+    p.e = e1 - w;
+    make_child(a, p, c1, PHOTON, w, dg, acc, ls, bs);
+    event(a, p, EV_HARD_BR, v);
+  } else {
+    ls.delta++;
+    event(a, p, EV_STEP, v);
+  }
+  return true;
+}
+
+template <typename T>
+__global__ void k_estep(KArgs<T> a, int par) {
+  const uint32_t n = min(a.cnt->n[q_ein(par)], a.cap);
+  if (blockIdx.x * blockDim.x >= n) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tab = reinterpret_cast<T*>(smem);
+  __shared__ BlockStats bs;
+  LaneStats ls;
+  stats_init(&bs, ls);
+  stage(a.tb, tab, T_NCH);
+  __syncthreads();
+  const Bank<T>& in = a.q[q_ein(par)];
+  const int ge = q_eout(par), gg = q_gout(par);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    bool alive = i < n;
+    Part<T> p;
+    DepAcc acc{kEmptyKey, 0.0};
+    if (alive) load_part(a, in, i, p);
+    for (uint32_t s = 0; s < a.steps; ++s) {
+      Child<T> c1, c2;
+      c1.on = false;
+      c2.on = false;
+      if (alive) alive = e_step(a, tab, p, c1, c2, acc, ls, &bs);
+      // secondaries of this step, wavefront-aggregated
+      const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
+      const uint32_t se = append(a, ge, c1e);
+      if (c1e && se != ~0u) store_child(a, a.q[ge], se, p, c1);
+      const uint32_t sg = append(a, gg, c1g);
+      if (c1g && sg != ~0u) store_child(a, a.q[gg], sg, p, c1);
+      const uint32_t s2 = append(a, gg, c2.on);
+      if (c2.on && s2 != ~0u) store_child(a, a.q[gg], s2, p, c2);
+      if (!__any(alive)) break;
+    }
+    dep_flush(a, acc);
+    const uint32_t so = append(a, ge, alive);
+    if (alive && so != ~0u) store_part(a, a.q[ge], so, p);
+  }
+  stats_flush(&bs, ls, a.cnt);
+}
+
+// ---------------------------------------------------------------------------
+// bookkeeping between iterations (one thread)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_advance(Counters* c, int par, uint32_t target, uint32_t cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  c->n[Q_G0 + 1 - par] = min(c->n[Q_G0 + 1 - par], cap);
+  c->n[Q_E0 + 1 - par] = min(c->n[Q_E0 + 1 - par], cap);
+  c->n[Q_G0 + par] = 0u;
+  c->n[Q_E0 + par] = 0u;
+  c->n[Q_KC] = c->n[Q_KP] = c->n[Q_KR] = c->n[Q_KX] = 0u;
+  c->cursor += c->adm;
+  const uint32_t pop = c->n[Q_G0 + 1 - par] + c->n[Q_E0 + 1 - par];
+  const uint64_t rem = c->chunk_end - c->cursor;
+  uint64_t adm = target > pop ? uint64_t(target - pop) : 0ull;
+  if (adm > rem) adm = rem;
+  c->adm = uint32_t(adm);
+  c->done = (pop == 0u && rem == 0ull) ? 1u : 0u;
+  c->iter++;
+}
+
+// start of a chunk of histories [first, end)
+template <typename T>
+__global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int q = 0; q < Q_NQ; ++q) c->n[q] = 0u;
+  c->overflow = 0u;
+  c->done = 0u;
+  c->iter = 0u;
+  c->cursor = first;
+  c->chunk_end = end;
+  c->run_first = run_first;
+  c->adm = adm;
+  c->occupied = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// tally flush: each (history, voxel) score q becomes Sum q += q and
+// Sum q^2 += q^2 (Eq. (1)-(3)); slots are cleared for the next chunk
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2,
+                        Counters* cnt, int test_mode, double* hist_led, uint64_t n_run) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  uint32_t occ = 0;
+  for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
+    const uint64_t k = keys[s];
+    if (k == kEmptyKey) continue;
+    const double q = vals[s];
+    const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
+    unsafeAtomicAdd(&sum_q[v], q);
+    unsafeAtomicAdd(&sum_q2[v], q * q);
+    if (test_mode) {
+      const uint64_t h = (k >> 32) - cnt->run_first;
+      if (h < n_run) unsafeAtomicAdd(&hist_led[3 * h], q);
+    }
+    keys[s] = kEmptyKey;
+    vals[s] = 0.0;
+    ++occ;
+  }
+  occ = wave_sum(occ);
+  if (__lane_id() == 0 && occ) atomicAdd((unsigned long long*)&cnt->occupied, (unsigned long long)occ);
+}
+
+// dose (eV/g per history) and its standard error, Eq. (1)-(3)
+template <typename T>
+__global__ void k_dose(const double* sum_q, const double* sum_q2, const T* rho, uint64_t nvox, double vol,
+                       double nhist, double* dose, double* sigma) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nvox; v += stride) {
+    const double mass = double(rho[v]) * vol;
+    const double qm = sum_q[v] / nhist, q2 = sum_q2[v] / nhist;
+    double var = (q2 - qm * qm) / nhist;
+    if (var < 0.0) var = 0.0;
+    dose[v] = qm * 1e6 / mass;
+    if (sigma) sigma[v] = sqrt(var) * 1e6 / mass;
+  }
+}
+
+}  // namespace mcx
