@@ -136,6 +136,14 @@ typedef struct {
   uint64_t pos_esc;
   uint64_t iterations, chunks, tally_pairs;
   double ms_transport, ms_flush;
+  /* work counters of the e+- step kernel: records read, records written,
+   * tally-table insertions */
+  uint64_t evisits, ewrites, inserts;
+  /* per-kernel GPU time (HIP events on the run's stream) when timing is on:
+   * source, photon flight, photon interactions, e+- steps; and the number of
+   * iterations timed (each iteration launches each kernel once) */
+  double ms_source, ms_flight, ms_knock, ms_estep;
+  uint64_t timed_iterations;
 } mcx_stats;
 
 /* Create a context on HIP device `hip_device` computing in `precision`
@@ -161,6 +169,9 @@ int mcx_set_sources(mcx_ctx* ctx, const mcx_source* s, int n);
  * queue (capacity of each event queue), block = threads per block (multiple
  * of 64, <= 1024), steps = Class II steps per visit of the e+- kernel. */
 int mcx_set_launch(mcx_ctx* ctx, uint32_t bank, uint32_t block, uint32_t steps);
+/* Enable (1) or disable (0) per-kernel timing with HIP events recorded on
+ * the run's stream around each transport kernel (small overhead). */
+int mcx_set_timing(mcx_ctx* ctx, int on);
 /* Enable (1) or disable (0) the per-history event hash and energy ledger
  * used by the parity tests (costs extra device traffic). */
 int mcx_set_test_mode(mcx_ctx* ctx, int on);

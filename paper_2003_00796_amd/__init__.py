@@ -28,7 +28,7 @@ ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM"
 
 # every symbol the C ABI exports (include/mcx.h)
 ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport", "mcx_load_material",
-               "mcx_load_phantom", "mcx_set_sources", "mcx_set_launch", "mcx_set_test_mode", "mcx_run",
+               "mcx_load_phantom", "mcx_set_sources", "mcx_set_launch", "mcx_set_timing", "mcx_set_test_mode", "mcx_run",
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
                "mcx_get_history_results")
 
@@ -64,7 +64,9 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in _STATS_U64_A] + [
         ("e_dep", C.c_double), ("e_esc", C.c_double), ("pos_esc", C.c_uint64), ("iterations", C.c_uint64),
         ("chunks", C.c_uint64), ("tally_pairs", C.c_uint64), ("ms_transport", C.c_double),
-        ("ms_flush", C.c_double)]
+        ("ms_flush", C.c_double), ("evisits", C.c_uint64), ("ewrites", C.c_uint64), ("inserts", C.c_uint64),
+        ("ms_source", C.c_double), ("ms_flight", C.c_double), ("ms_knock", C.c_double), ("ms_estep", C.c_double),
+        ("timed_iterations", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -97,6 +99,7 @@ def lib():
         L.mcx_set_sources.argtypes = [vp, C.POINTER(Source), C.c_int]
         L.mcx_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
         L.mcx_set_test_mode.argtypes = [vp, C.c_int]
+        L.mcx_set_timing.argtypes = [vp, C.c_int]
         L.mcx_run.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp]
         L.mcx_get_dose.argtypes = [vp, vp, vp, C.c_int, vp]
         L.mcx_get_tally.argtypes = [vp, vp, vp, C.c_int, vp]
@@ -200,6 +203,9 @@ class Simulator:
 
     def set_launch(self, bank: int = 0, block: int = 0, steps: int = 0):
         self._check(self._L.mcx_set_launch(self._h, bank, block, steps), "set_launch")
+
+    def set_timing(self, on: bool):
+        self._check(self._L.mcx_set_timing(self._h, 1 if on else 0), "set_timing")
 
     def set_test_mode(self, on: bool):
         self._check(self._L.mcx_set_test_mode(self._h, 1 if on else 0), "set_test_mode")

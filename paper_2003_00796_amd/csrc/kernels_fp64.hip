@@ -5,13 +5,19 @@
 
 namespace mcx {
 
-hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s) {
+hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                            hipEvent_t* ev) {
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(double);
   const size_t sm_e = size_t(T_NCH) * a.tb.n * sizeof(double);
+  if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(block), 0, s, a, par);
+  if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_flight<double>, dim3(grid), dim3(block), sm_f, s, a, par);
+  if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_knock<double>, dim3(grid), dim3(block), 0, s, a, par);
+  if (ev) (void)hipEventRecord(ev[3], s);
   hipLaunchKernelGGL(k_estep<double>, dim3(grid), dim3(block), sm_e, s, a, par);
+  if (ev) (void)hipEventRecord(ev[4], s);
   hipLaunchKernelGGL(k_advance<double>, dim3(1), dim3(64), 0, s, a.cnt, par, target, a.cap);
   return hipGetLastError();
 }

@@ -7,9 +7,14 @@
 
 namespace mcx {
 
-// one iteration of the event loop: source, flight, knock, e+- steps, advance
-hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s);
-hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s);
+// one iteration of the event loop: source, flight, knock, e+- steps, advance;
+// if ev is not null, ev[0..4] are recorded before the source kernel and after
+// each of the four transport kernels (per-kernel durations)
+constexpr int kTimedKernels = 4;
+hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                            hipEvent_t* ev);
+hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                            hipEvent_t* ev);
 hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm,
                              hipStream_t s);
 hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2,

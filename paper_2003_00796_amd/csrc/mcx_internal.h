@@ -53,7 +53,11 @@ enum Queue : int { Q_G0 = 0, Q_G1, Q_E0, Q_E1, Q_KC, Q_KP, Q_KR, Q_KX, Q_NQ };
 enum Stat : int {
   S_FLIGHTS = 0, S_COMPTON, S_PHOTO, S_RAYLEIGH, S_PAIR, S_ESTEPS, S_HARD_EL, S_HARD_IN,
   S_HARD_BR, S_DELTA, S_ANNIH, S_CROSSINGS, S_SECONDARIES, S_DEPOSITS, S_ABSORBED,
-  S_ESCAPED, S_POSESC, S_NSTAT
+  S_ESCAPED, S_POSESC,
+  S_EVISITS,    // e+- records read by the step kernel
+  S_EWRITES,    // records written by the step kernel (survivors + secondaries)
+  S_INSERTS,    // tally-table insertions
+  S_NSTAT
 };
 
 enum Overflow : uint32_t { OVF_QUEUE = 1u, OVF_TALLY = 2u, OVF_SOURCE = 4u, OVF_LOST = 8u };

@@ -69,7 +69,14 @@ struct mcx_ctx {
   // stats
   uint64_t iterations = 0, chunks = 0, tally_pairs = 0;
   double ms_transport = 0.0, ms_flush = 0.0;
+  // per-kernel timing with HIP events on the run's stream
+  int timing = 0;
+  std::vector<hipEvent_t> events;  // kBatch iterations x (kTimedKernels + 1)
+  double ms_kernel[kTimedKernels] = {0, 0, 0, 0};
+  uint64_t timed_iterations = 0;
 };
+
+static constexpr int kBatch = 8;  // iterations between completion checks
 
 namespace {
 
@@ -240,8 +247,9 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
     hipError_t e = launch_chunk_init(a.cnt, cf, ce, first, uint32_t(std::min<uint64_t>(chunk, target)), s);
     if (e != hipSuccess) return hip_fail(c, e, "chunk init launch");
     for (;;) {
-      for (int k = 0; k < 8; ++k) {
-        e = launch_iteration(a, par, target, grid, int(c->block), s);
+      for (int k = 0; k < kBatch; ++k) {
+        hipEvent_t* ev = c->timing ? &c->events[size_t(k) * (kTimedKernels + 1)] : nullptr;
+        e = launch_iteration(a, par, target, grid, int(c->block), s, ev);
         if (e != hipSuccess) return hip_fail(c, e, "iteration launch");
         par ^= 1;
         c->iterations++;
@@ -249,6 +257,16 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) return hip_fail(c, e, "transport iterations");
+      if (c->timing) {
+        for (int k = 0; k < kBatch; ++k) {
+          const hipEvent_t* ev = &c->events[size_t(k) * (kTimedKernels + 1)];
+          for (int j = 0; j < kTimedKernels; ++j) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[j], ev[j + 1]) == hipSuccess) c->ms_kernel[j] += ms;
+          }
+        }
+        c->timed_iterations += kBatch;
+      }
       if (c->h_cnt->overflow & OVF_QUEUE)
         return fail(c, MCX_E_RANGE, "event queue overflow (capacity %u records); raise the bank size", c->cap);
       if (c->h_cnt->overflow & OVF_TALLY)
@@ -307,6 +325,7 @@ void mcx_destroy(mcx_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
                     &c->d_hvals, &c->d_hhash, &c->d_hled})
     dfree(*b);
@@ -379,6 +398,8 @@ int mcx_reset_tallies(mcx_ctx* c) {
   c->n_done = 0;
   c->iterations = c->chunks = c->tally_pairs = 0;
   c->ms_transport = c->ms_flush = 0.0;
+  for (double& m : c->ms_kernel) m = 0.0;
+  c->timed_iterations = 0;
   return MCX_OK;
 }
 
@@ -494,6 +515,23 @@ int mcx_set_launch(mcx_ctx* c, uint32_t bank, uint32_t block, uint32_t steps) {
   return MCX_OK;
 }
 
+int mcx_set_timing(mcx_ctx* c, int on) {
+  if (!c) return MCX_E_INVALID;
+  if (on && c->events.empty()) {
+    (void)hipSetDevice(c->device);
+    c->events.resize(size_t(kBatch) * (kTimedKernels + 1));
+    for (hipEvent_t& ev : c->events) {
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) {
+        c->events.clear();
+        return hip_fail(c, e, "hipEventCreate");
+      }
+    }
+  }
+  c->timing = on ? 1 : 0;
+  return MCX_OK;
+}
+
 int mcx_set_test_mode(mcx_ctx* c, int on) {
   if (!c) return MCX_E_INVALID;
   c->test_mode = on ? 1 : 0;
@@ -590,6 +628,11 @@ int mcx_get_stats(mcx_ctx* c, mcx_stats* out) {
   out->tally_pairs = c->tally_pairs;
   out->ms_transport = c->ms_transport;
   out->ms_flush = c->ms_flush;
+  out->ms_source = c->ms_kernel[0];
+  out->ms_flight = c->ms_kernel[1];
+  out->ms_knock = c->ms_kernel[2];
+  out->ms_estep = c->ms_kernel[3];
+  out->timed_iterations = c->timed_iterations;
   if (!c->d_cnt.p) return MCX_OK;
   (void)hipSetDevice(c->device);
   Counters h;
@@ -612,6 +655,9 @@ int mcx_get_stats(mcx_ctx* c, mcx_stats* out) {
   out->absorbed = h.stat[S_ABSORBED];
   out->escaped = h.stat[S_ESCAPED];
   out->pos_esc = h.stat[S_POSESC];
+  out->evisits = h.stat[S_EVISITS];
+  out->ewrites = h.stat[S_EWRITES];
+  out->inserts = h.stat[S_INSERTS];
   out->e_dep = h.e_dep;
   out->e_esc = h.e_esc;
   return MCX_OK;

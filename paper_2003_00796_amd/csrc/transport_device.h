@@ -224,14 +224,14 @@ struct BlockStats {
 };
 
 struct LaneStats {
-  uint32_t esteps, deposits, crossings, hard_el, delta, flights;
+  uint32_t esteps, deposits, crossings, hard_el, delta, flights, inserts, visits, writes;
   double e_dep;
 };
 
 __device__ __forceinline__ void stats_init(BlockStats* s, LaneStats& l) {
   for (int i = threadIdx.x; i < S_NSTAT; i += blockDim.x) s->c[i] = 0ull;
   if (threadIdx.x == 0) { s->e_dep = 0.0; s->e_esc = 0.0; }
-  l.esteps = l.deposits = l.crossings = l.hard_el = l.delta = l.flights = 0u;
+  l.esteps = l.deposits = l.crossings = l.hard_el = l.delta = l.flights = l.inserts = l.visits = l.writes = 0u;
   l.e_dep = 0.0;
 }
 
@@ -250,6 +250,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ void stats_flush(BlockStats* s, const LaneStats& l, Counters* cnt) {
   const uint32_t es = wave_sum(l.esteps), de = wave_sum(l.deposits), cr = wave_sum(l.crossings);
   const uint32_t he = wave_sum(l.hard_el), dl = wave_sum(l.delta), fl = wave_sum(l.flights);
+  const uint32_t in = wave_sum(l.inserts), vi = wave_sum(l.visits), wr = wave_sum(l.writes);
   const double ed = wave_sum(l.e_dep);
   if (__lane_id() == 0) {
     if (es) atomicAdd(&s->c[S_ESTEPS], (unsigned long long)es);
@@ -258,6 +259,9 @@ __device__ __forceinline__ void stats_flush(BlockStats* s, const LaneStats& l, C
     if (he) atomicAdd(&s->c[S_HARD_EL], (unsigned long long)he);
     if (dl) atomicAdd(&s->c[S_DELTA], (unsigned long long)dl);
     if (fl) atomicAdd(&s->c[S_FLIGHTS], (unsigned long long)fl);
+    if (in) atomicAdd(&s->c[S_INSERTS], (unsigned long long)in);
+    if (vi) atomicAdd(&s->c[S_EVISITS], (unsigned long long)vi);
+    if (wr) atomicAdd(&s->c[S_EWRITES], (unsigned long long)wr);
     if (ed != 0.0) atomicAdd(&s->e_dep, ed);
   }
   __syncthreads();
@@ -277,7 +281,8 @@ __device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long lon
 // tally: (history, voxel) -> score, open addressing with linear probing
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void tally_insert(const KArgs<T>& a, uint64_t key, double q) {
+__device__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
+  ls.inserts++;
   uint64_t slot = mix64(key) & a.hmask;
   for (int probe = 0; probe < 4096; ++probe) {
     uint64_t k = __hip_atomic_load(&a.hkeys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -302,8 +307,8 @@ struct DepAcc {
 };
 
 template <typename T>
-__device__ __forceinline__ void dep_flush(const KArgs<T>& a, DepAcc& acc) {
-  if (acc.key != kEmptyKey && acc.q != 0.0) tally_insert(a, acc.key, acc.q);
+__device__ __forceinline__ void dep_flush(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
+  if (acc.key != kEmptyKey && acc.q != 0.0) tally_insert(a, acc.key, acc.q, ls);
   acc.key = kEmptyKey;
   acc.q = 0.0;
 }
@@ -318,7 +323,7 @@ __device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStat
   if (e == T(0)) return;
   const uint64_t key = (uint64_t(p.hist) << 32) | vlin(a, p.ix);
   if (key != acc.key) {
-    dep_flush(a, acc);
+    dep_flush(a, acc, ls);
     acc.key = key;
   }
   acc.q += double(e);

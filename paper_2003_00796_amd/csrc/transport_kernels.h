@@ -304,7 +304,7 @@ __global__ void k_knock(KArgs<T> a, int par) {
         event(a, p, EV_PAIR, v);
       }
       if (!keep) finish(a, p);
-      dep_flush(a, acc);
+      dep_flush(a, acc, ls);
     }
     const uint32_t sg = append(a, q_gout(par), keep);
     if (keep && sg != ~0u) store_part(a, a.q[q_gout(par)], sg, p);
@@ -540,7 +540,10 @@ __global__ void k_estep(KArgs<T> a, int par) {
     bool alive = i < n;
     Part<T> p;
     DepAcc acc{kEmptyKey, 0.0};
-    if (alive) load_part(a, in, i, p);
+    if (alive) {
+      load_part(a, in, i, p);
+      ls.visits++;
+    }
     for (uint32_t s = 0; s < a.steps; ++s) {
       Child<T> c1, c2;
       c1.on = false;
@@ -554,11 +557,13 @@ __global__ void k_estep(KArgs<T> a, int par) {
       if (c1g && sg != ~0u) store_child(a, a.q[gg], sg, p, c1);
       const uint32_t s2 = append(a, gg, c2.on);
       if (c2.on && s2 != ~0u) store_child(a, a.q[gg], s2, p, c2);
+      ls.writes += uint32_t(c1.on) + uint32_t(c2.on);
       if (!__any(alive)) break;
     }
-    dep_flush(a, acc);
+    dep_flush(a, acc, ls);
     const uint32_t so = append(a, ge, alive);
     if (alive && so != ~0u) store_part(a, a.q[ge], so, p);
+    ls.writes += uint32_t(alive);
   }
   stats_flush(&bs, ls, a.cnt);
 }

@@ -192,7 +192,10 @@ def test_independent_seed_z_scores():
     wl = W.workload("water_pencil_32", 20000)
     g = gpu_run(wl, 20000, seed=11, test=False)
     o = oracle_run(wl, 20000, seed=12)
-    hi = o["dose"] > 0.01 * o["dose"].max()
+    # select on the mean of both runs: selecting on one run alone keeps that
+    # run's upward fluctuations near the threshold and biases z downwards
+    m = 0.5 * (g["dose"] + o["dose"])
+    hi = m > 0.01 * m.max()
     z = (g["dose"] - o["dose"])[hi] / np.sqrt(g["sigma"][hi] ** 2 + o["sigma"][hi] ** 2)
     assert abs(z.mean()) < 5 / math.sqrt(z.size) + 0.05
     assert 0.85 < z.std() < 1.15
