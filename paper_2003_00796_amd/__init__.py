@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmcx.so")
+# MCX_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MCX_LIBRARY") or os.path.join(_HERE, "libmcx.so")
 
 FP64, MIXED = 0, 1
 PHOTON, ELECTRON, POSITRON = 0, 1, 2

@@ -1,7 +1,8 @@
 """Build libmcx.so (HIP for gfx950) in-tree with hipcc.
 
 Each source is compiled on its own; the FP64 kernels are compiled without
-multiply-add contraction, the mixed-precision kernels with it.  Packed FP32
+multiply-add contraction, the mixed-precision kernels with it and with
+reciprocal-based FP32 division.  Packed FP32
 instructions are disabled for all device code.
 """
 from __future__ import annotations
@@ -23,8 +24,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.
           "-Wall", "-Wno-unused-function"]
 
 UNITS = [
+    # FP64 path: IEEE division and square root, no multiply-add fusion
     ("kernels_fp64.hip", ["-ffp-contract=off"]),
-    ("kernels_mixed.hip", []),
+    # mixed path: FP32 physics may use reciprocal-based division and flush
+    # FP32 denormals; infinities and NaNs keep their IEEE meaning
+    ("kernels_mixed.hip", ["-freciprocal-math", "-fno-signed-zeros", "-fno-trapping-math", "-fno-math-errno",
+                           "-fgpu-flush-denormals-to-zero"]),
     ("runtime.hip", []),
 ]
 
@@ -37,25 +42,26 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, defines=(), lib: str = LIB, out: str = OUT) -> str:
+    """Compile and link; `defines` are extra -D flags for the device code."""
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    os.makedirs(OUT, exist_ok=True)
+    os.makedirs(out, exist_ok=True)
     objs = []
     for src, extra in UNITS:
-        obj = os.path.join(OUT, src + ".o")
-        cmd = [hipcc] + COMMON + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        obj = os.path.join(out, src + ".o")
+        cmd = [hipcc] + COMMON + [f"-D{d}" for d in defines] + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd))
         _run(cmd)
         objs.append(obj)
-    tobj = os.path.join(OUT, "tables.o")
+    tobj = os.path.join(out, "tables.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC, "-c", "-o", tobj, os.path.join(CSRC, "tables.cpp")])
     objs.append(tobj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

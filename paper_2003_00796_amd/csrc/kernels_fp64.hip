@@ -8,7 +8,7 @@ namespace mcx {
 hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
                             hipEvent_t* ev) {
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(double);
-  const size_t sm_e = size_t(T_NCH) * a.tb.n * sizeof(double);
+  const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(double);
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
@@ -28,12 +28,10 @@ hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   return hipGetLastError();
 }
 
-hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2,
-                        Counters* cnt, int test_mode, double* hist_led, uint64_t n_run, hipStream_t s) {
-  const int block = 256;
-  uint64_t g = (nslot + block - 1) / block;
-  if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_flush<double>, dim3(unsigned(g)), dim3(block), 0, s, keys, vals, nslot, sum_q, sum_q2, cnt,
+hipError_t launch_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, uint64_t nslot, double* sum_q,
+                        double* sum_q2, Counters* cnt, int test_mode, double* hist_led, uint64_t n_run,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_flush<double>, dim3(4096), dim3(256), 0, s, keys, vals, occ_list, nslot, sum_q, sum_q2, cnt,
                      test_mode, hist_led, n_run);
   return hipGetLastError();
 }
@@ -48,7 +46,9 @@ hipError_t launch_dose(const double* sum_q, const double* sum_q2, const double* 
   return hipGetLastError();
 }
 
-size_t estep_lds_bytes(int n, bool fp64) { return size_t(T_NCH) * n * (fp64 ? sizeof(double) : sizeof(float)); }
+size_t estep_lds_bytes(int n, bool fp64) {
+  return (size_t(T_NCH) * n + kSoftN) * (fp64 ? sizeof(double) : sizeof(float));
+}
 
 hipError_t configure_fp64(int n_grid) {
   const int bytes = int(estep_lds_bytes(n_grid, true));

@@ -8,7 +8,7 @@ namespace mcx {
 hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
                             hipEvent_t* ev) {
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(float);
-  const size_t sm_e = size_t(T_NCH) * a.tb.n * sizeof(float);
+  const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(float);
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);

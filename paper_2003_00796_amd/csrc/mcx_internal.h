@@ -25,6 +25,7 @@ constexpr double kHc = 1.23984198e-2;        // MeV Angstrom
 constexpr double kPi = 3.14159265358979323846;
 
 constexpr int kMaxGrid = 512;
+constexpr int kMaxBlock = 256;  // kernels are compiled for blocks of at most 256 threads
 constexpr uint64_t kEmptyKey = ~0ull;
 
 enum Particle : uint32_t { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
@@ -35,6 +36,13 @@ enum Particle : uint32_t { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
 // elastic, ln hard inelastic, ln hard bremsstrahlung, ln soft transport
 // coefficient, node sum of the three hard coefficients.  Zero values are
 // stored as ln 0 = -inf.
+// Initial guess of the soft angular law parameter: ln A at kSoftN points
+// uniform in ln <mu> over [ln kSoftMLo, ln kSoftMHi], stored after the
+// channel block (offset T_NCH * n).
+constexpr int kSoftN = 256;
+constexpr double kSoftMLo = 1e-9;
+constexpr double kSoftMHi = 0.49;
+
 enum TabChannel : int {
   T_ENODE = 0,  // node energies
   T_LMU_C = 1, T_LMU_PE = 2, T_LMU_R = 3, T_LMU_PP = 4,
@@ -71,12 +79,14 @@ struct Counters {
   uint32_t done;           // chunk finished
   uint32_t adm;            // histories admitted by the next source launch
   uint32_t iter;
+  uint32_t take_e;         // records of the e+- input queue taken in this iteration
   uint64_t cursor;         // next history id to admit
   uint64_t chunk_end;      // end of the current chunk (exclusive)
   uint64_t run_first;      // first history id of the current mcx_run call
   uint64_t stat[S_NSTAT];
   double e_dep, e_esc;
   uint64_t occupied;       // tally pairs seen by the last flush
+  uint64_t n_occ;          // tally slots claimed in the current chunk (list length)
 };
 
 template <typename T>
@@ -129,6 +139,7 @@ struct KArgs {
   uint64_t* hkeys;
   double* hvals;
   uint64_t hmask;
+  uint32_t* occ_list;    // slots claimed in this chunk, in claim order
   double* sum_q;
   double* sum_q2;
   // test mode per-history outputs (indexed by history - cnt->run_first)

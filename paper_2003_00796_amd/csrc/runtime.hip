@@ -51,14 +51,14 @@ struct mcx_ctx {
   DevBuf d_sumq, d_sumq2;
   uint64_t n_done = 0;
   // event queues
-  uint32_t cap = 1u << 21, block = 256, steps = 32;
+  uint32_t cap = 1u << 21, block = 256, steps = 128;
   DevBuf d_queues;
   size_t queue_cap_built = 0;
   DevBuf d_cnt;
   Counters* h_cnt = nullptr;  // pinned
   // tally table
   uint64_t hslots = 1ull << 27;
-  DevBuf d_hkeys, d_hvals;
+  DevBuf d_hkeys, d_hvals, d_occ;
   double pairs_per_hist = 0.0;
   bool table_dirty = false;  // a failed run may have left entries behind
   // test mode
@@ -164,10 +164,14 @@ int ensure_workspace(mcx_ctx* c) {
     if ((rc = dalloc(c, c->d_queues, queue_bytes(c), "event queues"))) return rc;
     c->queue_cap_built = c->cap;
   }
+  // fresh allocations are cleared on the context's stream (non-blocking, so
+  // it does not order against the null stream) and waited for: reused device
+  // memory may still hold an earlier context's entries
   if (!c->d_cnt.p) {
     if ((rc = dalloc(c, c->d_cnt, sizeof(Counters), "counters"))) return rc;
-    hipError_t e = hipMemset(c->d_cnt.p, 0, sizeof(Counters));
-    if (e != hipSuccess) return hip_fail(c, e, "hipMemset counters");
+    hipError_t e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "clear counters");
   }
   if (!c->h_cnt) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->h_cnt), sizeof(Counters), hipHostMallocDefault);
@@ -176,9 +180,11 @@ int ensure_workspace(mcx_ctx* c) {
   if (!c->d_hkeys.p) {
     if ((rc = dalloc(c, c->d_hkeys, c->hslots * sizeof(uint64_t), "tally keys"))) return rc;
     if ((rc = dalloc(c, c->d_hvals, c->hslots * sizeof(double), "tally values"))) return rc;
-    hipError_t e = hipMemset(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMemset(c->d_hvals.p, 0, c->hslots * sizeof(double));
-    if (e != hipSuccess) return hip_fail(c, e, "hipMemset tally table");
+    if ((rc = dalloc(c, c->d_occ, c->hslots * sizeof(uint32_t), "tally slot list"))) return rc;
+    hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, c->hslots * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "clear tally table");
   }
   return MCX_OK;
 }
@@ -214,6 +220,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed) {
   a.hkeys = static_cast<uint64_t*>(c->d_hkeys.p);
   a.hvals = static_cast<double*>(c->d_hvals.p);
   a.hmask = c->hslots - 1;
+  a.occ_list = static_cast<uint32_t*>(c->d_occ.p);
   a.sum_q = static_cast<double*>(c->d_sumq.p);
   a.sum_q2 = static_cast<double*>(c->d_sumq2.p);
   a.test_mode = c->test_mode;
@@ -276,7 +283,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       if (c->h_cnt->done) break;
     }
     auto tf = std::chrono::steady_clock::now();
-    e = launch_flush(a.hkeys, a.hvals, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+    e = launch_flush(a.hkeys, a.hvals, a.occ_list, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "tally flush");
@@ -327,7 +334,7 @@ void mcx_destroy(mcx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
-                    &c->d_hvals, &c->d_hhash, &c->d_hled})
+                    &c->d_hvals, &c->d_occ, &c->d_hhash, &c->d_hled})
     dfree(*b);
   if (c->h_cnt) (void)hipHostFree(c->h_cnt);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -367,7 +374,7 @@ int mcx_load_material(mcx_ctx* c, int mat_id, const mcx_material_desc* m) {
   if (!build_tables(*m, c->tr, &b, &err)) return fail(c, MCX_E_INVALID, "%s", err.c_str());
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   int rc;
-  const size_t bytes = b.block.size() * tsize(c);
+  const size_t bytes = b.block.size() * tsize(c);  // channels + soft-law guesses
   if ((rc = dalloc(c, c->d_tab, bytes, "tables"))) return rc;
   hipError_t e;
   if (fp64(c)) {
@@ -505,7 +512,8 @@ int mcx_set_launch(mcx_ctx* c, uint32_t bank, uint32_t block, uint32_t steps) {
     c->cap = bank;
   }
   if (block) {
-    if (block % 64 || block > 1024) return fail(c, MCX_E_INVALID, "block must be a multiple of 64, <= 1024");
+    if (block % 64 || block > uint32_t(kMaxBlock))
+      return fail(c, MCX_E_INVALID, "block must be a multiple of 64, <= %d", kMaxBlock);
     c->block = block;
   }
   if (steps) {

@@ -171,7 +171,7 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
   b.n = n;
   b.lemin = std::log(t.e_min);
   b.dl = (std::log(t.e_max) - b.lemin) / double(n - 1);
-  b.block.assign(size_t(T_NCH) * n, 0.0);
+  b.block.assign(size_t(T_NCH) * n + kSoftN, 0.0);
   auto ch = [&](int c) { return b.block.data() + size_t(c) * n; };
   Model md(m, t);
   const uint32_t fl = t.flags;
@@ -241,6 +241,23 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
                                                 : (e[i] / s_soft[i]) * (std::pow(x, q) - 1.0) / q;
         r += seg;
       }
+    }
+  }
+  // ln A(<mu>) of the soft law p(mu) ~ (mu + A)^-2, mean A(1+A)ln(1+1/A) - A,
+  // by bisection in ln A (initial guesses for the device's Newton steps)
+  {
+    double* soft = b.block.data() + size_t(T_NCH) * n;
+    const double x0 = std::log(kSoftMLo), x1 = std::log(kSoftMHi);
+    for (int j = 0; j < kSoftN; ++j) {
+      const double m = std::exp(x0 + (x1 - x0) * j / (kSoftN - 1));
+      double lo = -700.0, hi = std::log(1e6);
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi), a = std::exp(mid);
+        const double mean = a * ((1.0 + a) * std::log1p(1.0 / a) - 1.0);
+        if (mean < m) lo = mid;
+        else hi = mid;
+      }
+      soft[j] = 0.5 * (lo + hi);
     }
   }
   b.k_coef = md.k_coef();

@@ -11,7 +11,7 @@ namespace mcx {
 struct BuiltTables {
   int n = 0;
   double lemin = 0, dl = 0;
-  std::vector<double> block;  // T_NCH * n, channel-major
+  std::vector<double> block;  // T_NCH * n channel-major, then kSoftN soft-law guesses
   double thr_pp = 0, thr_in[2] = {0, 0}, thr_br = 0;
   double k_coef = 0, eta_a = 0, eta_b = 0, ray_a = 0;
 };

@@ -289,7 +289,13 @@ __device__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStat
     if (k == kEmptyKey) {
       k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
                     (unsigned long long)key);
-      if (k == kEmptyKey) k = key;
+      if (k == kEmptyKey) {
+        // this lane claimed the slot: record it for the flush (at most one
+        // entry per slot and chunk, so the list never exceeds the table)
+        const unsigned long long idx = atomicAdd((unsigned long long*)&a.cnt->n_occ, 1ull);
+        a.occ_list[idx] = uint32_t(slot);
+        k = key;
+      }
     }
     if (k == key) {
       unsafeAtomicAdd(&a.hvals[slot], q);
@@ -402,13 +408,20 @@ __device__ __forceinline__ bool cross(const KArgs<T>& a, Part<T>& p, double s, i
   const double o[3] = {a.ox, a.oy, a.oz};
   const double dd[3] = {a.dx, a.dy, a.dz};
   const int n[3] = {a.nx, a.ny, a.nz};
-  const bool up = p.d[ax] > T(0);
-  const double fv = up ? o[ax] + double(p.ix[ax] + 1) * dd[ax] : o[ax] + double(p.ix[ax]) * dd[ax];
   move(p, s);
-  p.x[ax] = fv;
-  p.ix[ax] += up ? 1 : -1;
+  bool out = false;
+  // unrolled so that every array index is a constant (no scratch memory)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k == ax) {
+      const bool up = p.d[k] > T(0);
+      p.x[k] = up ? o[k] + double(p.ix[k] + 1) * dd[k] : o[k] + double(p.ix[k]) * dd[k];
+      p.ix[k] += up ? 1 : -1;
+      out = p.ix[k] < 0 || p.ix[k] >= n[k];
+    }
+  }
   ls.crossings++;
-  return p.ix[ax] < 0 || p.ix[ax] >= n[ax];
+  return out;
 }
 
 // polar deflection by cos_t and azimuth phi, then renormalise
@@ -489,17 +502,16 @@ __device__ __forceinline__ T range_at(const T* s, int n, int base, const Grid<T>
   return ri + seg;
 }
 
-// inverse range: the energy whose range is r (E_min if r <= 0)
+// inverse range: the energy whose range is r (E_min if r <= 0).  The segment
+// i with R_i <= r < R_{i+1} is found by walking from the node `hint` (the
+// node of the energy before the loss, which lies at most a few nodes away)
 template <typename T>
-__device__ __forceinline__ T range_inv(const T* s, int n, int base, T r) {
+__device__ __forceinline__ T range_inv(const T* s, int n, int base, T r, int hint) {
   if (!(r > T(0))) return s[T_ENODE * n];
   const T* rr = s + (base + O_R) * n;
-  int lo = 0, hi = n - 1;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rr[mid] <= r) lo = mid;
-    else hi = mid;
-  }
+  int lo = hint < 0 ? 0 : (hint > n - 2 ? n - 2 : hint);
+  while (lo > 0 && rr[lo] > r) --lo;
+  while (lo < n - 2 && rr[lo + 1] <= r) ++lo;
   const T ei = s[T_ENODE * n + lo];
   const T si = s[(base + O_S) * n + lo];
   const T q = s[(base + O_Q) * n + lo];
@@ -537,40 +549,35 @@ __device__ __forceinline__ T majorant(const Tab<T>& tb, const T* s, int base, in
 }
 
 // A of the soft angular law p(mu) ~ (mu + A)^-2 on [0,1] whose mean
-// A (1 + A) ln(1 + 1/A) - A equals mbar (clamped to 0.49): safeguarded
-// Newton iteration on ln A
+// A (1 + A) ln(1 + 1/A) - A equals mbar (clamped to 0.49).  Start from the
+// tabulated ln A (linear in ln mbar) or, below the table, from the small-A
+// expansion A (ln(1/A) - 1) = mbar; then a fixed number of Newton steps on
+// ln A (quadratic convergence: FP32 needs one, FP64 three).
 template <typename T>
-__device__ __forceinline__ T soft_a(T mbar) {
+__device__ __forceinline__ T soft_a(T mbar, const T* soft) {
   if (!(mbar > T(0))) return T(0);
-  if (mbar > T(0.49)) mbar = T(0.49);
-  // all iteration in FP64 for the FP64 path, FP32 otherwise
-  T lo = T(-690.0), hi = M<T>::log(T(1e6));
-  if (!is_fp64<T>()) lo = T(-87.0);
-  // initial guess from the small-A expansion A (ln(1/A) - 1) = mbar, or the
-  // large-A expansion 1/2 - 1/(6A)
+  if (mbar > T(kSoftMHi)) mbar = T(kSoftMHi);
+  const T lm = M<T>::log(mbar);
+  const T x0 = T(-20.72326583694641);  // ln 1e-9
+  const T inv_dx = T(double(kSoftN - 1) / (-0.7133498878774648 + 20.72326583694641));
   T s;
-  if (mbar < T(0.2)) {
-    const T a0 = mbar / (-M<T>::log(mbar));
-    const T a1 = mbar / (-M<T>::log(a0) - T(1));
-    s = M<T>::log(a1 > T(0) ? a1 : a0);
+  if (mbar < T(kSoftMLo)) {
+    const T a0 = mbar / (-lm);
+    s = M<T>::log(mbar / (-M<T>::log(a0) - T(1)));
   } else {
-    s = M<T>::log(T(1) / (T(6) * (T(0.5) - mbar)));
+    T x = (lm - x0) * inv_dx;
+    int j = int(x);
+    j = j < 0 ? 0 : (j > kSoftN - 2 ? kSoftN - 2 : j);
+    const T f = x - T(j);
+    s = soft[j] + f * (soft[j + 1] - soft[j]);
   }
-  const T tol = is_fp64<T>() ? T(1e-14) : T(2e-6);
-  for (int it = 0; it < 60; ++it) {
-    if (!(s > lo) || !(s < hi)) s = T(0.5) * (lo + hi);
+  const int steps = is_fp64<T>() ? 3 : 1;
+  for (int it = 0; it < steps; ++it) {
     const T A = M<T>::exp(s);
     const T L = M<T>::log1p(T(1) / A);
     const T g = A * ((T(1) + A) * L - T(1)) - mbar;
-    if (g < T(0)) lo = s;
-    else hi = s;
     const T dg = A * ((T(1) + T(2) * A) * L - T(2));  // d g / d ln A
-    T sn = (dg > T(0)) ? s - g / dg : T(0.5) * (lo + hi);
-    if (!(sn > lo) || !(sn < hi)) sn = T(0.5) * (lo + hi);
-    const T step = sn - s;
-    s = sn;
-    if (step < tol && step > -tol) break;
-    if (hi - lo < tol) break;
+    if (dg > T(0)) s -= g / dg;
   }
   return M<T>::exp(s);
 }
@@ -589,10 +596,10 @@ __device__ __forceinline__ T beta_of(T t) {
 // ---------------------------------------------------------------------------
 // LDS staging of table channels [c0, c1)
 // ---------------------------------------------------------------------------
-// channels [0, c1) of the table block into LDS
+// channels [0, c1) of the table block into LDS, plus `extra` values after them
 template <typename T>
-__device__ __forceinline__ void stage(const Tab<T>& tb, T* lds, int c1) {
-  const int total = c1 * tb.n;
+__device__ __forceinline__ void stage(const Tab<T>& tb, T* lds, int c1, int extra = 0) {
+  const int total = c1 * tb.n + extra;
   for (int k = threadIdx.x; k < total; k += blockDim.x) lds[k] = tb.t[k];
 }
 

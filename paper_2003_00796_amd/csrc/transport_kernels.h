@@ -7,6 +7,12 @@
 #include "launch.h"
 #include "transport_device.h"
 
+// minimum waves per SIMD the e+- step kernel is compiled for (bounds its
+// registers); 1 lets the compiler use as many registers as it wants
+#ifndef MCX_ESTEP_WAVES
+#define MCX_ESTEP_WAVES 1
+#endif
+
 namespace mcx {
 
 // queue roles of an iteration with parity `par`
@@ -29,7 +35,7 @@ __device__ __forceinline__ uint32_t append(const KArgs<T>& a, int q, bool pred) 
 // source: primaries for history ids [cursor, cursor + adm)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_source(KArgs<T> a, int par) {
+__global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
   const uint32_t adm = a.cnt->adm;
   const uint64_t first = a.cnt->cursor;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -91,7 +97,7 @@ __global__ void k_source(KArgs<T> a, int par) {
 // escaped photons end here, the others are sorted by interaction type
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_flight(KArgs<T> a, int par) {
+__global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
   const uint32_t n = min(a.cnt->n[q_gin(par)], a.cap);
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -120,30 +126,73 @@ __global__ void k_flight(KArgs<T> a, int par) {
       const T mt = mu[0] + mu[1] + mu[2] + mu[3];
       ls.flights++;
       double tau = double(-M<T>::log(uni<T>(p.rng)) / mt);
-      bool escaped = false;
-      for (;;) {
-        int ax;
-        const double s = face_dist(a, p, &ax);
-        const uint32_t v = vlin(a, p.ix);
-        if (ax < 0) {
-          atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
-          escaped = true;
-          break;
+      // incremental DDA: tn[k] = distance along the ray to the next face
+      // normal to axis k, advanced by the voxel pitch over |d_k| per crossing
+      const double o[3] = {a.ox, a.oy, a.oz};
+      const double dd[3] = {a.dx, a.dy, a.dz};
+      const int nn[3] = {a.nx, a.ny, a.nz};
+      double tn[3], dt[3];
+      int stp[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double dk = double(p.d[k]);
+        if (dk > 0.0) {
+          stp[k] = 1;
+          tn[k] = (o[k] + double(p.ix[k] + 1) * dd[k] - p.x[k]) / dk;
+          dt[k] = dd[k] / dk;
+        } else if (dk < 0.0) {
+          stp[k] = -1;
+          tn[k] = (o[k] + double(p.ix[k]) * dd[k] - p.x[k]) / dk;
+          dt[k] = -dd[k] / dk;
+        } else {
+          stp[k] = 0;
+          tn[k] = __builtin_huge_val();
+          dt[k] = 0.0;
         }
+        if (tn[k] < 0.0) tn[k] = 0.0;
+      }
+      if (!(tn[0] < __builtin_huge_val()) && !(tn[1] < __builtin_huge_val()) &&
+          !(tn[2] < __builtin_huge_val())) {
+        atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+        tau = 0.0;
+      }
+      double t = 0.0;
+      bool escaped = false;
+      uint32_t v = vlin(a, p.ix);
+      double t0 = tn[0], t1 = tn[1], t2 = tn[2];
+      for (;;) {
+        const int ax = (t0 <= t1 && t0 <= t2) ? 0 : (t1 <= t2 ? 1 : 2);
+        const double tf = ax == 0 ? t0 : (ax == 1 ? t1 : t2);
+        const double s = tf - t;
         const double rho = double(a.rho[v]);
         if (rho * s >= tau) {
-          move(p, tau / rho);
+          t += tau / rho;
           break;
         }
         tau -= rho * s;
-        if (cross(a, p, s, ax, ls)) {
+        t = tf;
+        bool out = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (k == ax) {
+            p.ix[k] += stp[k];
+            out = p.ix[k] < 0 || p.ix[k] >= nn[k];
+          }
+        }
+        if (ax == 0) t0 += dt[0];
+        else if (ax == 1) t1 += dt[1];
+        else t2 += dt[2];
+        ls.crossings++;
+        if (out) {
           ledger_escape(a, &bs, p);
           event(a, p, EV_PH_ESCAPE, v);
           finish(a, p);
           escaped = true;
           break;
         }
+        v = vlin(a, p.ix);
       }
+      move(p, t);
       if (!escaped) {
         const T u = uni<T>(p.rng) * mt;
         T cum = T(0);
@@ -152,9 +201,11 @@ __global__ void k_flight(KArgs<T> a, int par) {
           cum += mu[k];
           if (ch < 0 && u < cum) ch = k;
         }
-        if (ch < 0)
+        if (ch < 0) {
+#pragma unroll
           for (int k = 3; k >= 0; --k)
             if (ch < 0 && mu[k] > T(0)) ch = k;
+        }
       }
     }
 #pragma unroll
@@ -225,7 +276,7 @@ __device__ __forceinline__ void make_child(const KArgs<T>& a, Part<T>& p, Child<
 }
 
 template <typename T>
-__global__ void k_knock(KArgs<T> a, int par) {
+__global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
   Counters* C = a.cnt;
   const uint32_t n0 = min(C->n[Q_KC], a.cap), n1 = min(C->n[Q_KP], a.cap);
   const uint32_t n2 = min(C->n[Q_KR], a.cap), n3 = min(C->n[Q_KX], a.cap);
@@ -382,7 +433,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const T ss = interp(tab, nt, base + O_LS, g, e, T(0));
   const T tau_max = a.c2 * e / ss;
   const T r0 = range_at(tab, nt, base, g, e);
-  T elo = r0 - tau_max > T(0) ? range_inv(tab, nt, base, r0 - tau_max) : tb.emin;
+  T elo = r0 - tau_max > T(0) ? range_inv(tab, nt, base, r0 - tau_max, g.i) : tb.emin;
   if (elo > e) elo = e;
   const T smaj = majorant(tb, tab, base, lep, elo, g, e);
   const T u1 = uni<T>(p.rng);
@@ -399,7 +450,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   }
   if (db <= th) {
     // the face comes first: soft loss over db, cross, start a new step
-    T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * db)));
+    T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * db)), g.i);
     if (!(e1 < e)) e1 = e;
     deposit(a, acc, ls, p, e - e1);
     p.e = e1;
@@ -412,7 +463,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   }
   // hinge: the soft energy loss of the whole step is charged here
   move(p, th);
-  T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * len)));
+  T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * len)), g.i);
   if (!(e1 < e)) e1 = e;
   deposit(a, acc, ls, p, e - e1);
   p.e = e1;
@@ -422,7 +473,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   }
   const T t1s = interp(tab, nt, base + O_LT1S, g, e, T(0));
   const T mbar = T(0.5) * (T(1) - M<T>::exp(-T(double(rho) * len) * t1s));
-  const T A = soft_a(mbar);
+  const T A = soft_a(mbar, tab + T_NCH * nt);
   const T u3 = uni<T>(p.rng);
   const T mu = A * u3 / (T(1) + A - u3);
   const T phi = T(2.0 * kPi) * uni<T>(p.rng);
@@ -521,8 +572,11 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   return true;
 }
 
+// The e+- kernel keeps its lanes busy: a lane whose particle is gone (or has
+// used its step budget and is written back to the output queue) takes the
+// next record of the input queue, until the queue is exhausted.
 template <typename T>
-__global__ void k_estep(KArgs<T> a, int par) {
+__global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a, int par) {
   const uint32_t n = min(a.cnt->n[q_ein(par)], a.cap);
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -530,41 +584,53 @@ __global__ void k_estep(KArgs<T> a, int par) {
   __shared__ BlockStats bs;
   LaneStats ls;
   stats_init(&bs, ls);
-  stage(a.tb, tab, T_NCH);
+  stage(a.tb, tab, T_NCH, kSoftN);
   __syncthreads();
   const Bank<T>& in = a.q[q_ein(par)];
   const int ge = q_eout(par), gg = q_gout(par);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-    const uint32_t i = base + threadIdx.x;
-    bool alive = i < n;
-    Part<T> p;
-    DepAcc acc{kEmptyKey, 0.0};
+  Part<T> p;
+  DepAcc acc{kEmptyKey, 0.0};
+  bool alive = false, taking = true;
+  uint32_t used = 0;
+  for (;;) {
+    // lanes without a particle take the next input records (one atomic per wave)
+    if (taking) {
+      const bool need = !alive;
+      const uint32_t idx = wave_append(&a.cnt->take_e, need);
+      const uint32_t first = __shfl(idx, int(__ffsll((unsigned long long)__ballot(need)) - 1));
+      if (__ballot(need) != 0ull && first >= n) taking = false;  // wave-uniform
+      if (need && idx < n) {
+        load_part(a, in, idx, p);
+        alive = true;
+        used = 0;
+        ls.visits++;
+      }
+    }
+    if (!__any(alive)) break;
+    Child<T> c1, c2;
+    c1.on = false;
+    c2.on = false;
     if (alive) {
-      load_part(a, in, i, p);
-      ls.visits++;
+      alive = e_step(a, tab, p, c1, c2, acc, ls, &bs);
+      ++used;
     }
-    for (uint32_t s = 0; s < a.steps; ++s) {
-      Child<T> c1, c2;
-      c1.on = false;
-      c2.on = false;
-      if (alive) alive = e_step(a, tab, p, c1, c2, acc, ls, &bs);
-      // secondaries of this step, wavefront-aggregated
-      const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
-      const uint32_t se = append(a, ge, c1e);
-      if (c1e && se != ~0u) store_child(a, a.q[ge], se, p, c1);
-      const uint32_t sg = append(a, gg, c1g);
-      if (c1g && sg != ~0u) store_child(a, a.q[gg], sg, p, c1);
-      const uint32_t s2 = append(a, gg, c2.on);
-      if (c2.on && s2 != ~0u) store_child(a, a.q[gg], s2, p, c2);
-      ls.writes += uint32_t(c1.on) + uint32_t(c2.on);
-      if (!__any(alive)) break;
-    }
-    dep_flush(a, acc, ls);
-    const uint32_t so = append(a, ge, alive);
-    if (alive && so != ~0u) store_part(a, a.q[ge], so, p);
-    ls.writes += uint32_t(alive);
+    // secondaries of this step, wavefront-aggregated
+    const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
+    const uint32_t se = append(a, ge, c1e);
+    if (c1e && se != ~0u) store_child(a, a.q[ge], se, p, c1);
+    const uint32_t sg = append(a, gg, c1g);
+    if (c1g && sg != ~0u) store_child(a, a.q[gg], sg, p, c1);
+    const uint32_t s2 = append(a, gg, c2.on);
+    if (c2.on && s2 != ~0u) store_child(a, a.q[gg], s2, p, c2);
+    ls.writes += uint32_t(c1.on) + uint32_t(c2.on);
+    // a particle that used its budget goes back to the output queue
+    const bool park = alive && used >= a.steps;
+    const uint32_t so = append(a, ge, park);
+    if (park && so != ~0u) store_part(a, a.q[ge], so, p);
+    ls.writes += uint32_t(park);
+    if (park) alive = false;
   }
+  dep_flush(a, acc, ls);
   stats_flush(&bs, ls, a.cnt);
 }
 
@@ -579,6 +645,7 @@ __global__ void k_advance(Counters* c, int par, uint32_t target, uint32_t cap) {
   c->n[Q_G0 + par] = 0u;
   c->n[Q_E0 + par] = 0u;
   c->n[Q_KC] = c->n[Q_KP] = c->n[Q_KR] = c->n[Q_KX] = 0u;
+  c->take_e = 0u;
   c->cursor += c->adm;
   const uint32_t pop = c->n[Q_G0 + 1 - par] + c->n[Q_E0 + 1 - par];
   const uint64_t rem = c->chunk_end - c->cursor;
@@ -602,6 +669,8 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   c->run_first = run_first;
   c->adm = adm;
   c->occupied = 0ull;
+  c->n_occ = 0ull;
+  c->take_e = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -609,13 +678,13 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
 // Sum q^2 += q^2 (Eq. (1)-(3)); slots are cleared for the next chunk
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2,
-                        Counters* cnt, int test_mode, double* hist_led, uint64_t n_run) {
+__global__ void k_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, uint64_t nslot, double* sum_q,
+                        double* sum_q2, Counters* cnt, int test_mode, double* hist_led, uint64_t n_run) {
+  const uint64_t n = min(cnt->n_occ, nslot);
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  uint32_t occ = 0;
-  for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint64_t s = occ_list[i];
     const uint64_t k = keys[s];
-    if (k == kEmptyKey) continue;
     const double q = vals[s];
     const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
     unsafeAtomicAdd(&sum_q[v], q);
@@ -626,10 +695,8 @@ __global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* su
     }
     keys[s] = kEmptyKey;
     vals[s] = 0.0;
-    ++occ;
   }
-  occ = wave_sum(occ);
-  if (__lane_id() == 0 && occ) atomicAdd((unsigned long long*)&cnt->occupied, (unsigned long long)occ);
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->occupied = n;
 }
 
 // dose (eV/g per history) and its standard error, Eq. (1)-(3)
