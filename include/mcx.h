@@ -144,6 +144,8 @@ typedef struct {
    * iterations timed (each iteration launches each kernel once) */
   double ms_source, ms_flight, ms_knock, ms_estep;
   uint64_t timed_iterations;
+  /* host wall time of the two density-gradient replays */
+  double ms_backward;
 } mcx_stats;
 
 /* Create a context on HIP device `hip_device` computing in `precision`
@@ -183,6 +185,23 @@ int mcx_set_test_mode(mcx_ctx* ctx, int on);
  * (seed, history range).  first_hist + n_hist must not exceed the total of
  * the sources nor 2^32. */
 int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, void* stream);
+
+/* Gradient of a dose loss with respect to every voxel density.  dl_ddose
+ * holds dL/dD_v (D in eV/g per history, as from mcx_get_dose); dl_drho
+ * receives dL/drho_v (nx*ny*nz doubles each; device arrays if on_device,
+ * else host).  The histories of the last mcx_run are replayed twice from
+ * their random-number counters (no tracks are stored): the first replay forms
+ * each history's weighted score Q_h = sum_v w_v q_hv with
+ * w_v = dL/dD_v * 1e6 / (rho_v V) and the local derivative of the soft energy
+ * loss of electron/positron steps stopped by a voxel face; the second adds
+ * (Q_h - mean Q) times the likelihood-ratio score of every photon free flight
+ * (-mu l_j per traversed voxel, +1/rho at the interaction).  The explicit
+ * mass term -dL/dD_v D_v / rho_v completes the gradient.  Unbiased when
+ * electrons are absorbed where they are created; with Class II transport the
+ * downstream effect of density on electron tracks is not included.  Requires
+ * that the tallies hold exactly one mcx_run since the last reset
+ * (MCX_E_STATE otherwise).  The tallies and statistics are unchanged. */
+int mcx_dose_backward(mcx_ctx* ctx, const double* dl_ddose, double* dl_drho, int on_device, void* stream);
 
 /* Dose (eV/g per history) and its standard error per voxel from the
  * accumulated counters, Eq. (1)-(3).  dose and sigma are caller-owned arrays

@@ -128,6 +128,10 @@ def lib():
                               C.POINTER(Source), C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
                               dp, dp, C.POINTER(Stats), C.POINTER(C.c_uint64), dp]
         L.orc_dose.argtypes = [C.POINTER(Phantom), C.c_uint64, dp, dp, dp, dp]
+        L.orc_run_gradient.restype = C.c_int
+        L.orc_run_gradient.argtypes = [C.c_void_p, C.POINTER(Transport), C.POINTER(Phantom),
+                                       C.POINTER(Source), C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
+                                       dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -287,3 +291,26 @@ def dose(phantom: dict, result: RunResult, n_hist: int | None = None):
     lib().orc_dose(C.byref(ph), n_hist or result.n, _dp(result.sum_q), _dp(result.sum_q2), _dp(d), _dp(s))
     shape = tuple(phantom["shape"])
     return d.reshape(shape), s.reshape(shape)
+
+
+def gradient(tables: Tables, phantom: dict, sources, seed: int, first: int, n: int, dl_ddose: np.ndarray,
+             dose: np.ndarray):
+    """Score-function estimate of dL/drho for L with dL/dD = dl_ddose (shape of
+    the phantom), given the dose D of the same histories (eV/g per history).
+    Returns (grad, parts) with parts = dict(a, b, p, qbar) of oracle.h."""
+    ph, rho = phantom_struct(phantom)
+    vol = phantom["voxel"][0] * phantom["voxel"][1] * phantom["voxel"][2]
+    g = np.ascontiguousarray(dl_ddose, dtype=np.float64).ravel()
+    w = g * 1e6 / (rho * vol)
+    a = np.zeros(rho.size)
+    b = np.zeros(rho.size)
+    p = np.zeros(rho.size)
+    sq = C.c_double(0.0)
+    src = source_array(sources)
+    rc = lib().orc_run_gradient(tables.h, C.byref(tables.t), C.byref(ph), src, len(sources), seed, first, n,
+                                _dp(w), _dp(a), _dp(b), _dp(p), C.byref(sq))
+    if rc:
+        raise RuntimeError(f"orc_run_gradient failed: {rc}")
+    qbar = sq.value / n
+    grad = (a - qbar * b + p) / n - g * np.asarray(dose, dtype=np.float64).ravel() / rho
+    return grad.reshape(tuple(phantom["shape"])), dict(a=a, b=b, p=p, qbar=qbar)

@@ -512,6 +512,14 @@ typedef struct {
   orc_stats* st;
   double led[ORC_LED_N];
   uint64_t hist_hash;
+  /* gradient (score-function) accumulation, NULL when off */
+  const double* w;
+  double q_h;           /* sum_v w_v q_hv of the current history */
+  double* s_tmp;        /* per-history score S_hj, valid where s_mark == cur */
+  uint64_t* s_mark;
+  int64_t* s_touched;
+  int64_t n_s_touched;
+  double* p_acc;
 } ctx;
 
 static int64_t lin(const ctx* c, const int ix[3]) {
@@ -588,6 +596,17 @@ static void deposit(ctx* c, const part* p, double e) {
   c->tmp[v] += e;
   c->led[ORC_LED_DEP] += e;
   c->st->deposits++;
+  if (c->w) c->q_h += c->w[v] * e;
+}
+
+/* score of voxel v for the current history (gradient mode only) */
+static void score(ctx* c, int64_t v, double s) {
+  if (c->s_mark[v] != c->cur) {
+    c->s_mark[v] = c->cur;
+    c->s_tmp[v] = 0.0;
+    c->s_touched[c->n_s_touched++] = v;
+  }
+  c->s_tmp[v] += s;
 }
 
 /* event codes folded into the particle hash */
@@ -761,9 +780,12 @@ static void photon_track(ctx* c, part* p) {
       double s = face(c, p, &a);
       double rho = c->ph->rho[lin(c, p->ix)];
       if (rho * s >= tau) {
+        /* the flight ends inside this voxel: d ln p / d rho = -mu l + 1/rho */
+        if (c->w) score(c, lin(c, p->ix), -mt * (tau / rho) + 1.0 / rho);
         move(p, tau / rho);
         break;
       }
+      if (c->w) score(c, lin(c, p->ix), -mt * s);
       tau -= rho * s;
       int64_t v = lin(c, p->ix);
       if (cross(c, p, s, a)) {
@@ -929,6 +951,8 @@ static void electron_track(ctx* c, part* p) {
       if (!(e1 < e)) e1 = e;
       deposit(c, p, e - e1);
       c->led[ORC_LED_PATH] += rho * db;
+      /* loss over the geometric length db: d(E - E')/d rho = db S_soft(E') */
+      if (c->w && e1 < e) c->p_acc[v] += c->w[v] * db * interp(tb, tb->el[ti][CH_S], 0.0, e1);
       p->e = e1;
       event(c, p, EV_CROSS, v);
       if (cross(c, p, db, a)) { e_escape(c, p, v); return; }
@@ -989,10 +1013,11 @@ static int locate(const ctx* c, part* p) {
   return 0;
 }
 
-int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
-            const orc_source* src, int n_src, uint32_t seed, uint64_t first,
-            uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
-            uint64_t* hashes, double* ledger) {
+static int run_body(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
+                    const orc_source* src, int n_src, uint32_t seed, uint64_t first,
+                    uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
+                    uint64_t* hashes, double* ledger, const double* w, double* a_acc,
+                    double* b_acc, double* p_acc, double* sum_q_h) {
   if (!tb || !t || !ph || !src || n_src <= 0 || !sum_q || !sum_q2 || !stats) return -1;
   uint64_t total = 0;
   for (int s = 0; s < n_src; ++s) total += src[s].n_hist;
@@ -1011,6 +1036,14 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
   c.touched = (int64_t*)malloc(sizeof(int64_t) * (size_t)nv);
   for (int64_t v = 0; v < nv; ++v) c.mark[v] = ~0ull;
   c.st = stats;
+  if (w) {
+    c.w = w;
+    c.p_acc = p_acc;
+    c.s_tmp = (double*)calloc((size_t)nv, sizeof(double));
+    c.s_mark = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nv);
+    c.s_touched = (int64_t*)malloc(sizeof(int64_t) * (size_t)nv);
+    for (int64_t v = 0; v < nv; ++v) c.s_mark[v] = ~0ull;
+  }
   int rc = 0;
   for (uint64_t i = 0; i < n; ++i) {
     uint64_t h = first + i;
@@ -1035,6 +1068,8 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
     if (locate(&c, &p)) { rc = -3; break; }
     c.cur = h;
     c.n_touched = 0;
+    c.n_s_touched = 0;
+    c.q_h = 0.0;
     memset(c.led, 0, sizeof(c.led));
     c.hist_hash = 0;
     push(&c, &p);
@@ -1050,6 +1085,15 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
       sum_q[v] += q;
       sum_q2[v] += q * q;
     }
+    if (w) {
+      /* score-function estimator: Q_h times the history's score */
+      for (int64_t j = 0; j < c.n_s_touched; ++j) {
+        int64_t v = c.s_touched[j];
+        a_acc[v] += c.q_h * c.s_tmp[v];
+        b_acc[v] += c.s_tmp[v];
+      }
+      *sum_q_h += c.q_h;
+    }
     stats->histories++;
     stats->e_dep += c.led[ORC_LED_DEP];
     stats->e_esc += c.led[ORC_LED_ESC];
@@ -1061,6 +1105,34 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
   free(c.mark);
   free(c.touched);
   free(c.stack);
+  free(c.s_tmp);
+  free(c.s_mark);
+  free(c.s_touched);
+  return rc;
+}
+
+int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
+            const orc_source* src, int n_src, uint32_t seed, uint64_t first,
+            uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
+            uint64_t* hashes, double* ledger) {
+  return run_body(tb, t, ph, src, n_src, seed, first, n, sum_q, sum_q2, stats, hashes, ledger,
+                  NULL, NULL, NULL, NULL, NULL);
+}
+
+int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
+                     const orc_source* src, int n_src, uint32_t seed, uint64_t first,
+                     uint64_t n, const double* w, double* a_acc, double* b_acc,
+                     double* p_acc, double* sum_q_h) {
+  if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
+  int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
+  double* q = (double*)calloc((size_t)nv, sizeof(double));
+  double* q2 = (double*)calloc((size_t)nv, sizeof(double));
+  orc_stats st;
+  memset(&st, 0, sizeof(st));
+  int rc = run_body(tb, t, ph, src, n_src, seed, first, n, q, q2, &st, NULL, NULL, w, a_acc, b_acc,
+                    p_acc, sum_q_h);
+  free(q);
+  free(q2);
   return rc;
 }
 

@@ -159,6 +159,22 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
             uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
             uint64_t* hashes, double* ledger);
 
+/* Density gradient of a dose loss by the score-function (likelihood-ratio)
+ * estimator, one history at a time.  w[v] = (dL/dD_v) * 1e6 / (rho_v V) is
+ * the loss weight per MeV deposited in voxel v.  Per history h:
+ *   Q_h   = sum_v w_v q_hv                       (weighted score of the history)
+ *   S_hj  = sum over photon free flights of -mu * l_j (length in voxel j),
+ *           + 1/rho_k for the voxel k where a flight ends in an interaction
+ *   P_hj  = sum over electron/positron steps stopped by a face of voxel j of
+ *           w_j * l * S_soft(E')  (local derivative of the soft loss)
+ * Accumulated: A_j += Q_h S_hj, B_j += S_hj, P_j += P_hj, *sum_q_h += Q_h.
+ * The gradient of E[L] is (A_j - Qbar B_j + P_j)/N - (dL/dD_j) D_j / rho_j,
+ * Qbar = sum_q_h / N.  Exact when electrons deposit where they are created. */
+int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
+                     const orc_source* src, int n_src, uint32_t seed, uint64_t first,
+                     uint64_t n, const double* w, double* a_acc, double* b_acc,
+                     double* p_acc, double* sum_q_h);
+
 /* Dose (eV/g per history) and its standard error from the counters,
  * Eq. (1)-(3) with the square root of Eq. (2) restored. */
 void orc_dose(const orc_phantom* ph, uint64_t n_hist, const double* sum_q,

@@ -31,7 +31,7 @@ ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM"
 ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport", "mcx_load_material",
                "mcx_load_phantom", "mcx_set_sources", "mcx_set_launch", "mcx_set_timing", "mcx_set_test_mode", "mcx_run",
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
-               "mcx_get_history_results")
+               "mcx_get_history_results", "mcx_dose_backward")
 
 
 class MaterialDesc(C.Structure):
@@ -67,7 +67,7 @@ class Stats(C.Structure):
         ("chunks", C.c_uint64), ("tally_pairs", C.c_uint64), ("ms_transport", C.c_double),
         ("ms_flush", C.c_double), ("evisits", C.c_uint64), ("ewrites", C.c_uint64), ("inserts", C.c_uint64),
         ("ms_source", C.c_double), ("ms_flight", C.c_double), ("ms_knock", C.c_double), ("ms_estep", C.c_double),
-        ("timed_iterations", C.c_uint64)]
+        ("timed_iterations", C.c_uint64), ("ms_backward", C.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -84,6 +84,13 @@ def lib():
     """Load libmcx.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 with
+        # the same soname, so load it first and libmcx binds to that copy
+        # (loading the system runtime first leaves PyTorch without a device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise MCXError(f"{LIB_PATH} is missing: build the HIP library first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
@@ -107,6 +114,7 @@ def lib():
         L.mcx_reset_tallies.argtypes = [vp]
         L.mcx_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.mcx_get_history_results.argtypes = [vp, vp, vp]
+        L.mcx_dose_backward.argtypes = [vp, vp, vp, C.c_int, vp]
         for f in ABI_SYMBOLS:
             if f not in ("mcx_destroy", "mcx_last_error"):
                 getattr(L, f).restype = C.c_int
@@ -253,8 +261,88 @@ class Simulator:
         self._check(self._L.mcx_get_stats(self._h, C.byref(s)), "get_stats")
         return s.as_dict()
 
+    def dose_backward(self, dl_ddose: np.ndarray) -> np.ndarray:
+        """dL/drho for dL/dD = dl_ddose (host arrays of the phantom shape)."""
+        g = np.ascontiguousarray(dl_ddose, dtype=np.float64)
+        out = np.zeros_like(g)
+        self._check(self._L.mcx_dose_backward(self._h, _ptr(g), _ptr(out), 0, None), "dose_backward")
+        return out
+
+    def dose_backward_into(self, dl_ddose_t, out_t, stream=None):
+        """Device variant: float64 contiguous tensors."""
+        sp = C.c_void_p(stream) if stream else None
+        self._check(self._L.mcx_dose_backward(self._h, C.c_void_p(dl_ddose_t.data_ptr()),
+                                               C.c_void_p(out_t.data_ptr()), 1, sp), "dose_backward")
+
     def history_results(self, n: int):
         h = np.zeros(n, dtype=np.uint64)
         led = np.zeros((n, 3))
         self._check(self._L.mcx_get_history_results(self._h, _ptr(h), _ptr(led)), "get_history_results")
         return h, led
+
+
+class DoseModel:
+    """A fixed transport problem whose voxel densities are the input: the dose
+    it produces is differentiable through DoseFunction."""
+
+    def __init__(self, workload: dict, n_hist: int, seed: int = 1, precision: int = FP64, device: int = 0):
+        self.sim = Simulator(precision, device)
+        self.sim.set_transport(workload["transport"])
+        self.sim.load_material(workload["material"])
+        self.workload = workload
+        self.n_hist = int(n_hist)
+        self.seed = int(seed)
+        self._sources_set = False
+
+    def forward(self, rho):
+        import torch
+        ph = dict(self.workload["phantom"], rho=rho.detach())
+        self.sim.load_phantom(ph)
+        if not self._sources_set:
+            self.sim.set_sources(self.workload["sources"])
+            self._sources_set = True
+        stream = torch.cuda.current_stream(rho.device).cuda_stream
+        self.sim.run(self.seed, 0, self.n_hist, stream)
+        dose = torch.empty(self.sim.shape, dtype=torch.float64, device=rho.device)
+        self.dose_sigma = torch.empty_like(dose)
+        self.sim.dose_into(dose, self.dose_sigma, stream)
+        return dose
+
+    def backward(self, grad_dose):
+        import torch
+        g = grad_dose.contiguous().double()
+        out = torch.empty_like(g)
+        self.sim.dose_backward_into(g, out, torch.cuda.current_stream(g.device).cuda_stream)
+        return out
+
+
+def _dose_function():
+    import torch
+
+    class DoseFunction(torch.autograd.Function):
+        """dose = DoseFunction.apply(rho, model): Monte-Carlo dose (eV/g per
+        history) of `model` with voxel densities rho (float64 CUDA tensor of
+        the phantom shape); backward replays the histories on the GPU."""
+
+        @staticmethod
+        def forward(ctx, rho, model):
+            ctx.model = model
+            return model.forward(rho)
+
+        @staticmethod
+        def backward(ctx, grad_dose):
+            return ctx.model.backward(grad_dose), None
+
+    return DoseFunction
+
+
+_DOSE_FUNCTION = None
+
+
+def __getattr__(name):
+    global _DOSE_FUNCTION
+    if name == "DoseFunction":
+        if _DOSE_FUNCTION is None:
+            _DOSE_FUNCTION = _dose_function()
+        return _DOSE_FUNCTION
+    raise AttributeError(name)

@@ -56,4 +56,23 @@ hipError_t configure_fp64(int n_grid) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+hipError_t launch_adjoint_weights(const double* dl_ddose, const double* rho, uint64_t nvox, double vol, double* w,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_weights<double>, dim3(2048), dim3(256), 0, s, dl_ddose, rho, nvox, vol, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddose, const double* sum_q,
+                                   const double* rho, uint64_t nvox, double vol, double nhist, double* out,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_finalize<double>, dim3(2048), dim3(256), 0, s, grad_acc, dl_ddose, sum_q, rho, nvox, vol,
+                     nhist, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* q, uint64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_sum<double>, dim3(1024), dim3(256), 0, s, q, n, out);
+  return hipGetLastError();
+}
+
 }  // namespace mcx

@@ -41,4 +41,18 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+hipError_t launch_adjoint_weights(const double* dl_ddose, const float* rho, uint64_t nvox, double vol, double* w,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_weights<float>, dim3(2048), dim3(256), 0, s, dl_ddose, rho, nvox, vol, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddose, const double* sum_q,
+                                   const float* rho, uint64_t nvox, double vol, double nhist, double* out,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_finalize<float>, dim3(2048), dim3(256), 0, s, grad_acc, dl_ddose, sum_q, rho, nvox, vol,
+                     nhist, out);
+  return hipGetLastError();
+}
+
 }  // namespace mcx

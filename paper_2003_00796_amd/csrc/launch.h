@@ -24,6 +24,18 @@ hipError_t launch_dose(const double* sum_q, const double* sum_q2, const double* 
                        double nhist, double* dose, double* sigma, hipStream_t s);
 hipError_t launch_dose(const double* sum_q, const double* sum_q2, const float* rho, uint64_t nvox, double vol,
                        double nhist, double* dose, double* sigma, hipStream_t s);
+// density gradient helpers
+hipError_t launch_adjoint_weights(const double* dl_ddose, const double* rho, uint64_t nvox, double vol, double* w,
+                                  hipStream_t s);
+hipError_t launch_adjoint_weights(const double* dl_ddose, const float* rho, uint64_t nvox, double vol, double* w,
+                                  hipStream_t s);
+hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddose, const double* sum_q,
+                                   const double* rho, uint64_t nvox, double vol, double nhist, double* out,
+                                   hipStream_t s);
+hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddose, const double* sum_q,
+                                   const float* rho, uint64_t nvox, double vol, double nhist, double* out,
+                                   hipStream_t s);
+hipError_t launch_sum(const double* q, uint64_t n, double* out, hipStream_t s);
 // LDS bytes the e+- kernel stages for a grid of n nodes
 size_t estep_lds_bytes(int n, bool fp64);
 hipError_t configure_kernels(int n_grid, bool fp64);

@@ -146,6 +146,14 @@ struct KArgs {
   int test_mode;
   uint64_t* hist_hash;
   double* hist_led;      // 3 per history: deposited, escaped, positrons escaped
+  // density gradient by replay (0: forward tally; 1: replay A accumulates
+  // each history's weighted score Q_h and the local soft-loss derivative;
+  // 2: replay B scatters (Q_h - Qbar) times the photon free-flight scores)
+  int mode;
+  const double* adj_w;   // per voxel: dL/dD_v * 1e6 / (rho_v V)
+  double* adj_q;         // per history of the run: Q_h
+  double* adj_grad;      // per voxel accumulator
+  double adj_qbar;       // mean Q_h (replay B)
   Counters* cnt;
   Bank<T> q[Q_NQ];
   uint32_t cap;          // records per queue

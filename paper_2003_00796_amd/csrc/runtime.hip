@@ -66,6 +66,12 @@ struct mcx_ctx {
   DevBuf d_hhash, d_hled;
   uint64_t last_n = 0;
   bool last_valid = false;
+  // the last run, for the density-gradient replays
+  uint32_t run_seed = 0;
+  uint64_t run_first = 0, run_n = 0;
+  bool run_known = false;
+  DevBuf d_adj_w, d_adj_q, d_adj_grad, d_adj_dl, d_adj_out, d_adj_sum;
+  double ms_backward = 0.0;
   // stats
   uint64_t iterations = 0, chunks = 0, tally_pairs = 0;
   double ms_transport = 0.0, ms_flush = 0.0;
@@ -190,7 +196,7 @@ int ensure_workspace(mcx_ctx* c) {
 }
 
 template <typename T>
-void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed) {
+void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar = 0.0) {
   std::memset(&a, 0, sizeof(a));
   const BuiltTables& b = c->tabs;
   a.tb.t = static_cast<const T*>(c->d_tab.p);
@@ -230,12 +236,21 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed) {
   carve_banks(c, a);
   a.cap = c->cap;
   a.steps = c->steps;
+  a.mode = mode;
+  if (mode) {
+    a.test_mode = 0;
+    a.adj_w = static_cast<const double*>(c->d_adj_w.p);
+    a.adj_q = static_cast<double*>(c->d_adj_q.p);
+    a.adj_grad = static_cast<double*>(c->d_adj_grad.p);
+    a.adj_qbar = qbar;
+  }
 }
 
 template <typename T>
-int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t s) {
+int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t s, int mode = 0,
+             double qbar = 0.0) {
   KArgs<T> a;
-  fill_args(c, a, seed);
+  fill_args(c, a, seed, mode, qbar);
   const uint32_t target = c->cap / 4;
   int grid = int((std::min<uint64_t>(c->cap, 2ull * target) + c->block - 1) / c->block);
   grid = std::max(grid, 1);
@@ -282,6 +297,10 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       if (c->h_cnt->overflow & OVF_LOST) return fail(c, MCX_E_DEVICE, "a particle lost its direction (no exit face)");
       if (c->h_cnt->done) break;
     }
+    if (mode != 0) {  // replays leave the tally table untouched
+      done += chunk;
+      continue;
+    }
     auto tf = std::chrono::steady_clock::now();
     e = launch_flush(a.hkeys, a.hvals, a.occ_list, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
@@ -297,6 +316,10 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
     done += chunk;
   }
   const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (mode != 0) {
+    c->ms_backward += total_ms;
+    return MCX_OK;
+  }
   c->ms_transport += total_ms - flush_ms;
   c->ms_flush += flush_ms;
   return MCX_OK;
@@ -334,7 +357,8 @@ void mcx_destroy(mcx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
-                    &c->d_hvals, &c->d_occ, &c->d_hhash, &c->d_hled})
+                    &c->d_hvals, &c->d_occ, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad, &c->d_adj_dl, &c->d_adj_out,
+                    &c->d_adj_sum, &c->d_hhash, &c->d_hled})
     dfree(*b);
   if (c->h_cnt) (void)hipHostFree(c->h_cnt);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -403,9 +427,11 @@ int mcx_reset_tallies(mcx_ctx* c) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reset tallies");
   c->n_done = 0;
+  c->run_known = false;
   c->iterations = c->chunks = c->tally_pairs = 0;
   c->ms_transport = c->ms_flush = 0.0;
   for (double& m : c->ms_kernel) m = 0.0;
+  c->ms_backward = 0.0;
   c->timed_iterations = 0;
   return MCX_OK;
 }
@@ -575,8 +601,85 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
   if (rc) return rc;
   c->table_dirty = false;
   c->n_done += n;
+  c->run_seed = uint32_t(seed);
+  c->run_first = first;
+  c->run_n = n;
+  c->run_known = c->n_done == n;
   c->last_n = n;
   c->last_valid = c->test_mode != 0;
+  return MCX_OK;
+}
+
+int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int on_device, void* stream) {
+  if (!c) return MCX_E_INVALID;
+  if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
+  if (!c->run_known)
+    return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const uint64_t nv = nvox(c), n = c->run_n;
+  int rc;
+  if ((rc = dalloc(c, c->d_adj_w, nv * sizeof(double), "gradient weights")) ||
+      (rc = dalloc(c, c->d_adj_grad, nv * sizeof(double), "gradient accumulator")) ||
+      (rc = dalloc(c, c->d_adj_q, n * sizeof(double), "history scores")) ||
+      (rc = dalloc(c, c->d_adj_sum, sizeof(double), "score sum")))
+    return rc;
+  const double* dl = dl_ddose;
+  double* out = dl_drho;
+  if (!on_device) {
+    if ((rc = dalloc(c, c->d_adj_dl, nv * sizeof(double), "loss gradient")) ||
+        (rc = dalloc(c, c->d_adj_out, nv * sizeof(double), "density gradient")))
+      return rc;
+    hipError_t e = hipMemcpyAsync(c->d_adj_dl.p, dl_ddose, nv * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "copy loss gradient");
+    dl = static_cast<const double*>(c->d_adj_dl.p);
+    out = static_cast<double*>(c->d_adj_out.p);
+  }
+  // the statistics describe the forward run: keep them across the replays
+  Counters saved;
+  hipError_t e = hipMemcpyAsync(&saved, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "save statistics");
+  const uint64_t iters = c->iterations, chunks = c->chunks;
+  const double vol = c->vox[0] * c->vox[1] * c->vox[2];
+  e = fp64(c) ? launch_adjoint_weights(dl, static_cast<const double*>(c->d_rho.p), nv, vol,
+                                       static_cast<double*>(c->d_adj_w.p), s)
+              : launch_adjoint_weights(dl, static_cast<const float*>(c->d_rho.p), nv, vol,
+                                       static_cast<double*>(c->d_adj_w.p), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_adj_grad.p, 0, nv * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_adj_q.p, 0, n * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_adj_sum.p, 0, sizeof(double), s);
+  if (e != hipSuccess) return hip_fail(c, e, "prepare gradient");
+  const int test = c->test_mode;
+  c->test_mode = 0;
+  // replay A: Q_h per history and the local soft-loss derivative
+  rc = fp64(c) ? run_impl<double>(c, c->run_seed, c->run_first, n, s, 1)
+               : run_impl<float>(c, c->run_seed, c->run_first, n, s, 1);
+  double qsum = 0.0;
+  if (!rc) {
+    e = launch_sum(static_cast<const double*>(c->d_adj_q.p), n, static_cast<double*>(c->d_adj_sum.p), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&qsum, c->d_adj_sum.p, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(c, e, "score mean");
+  }
+  // replay B: (Q_h - Qbar) times the free-flight scores
+  if (!rc)
+    rc = fp64(c) ? run_impl<double>(c, c->run_seed, c->run_first, n, s, 2, qsum / double(n))
+                 : run_impl<float>(c, c->run_seed, c->run_first, n, s, 2, qsum / double(n));
+  c->test_mode = test;
+  c->iterations = iters;
+  c->chunks = chunks;
+  if (rc) return rc;
+  e = fp64(c) ? launch_adjoint_finalize(static_cast<const double*>(c->d_adj_grad.p), dl,
+                                        static_cast<const double*>(c->d_sumq.p),
+                                        static_cast<const double*>(c->d_rho.p), nv, vol, double(n), out, s)
+              : launch_adjoint_finalize(static_cast<const double*>(c->d_adj_grad.p), dl,
+                                        static_cast<const double*>(c->d_sumq.p),
+                                        static_cast<const float*>(c->d_rho.p), nv, vol, double(n), out, s);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dl_drho, out, nv * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_cnt.p, &saved, sizeof(Counters), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "finalize gradient");
   return MCX_OK;
 }
 
@@ -641,6 +744,7 @@ int mcx_get_stats(mcx_ctx* c, mcx_stats* out) {
   out->ms_knock = c->ms_kernel[2];
   out->ms_estep = c->ms_kernel[3];
   out->timed_iterations = c->timed_iterations;
+  out->ms_backward = c->ms_backward;
   if (!c->d_cnt.p) return MCX_OK;
   (void)hipSetDevice(c->device);
   Counters h;

@@ -314,7 +314,15 @@ struct DepAcc {
 
 template <typename T>
 __device__ __forceinline__ void dep_flush(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
-  if (acc.key != kEmptyKey && acc.q != 0.0) tally_insert(a, acc.key, acc.q, ls);
+  if (acc.key != kEmptyKey && acc.q != 0.0) {
+    if (a.mode == 0) {
+      tally_insert(a, acc.key, acc.q, ls);
+    } else if (a.mode == 1) {
+      const uint32_t v = uint32_t(acc.key & 0xFFFFFFFFull);
+      const uint64_t h = (acc.key >> 32) - a.cnt->run_first;
+      unsafeAtomicAdd(&a.adj_q[h], a.adj_w[v] * acc.q);
+    }
+  }
   acc.key = kEmptyKey;
   acc.q = 0.0;
 }

@@ -160,15 +160,21 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
       bool escaped = false;
       uint32_t v = vlin(a, p.ix);
       double t0 = tn[0], t1 = tn[1], t2 = tn[2];
+      // replay B: the history's centred weighted score times d ln p / d rho_j
+      // of this free flight (-mu l_j per voxel, +1/rho at the interaction)
+      const double cq = a.mode == 2 ? a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar : 0.0;
+      const double mud = double(mt);
       for (;;) {
         const int ax = (t0 <= t1 && t0 <= t2) ? 0 : (t1 <= t2 ? 1 : 2);
         const double tf = ax == 0 ? t0 : (ax == 1 ? t1 : t2);
         const double s = tf - t;
         const double rho = double(a.rho[v]);
         if (rho * s >= tau) {
+          if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[v], cq * (-mud * (tau / rho) + 1.0 / rho));
           t += tau / rho;
           break;
         }
+        if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[v], cq * (-mud * s));
         tau -= rho * s;
         t = tf;
         bool out = false;
@@ -453,6 +459,12 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * db)), g.i);
     if (!(e1 < e)) e1 = e;
     deposit(a, acc, ls, p, e - e1);
+    if (a.mode == 1 && e1 < e) {
+      // replay A: d(loss over the geometric length db)/d rho = db S_soft(E')
+      const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
+      const T s1 = interp(tab, nt, base + O_LS, g1, e1, T(0));
+      unsafeAtomicAdd(&a.adj_grad[v], a.adj_w[v] * db * double(s1));
+    }
     p.e = e1;
     event(a, p, EV_CROSS, v);
     if (cross(a, p, db, ax, ls)) {
@@ -697,6 +709,35 @@ __global__ void k_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, 
     vals[s] = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt->occupied = n;
+}
+
+// density gradient helpers: loss weights per MeV, mean of Q_h, final terms
+template <typename T>
+__global__ void k_adj_weights(const double* dl_ddose, const T* rho, uint64_t nvox, double vol, double* w) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nvox; v += stride)
+    w[v] = dl_ddose[v] * 1e6 / (double(rho[v]) * vol);
+}
+
+template <typename T>
+__global__ void k_adj_sum(const double* q, uint64_t n, double* out) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) acc += q[i];
+  acc = wave_sum(acc);
+  if (__lane_id() == 0 && acc != 0.0) unsafeAtomicAdd(out, acc);
+}
+
+// dL/drho_j = (score and pathwise sums)/N - dL/dD_j * D_j / rho_j
+template <typename T>
+__global__ void k_adj_finalize(const double* grad_acc, const double* dl_ddose, const double* sum_q, const T* rho,
+                               uint64_t nvox, double vol, double nhist, double* out) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nvox; v += stride) {
+    const double r = double(rho[v]);
+    const double dose = sum_q[v] / nhist * 1e6 / (r * vol);
+    out[v] = grad_acc[v] / nhist - dl_ddose[v] * dose / r;
+  }
 }
 
 // dose (eV/g per history) and its standard error, Eq. (1)-(3)

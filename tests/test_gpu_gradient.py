@@ -1,0 +1,165 @@
+"""GPU density gradient (two replays from the random-number counters)
+against the oracle's score-function gradient on the same histories, the
+closed-form layered absorber, common-random-number finite differences, and
+the torch.autograd path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _mcx():
+    import paper_2003_00796_amd as mcx
+    return mcx
+
+
+def gpu_grad(wl, n, c, seed=1, precision=0):
+    mcx = _mcx()
+    sim = mcx.Simulator(precision, 0).setup(wl)
+    sim.run(seed, 0, n)
+    d, s = sim.dose()
+    g = sim.dose_backward(c)
+    st = sim.stats()
+    sim.close()
+    return g, d, st
+
+
+def oracle_grad(wl, n, c, seed=1):
+    tb = O.Tables(wl["material"], wl["transport"])
+    r = O.run(tb, wl["phantom"], wl["sources"], seed, 0, n)
+    d, _ = O.dose(wl["phantom"], r)
+    g, _ = O.gradient(tb, wl["phantom"], wl["sources"], seed, 0, n, c, d)
+    return g, d
+
+
+def slab_case(n):
+    rho = np.array([1.0, 0.3, 1.8, 1.0, 0.5, 2.2, 1.0, 1.3, 0.26, 1.1])
+    ph = W.slab_phantom(rho.size, 0.5, rho)
+    t = W.transport(flags=O.NO_COMPTON | O.NO_RAYLEIGH | O.NO_PAIR, eabs=(0.01, 1e9, 1e9))
+    return dict(name="slab", phantom=ph, transport=t, material=W.WATER,
+                sources=[W.pencil(0, 0.03, (50.0, 50.0, 0.0), n)], seed=1), rho
+
+
+def test_gradient_matches_oracle_kerma_and_class2():
+    rng = np.random.default_rng(7)
+    # kerma mode, full photon physics
+    wl = dict(W.workload("hetero_broad_64", 4000))
+    wl["transport"] = W.transport(eabs=(0.01, 1e9, 1e9))
+    c = rng.uniform(-1, 1, size=wl["phantom"]["shape"])
+    g, d, _ = gpu_grad(wl, 4000, c)
+    go, do = oracle_grad(wl, 4000, c)
+    scale = np.abs(go).max()
+    assert np.max(np.abs(g - go)) <= 1e-9 * scale, np.max(np.abs(g - go)) / scale
+    # full Class II transport: the same estimator on (almost) the same histories
+    wl = W.workload("hetero_broad_64", 2000)
+    g, d, _ = gpu_grad(wl, 2000, c)
+    go, do = oracle_grad(wl, 2000, c)
+    scale = np.abs(go).max()
+    rel = np.abs(g - go) / scale
+    print("class II max rel diff", rel.max())
+    assert np.mean(rel < 1e-6) > 0.99
+    assert rel.max() < 0.05
+
+
+def test_layered_absorber_closed_form_on_gpu():
+    n = 1_000_000
+    wl, rho = slab_case(n)
+    nz = rho.size
+    e0, dz = 0.03, 0.5
+    mu = 4.94 * 3.0 ** -3
+    vol = 100.0 * 100.0 * dz
+    c = np.random.default_rng(5).uniform(-1, 1, size=nz).reshape(nz, 1, 1)
+    cum = np.concatenate([[0.0], np.cumsum(rho * dz)])
+    T = np.exp(-mu * cum[:-1])
+    a = 1.0 - np.exp(-mu * rho * dz)
+    D = e0 * T * a * 1e6 / (rho * vol)
+    exact = np.zeros(nz)
+    for k in range(nz):
+        for j in range(nz):
+            if k < j:
+                deq = e0 * (-mu * dz) * T[j] * a[j]
+            elif k == j:
+                deq = e0 * T[j] * mu * dz * math.exp(-mu * rho[j] * dz)
+            else:
+                deq = 0.0
+            exact[k] += c.ravel()[j] * (1e6 / (rho[j] * vol) * deq - (D[j] / rho[j] if k == j else 0.0))
+    gs = np.array([gpu_grad(wl, n, c, seed=s)[0].ravel() for s in range(1, 9)])
+    mean, sem = gs.mean(0), gs.std(0, ddof=1) / math.sqrt(gs.shape[0])
+    z = (mean - exact) / sem
+    print("z", np.round(z, 2))
+    assert np.all(np.abs(z) < 4.5)
+
+
+def test_kerma_gradient_vs_crn_finite_differences():
+    """Exact setting (electrons absorbed where created): the replay gradient
+    agrees with central differences (+-10%, common random numbers).  The
+    finite differences are heavy-tailed (a density change moves some
+    interactions into neighbouring voxels), so they need 2e7 histories per
+    evaluation and 12 seeds to reach a useful standard error."""
+    rng = np.random.default_rng(3)
+    ph = W.water_cube(16, 8.0)
+    ph["rho"] = rng.uniform(0.5, 1.8, size=ph["rho"].shape)
+    n = 20_000_000
+    wl = dict(name="kerma", phantom=ph, transport=W.transport(eabs=(0.01, 1e9, 1e9)), material=W.WATER,
+              sources=[W.rect_field(0, 2.0, (4.0, 4.0, 0.0), (6.0, 6.0), n)], seed=1)
+    c = rng.uniform(-1, 1, size=ph["shape"])
+    mcx = _mcx()
+    sim = mcx.Simulator(0, 0).setup(wl)
+    gs = []
+    for s in range(1, 5):
+        sim.reset()
+        sim.run(s, 0, n)
+        sim.dose()
+        gs.append(sim.dose_backward(c))
+    sim.close()
+    gs = np.array(gs)
+    mean, sem = gs.mean(0), gs.std(0, ddof=1) / math.sqrt(gs.shape[0])
+    h = 0.1
+    for v in [(6, 7, 9), (2, 8, 8)]:
+        sims = {}
+        for sgn in (+1, -1):
+            p2 = dict(ph, rho=ph["rho"].copy())
+            p2["rho"][v] *= 1 + sgn * h
+            sims[sgn] = mcx.Simulator(0, 0).setup(dict(wl, phantom=p2))
+        fds = []
+        for s in range(100, 112):
+            vals = []
+            for sgn in (+1, -1):
+                sims[sgn].reset()
+                sims[sgn].run(s, 0, n)
+                d, _ = sims[sgn].dose()
+                vals.append(float((c * d).sum()))
+            fds.append((vals[0] - vals[1]) / (2 * h * ph["rho"][v]))
+        for sm in sims.values():
+            sm.close()
+        fd, fd_sem = np.mean(fds), np.std(fds, ddof=1) / math.sqrt(len(fds))
+        z = (mean[v] - fd) / math.sqrt(sem[v] ** 2 + fd_sem ** 2)
+        print(v, "replay", mean[v], "+-", sem[v], "fd", fd, "+-", fd_sem, "z", z)
+        assert abs(z) < 4.0
+
+
+def test_autograd_function_quadratic_loss():
+    import torch
+    mcx = _mcx()
+    wl = W.workload("hetero_broad_64", 20000)
+    model = mcx.DoseModel(wl, 20000, seed=3)
+    rho = torch.tensor(wl["phantom"]["rho"], device="cuda", dtype=torch.float64, requires_grad=True)
+    dose = mcx.DoseFunction.apply(rho, model)
+    target = 0.5 * dose.detach()
+    loss = ((dose - target) ** 2).sum()
+    loss.backward()
+    g = rho.grad.cpu().numpy()
+    # the same gradient through the plain ABI call
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.run(3, 0, 20000)
+    d, _ = sim.dose()
+    assert np.allclose(d, dose.detach().cpu().numpy(), rtol=1e-12, atol=0)
+    g2 = sim.dose_backward(2 * (d - 0.5 * d))
+    sim.close()
+    assert np.allclose(g, g2, rtol=1e-9, atol=1e-12 * np.abs(g2).max())
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
