@@ -70,6 +70,69 @@ def run_steps(sim, n, seeds, sync):
     return times
 
 
+def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
+    """Forward + backward (two replays) on the 64^3 heterogeneous phantom,
+    6 MeV field, loss sum_v (D_v - T_v)^2 with a seeded smooth target."""
+    from scipy.ndimage import gaussian_filter
+    wl = W.workload("hetero_broad_64", n)
+    sim = mcx.Simulator(mcx.FP64, 0).setup(wl)
+    sim.run(777, 0, min(n, 200_000))  # warm-up
+    sim.reset()
+    sync()
+    t0 = time.perf_counter()
+    sim.run(1, 0, n)
+    d, _ = sim.dose()
+    sync()
+    t1 = time.perf_counter()
+    rng = np.random.Generator(np.random.PCG64(5))
+    s = gaussian_filter(rng.standard_normal(d.shape), 3.0)
+    s = (s - s.min()) / (s.max() - s.min())
+    dbar = d[d >= 0.1 * d.max()].mean()
+    target = dbar * (0.5 + s)
+    g = sim.dose_backward(2.0 * (d - target))
+    sync()
+    t2 = time.perf_counter()
+    sim.close()
+    return dict(workload="hetero_broad_64: 6 MeV 10x10 field, 64^3 x 4 mm, FP64", histories=n,
+                forward_s=t1 - t0, backward_s=t2 - t1, fwd_bwd_s=t2 - t0, grad_abs_max=float(np.abs(g).max()))
+
+
+def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
+    """512 beamlets with lognormal history counts in one autotuned run (a
+    batch of iterations is one HIP graph launch) against one run per beamlet."""
+    wl = W.workload("beamlets_256", total)
+    sim = mcx.Simulator(mcx.MIXED, 0).setup(wl)
+    t0 = time.perf_counter()
+    chosen = sim.autotune(200_000, cache)
+    t_tune = time.perf_counter() - t0
+    sim.run(999, 0, 200_000)
+    sim.reset()
+    sync()
+    t0 = time.perf_counter()
+    sim.run(1, 0, sim.n_hist_total)
+    sync()
+    t_batched = time.perf_counter() - t0
+    d_all, _ = sim.dose()
+    sim.reset()
+    sync()
+    t0 = time.perf_counter()
+    first = 0
+    for src in wl["sources"]:
+        sim.run(1, first, src["n_hist"])
+        first += src["n_hist"]
+    sync()
+    t_each = time.perf_counter() - t0
+    d_each, _ = sim.dose()
+    sim.close()
+    hi = d_all >= 0.5 * d_all.max()
+    return dict(workload="beamlets_256: 512 beamlets 4-15 MeV, lognormal counts, 256^3 x 2 mm noise phantom, mixed",
+                histories=int(sum(x["n_hist"] for x in wl["sources"])), autotuned=dict(zip(("bank", "block", "steps"), chosen)),
+                autotune_s=t_tune, batched_s=t_batched, per_beamlet_s=t_each,
+                batched_hist_per_s=sum(x["n_hist"] for x in wl["sources"]) / t_batched,
+                speedup=t_each / t_batched,
+                same_dose_rel_max=float(np.max(np.abs(d_all[hi] - d_each[hi]) / d_all[hi])))
+
+
 def cpu_baseline(wl, n_sample: int) -> dict:
     import oracle as O
     tb = O.Tables(wl["material"], wl["transport"])
@@ -89,6 +152,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--beamlets", type=int, default=0, metavar="TOTAL",
+                    help="also time 512 beamlets with TOTAL histories batched vs one run each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -180,6 +246,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "launches": launches},
     }
+    if not args.no_gradient:
+        out["gradient"] = gradient_timing(mcx, W, sync)
+    if args.beamlets:
+        out["beamlets"] = beamlet_comparison(mcx, W, sync, args.beamlets,
+                                             os.path.join(ROOT, "gpurun_out", "autotune_cache.jsonl"))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
     print(json.dumps(out))

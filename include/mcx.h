@@ -171,6 +171,17 @@ int mcx_set_sources(mcx_ctx* ctx, const mcx_source* s, int n);
  * queue (capacity of each event queue), block = threads per block (multiple
  * of 64, <= 1024), steps = Class II steps per visit of the e+- kernel. */
 int mcx_set_launch(mcx_ctx* ctx, uint32_t bank, uint32_t block, uint32_t steps);
+/* Replay each batch of event-loop iterations as one captured HIP graph
+ * (1, default) or launch its kernels one by one (0).  Graphs are used only
+ * while per-kernel timing is off. */
+int mcx_set_graph(mcx_ctx* ctx, int on);
+/* Pick bank size, block size and steps per visit by timing a sample of
+ * n_sample histories (0: min(total, 2e5)) for each candidate, apply the
+ * fastest and reset the tallies.  With cache_path, a previous result for the
+ * same device and workload (a hash of architecture, precision, grid, transport
+ * parameters and sources) is reused, and a new one is appended as a JSON line.
+ * chosen (3 values: bank, block, steps) may be NULL. */
+int mcx_autotune(mcx_ctx* ctx, uint64_t n_sample, const char* cache_path, uint32_t* chosen);
 /* Enable (1) or disable (0) per-kernel timing with HIP events recorded on
  * the run's stream around each transport kernel (small overhead). */
 int mcx_set_timing(mcx_ctx* ctx, int on);

@@ -31,7 +31,7 @@ ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM"
 ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport", "mcx_load_material",
                "mcx_load_phantom", "mcx_set_sources", "mcx_set_launch", "mcx_set_timing", "mcx_set_test_mode", "mcx_run",
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
-               "mcx_get_history_results", "mcx_dose_backward")
+               "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune")
 
 
 class MaterialDesc(C.Structure):
@@ -115,6 +115,8 @@ def lib():
         L.mcx_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.mcx_get_history_results.argtypes = [vp, vp, vp]
         L.mcx_dose_backward.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.mcx_set_graph.argtypes = [vp, C.c_int]
+        L.mcx_autotune.argtypes = [vp, C.c_uint64, C.c_char_p, C.POINTER(C.c_uint32)]
         for f in ABI_SYMBOLS:
             if f not in ("mcx_destroy", "mcx_last_error"):
                 getattr(L, f).restype = C.c_int
@@ -215,6 +217,16 @@ class Simulator:
 
     def set_timing(self, on: bool):
         self._check(self._L.mcx_set_timing(self._h, 1 if on else 0), "set_timing")
+
+    def set_graph(self, on: bool):
+        self._check(self._L.mcx_set_graph(self._h, 1 if on else 0), "set_graph")
+
+    def autotune(self, n_sample: int = 0, cache_path: str | None = None):
+        """(bank, block, steps) chosen by timing a sample; see mcx_autotune."""
+        out = (C.c_uint32 * 3)()
+        self._check(self._L.mcx_autotune(self._h, n_sample, cache_path.encode() if cache_path else None, out),
+                    "autotune")
+        return tuple(out)
 
     def set_test_mode(self, on: bool):
         self._check(self._L.mcx_set_test_mode(self._h, 1 if on else 0), "set_test_mode")

@@ -75,6 +75,8 @@ struct mcx_ctx {
   // stats
   uint64_t iterations = 0, chunks = 0, tally_pairs = 0;
   double ms_transport = 0.0, ms_flush = 0.0;
+  // replay batches of iterations as one captured HIP graph (timing off only)
+  int use_graph = 1;
   // per-kernel timing with HIP events on the run's stream
   int timing = 0;
   std::vector<hipEvent_t> events;  // kBatch iterations x (kTimedKernels + 1)
@@ -259,6 +261,29 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   auto t0 = std::chrono::steady_clock::now();
   double flush_ms = 0.0;
   int par = 0;
+  // kBatch iterations (parities 0, 1, 0, ...) captured once per run: a batch
+  // is then one graph launch; kBatch is even, so every batch starts at parity 0
+  hipGraphExec_t gexec = nullptr;
+  const bool use_graph = c->use_graph && !c->timing;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < kBatch && e == hipSuccess; ++k) e = launch_iteration(a, k & 1, target, grid, int(c->block), s, nullptr);
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return hip_fail(c, e, "capture of the iteration graph");
+    }
+  }
+  struct GraphGuard {
+    hipGraphExec_t g;
+    ~GraphGuard() {
+      if (g) (void)hipGraphExecDestroy(g);
+    }
+  } guard{gexec};
   while (done < n) {
     uint64_t chunk;
     if (c->pairs_per_hist > 0.0) chunk = uint64_t(double(table_budget) / (1.25 * c->pairs_per_hist));
@@ -269,12 +294,18 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
     hipError_t e = launch_chunk_init(a.cnt, cf, ce, first, uint32_t(std::min<uint64_t>(chunk, target)), s);
     if (e != hipSuccess) return hip_fail(c, e, "chunk init launch");
     for (;;) {
-      for (int k = 0; k < kBatch; ++k) {
-        hipEvent_t* ev = c->timing ? &c->events[size_t(k) * (kTimedKernels + 1)] : nullptr;
-        e = launch_iteration(a, par, target, grid, int(c->block), s, ev);
-        if (e != hipSuccess) return hip_fail(c, e, "iteration launch");
-        par ^= 1;
-        c->iterations++;
+      if (use_graph) {
+        e = hipGraphLaunch(gexec, s);
+        if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+        c->iterations += kBatch;
+      } else {
+        for (int k = 0; k < kBatch; ++k) {
+          hipEvent_t* ev = c->timing ? &c->events[size_t(k) * (kTimedKernels + 1)] : nullptr;
+          e = launch_iteration(a, par, target, grid, int(c->block), s, ev);
+          if (e != hipSuccess) return hip_fail(c, e, "iteration launch");
+          par ^= 1;
+          c->iterations++;
+        }
       }
       e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -563,6 +594,89 @@ int mcx_set_timing(mcx_ctx* c, int on) {
     }
   }
   c->timing = on ? 1 : 0;
+  return MCX_OK;
+}
+
+int mcx_set_graph(mcx_ctx* c, int on) {
+  if (!c) return MCX_E_INVALID;
+  c->use_graph = on ? 1 : 0;
+  return MCX_OK;
+}
+
+// FNV-1a over the bytes that shape the workload
+static uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+int mcx_autotune(mcx_ctx* c, uint64_t n_sample, const char* cache_path, uint32_t* chosen) {
+  if (!c) return MCX_E_INVALID;
+  if (!c->have_sources) return fail(c, MCX_E_STATE, "set transport, material, phantom and sources first");
+  if (n_sample == 0 || n_sample > c->total_hist) n_sample = std::min<uint64_t>(c->total_hist, 200000);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "device properties");
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
+  h = fnv(h, &c->precision, sizeof(c->precision));
+  const int dims[3] = {c->nx, c->ny, c->nz};
+  h = fnv(h, dims, sizeof(dims));
+  h = fnv(h, &c->tr, sizeof(c->tr));
+  for (const SourceDev& sd : c->src) {
+    h = fnv(h, &sd.particle, sizeof(sd.particle));
+    h = fnv(h, &sd.energy, sizeof(sd.energy));
+  }
+  char key[32];
+  std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)h);
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        char k[64];
+        unsigned b = 0, bl = 0, st = 0;
+        if (std::sscanf(line, "{\"key\": \"%63[0-9a-f]\", \"bank\": %u, \"block\": %u, \"steps\": %u", k, &b, &bl,
+                        &st) == 4 &&
+            std::strcmp(k, key) == 0) {
+          std::fclose(f);
+          int rc = mcx_set_launch(c, b, bl, st);
+          if (!rc && chosen) { chosen[0] = b; chosen[1] = bl; chosen[2] = st; }
+          return rc;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  const uint32_t banks[] = {1u << 20, 1u << 21, 1u << 22};
+  const uint32_t blocks[] = {128u, 256u};
+  const uint32_t steps[] = {32u, 128u, 512u};
+  double best = 0.0;
+  uint32_t bb = c->cap, bbl = c->block, bst = c->steps;
+  const int test = c->test_mode;
+  c->test_mode = 0;
+  int rc = MCX_OK;
+  for (uint32_t b : banks)
+    for (uint32_t bl : blocks)
+      for (uint32_t st : steps) {
+        if ((rc = mcx_set_launch(c, b, bl, st))) break;
+        if ((rc = mcx_reset_tallies(c))) break;
+        auto t0 = std::chrono::steady_clock::now();
+        if ((rc = mcx_run(c, 12345, 0, n_sample, nullptr))) break;
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const double rate = double(n_sample) / dt;
+        if (rate > best) { best = rate; bb = b; bbl = bl; bst = st; }
+      }
+  c->test_mode = test;
+  if (rc) return rc;
+  if ((rc = mcx_set_launch(c, bb, bbl, bst))) return rc;
+  if ((rc = mcx_reset_tallies(c))) return rc;
+  if (chosen) { chosen[0] = bb; chosen[1] = bbl; chosen[2] = bst; }
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "{\"key\": \"%s\", \"bank\": %u, \"block\": %u, \"steps\": %u, \"hist_per_s\": %.6g, \"device\": \"%s\"}\n",
+                   key, bb, bbl, bst, best, prop.gcnArchName);
+      std::fclose(f);
+    }
+  }
   return MCX_OK;
 }
 

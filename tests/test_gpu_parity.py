@@ -202,3 +202,59 @@ def test_independent_seed_z_scores():
     assert abs(z.mean()) < 5 / math.sqrt(z.size) + 0.05
     assert 0.85 < z.std() < 1.15
     assert np.mean(np.abs(z) > 3) < 0.01
+
+
+def test_batched_beamlets_equal_per_beamlet_runs_and_graph_modes():
+    """Many sources in one run (one history-id space, a persistent event loop)
+    give the same histories as one run per source; graph replay and direct
+    launches are identical."""
+    srcs = W.beamlet_sources(nb=32, total=6000)[:12]
+    ph = W.ct_noise_phantom(n=48, d=0.2, seed=3)
+    # the lattice of the 512-beamlet layout is centred on a 51.2 cm face: move
+    # the first 12 beamlets onto the 9.6 cm face of this phantom
+    for i, s in enumerate(srcs):
+        s["pos"] = (2.0 + 0.5 * (i % 6), 2.0 + 0.5 * (i // 6), 0.0)
+        s["energy"] = min(s["energy"], 9.0)
+    wl = dict(name="beamlets", phantom=ph, sources=srcs, transport=W.transport(10.0, 200), material=W.WATER, seed=1)
+    n = sum(s["n_hist"] for s in srcs)
+    mcx = _mcx()
+    res = []
+    for graph in (True, False):
+        sim = mcx.Simulator(0, 0).setup(wl)
+        sim.set_graph(graph)
+        sim.set_test_mode(True)
+        sim.run(1, 0, n)
+        h, _ = sim.history_results(n)
+        q, _ = sim.tally()
+        res.append((h, q))
+        sim.close()
+    assert np.array_equal(res[0][0], res[1][0])
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.set_test_mode(True)
+    first, hs = 0, []
+    for s in srcs:
+        sim.run(1, first, s["n_hist"])
+        hs.append(sim.history_results(s["n_hist"])[0])
+        first += s["n_hist"]
+    q, _ = sim.tally()
+    sim.close()
+    assert np.array_equal(np.concatenate(hs), res[0][0])
+    assert np.allclose(q, res[0][1], rtol=1e-11, atol=1e-14)
+
+
+def test_autotune_picks_and_caches(tmp_path):
+    mcx = _mcx()
+    wl = W.workload("water_pencil_32", 20000)
+    cache = str(tmp_path / "tune.jsonl")
+    sim = mcx.Simulator(1, 0).setup(wl)
+    chosen = sim.autotune(20000, cache)
+    assert chosen[0] in (1 << 20, 1 << 21, 1 << 22) and chosen[1] in (128, 256) and chosen[2] in (32, 128, 512)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"key"' in lines[0]
+    again = sim.autotune(20000, cache)
+    assert again == chosen
+    assert len(open(cache).read().strip().splitlines()) == 1
+    sim.run(1, 0, 20000)
+    d, _ = sim.dose()
+    assert d.max() > 0
+    sim.close()
