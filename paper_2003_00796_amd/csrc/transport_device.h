@@ -281,7 +281,7 @@ __device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long lon
 // tally: (history, voxel) -> score, open addressing with linear probing
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
+__device__ __forceinline__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
   ls.inserts++;
   uint64_t slot = mix64(key) & a.hmask;
   for (int probe = 0; probe < 4096; ++probe) {
@@ -306,23 +306,45 @@ __device__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStat
   atomicOr(&a.cnt->overflow, uint32_t(OVF_TALLY));
 }
 
-// deposits of one particle are summed in registers while they stay in one voxel
+// deposits of one particle are summed in registers while they stay in one
+// voxel; when the voxel (or history) changes, the finished sum becomes
+// `pending` and is inserted at the caller's next flush point, so each kernel
+// has one inlined copy of the table insertion (all deposits of one Class II
+// step or one photon interaction fall in the same voxel)
 struct DepAcc {
   uint64_t key;
   double q;
+  uint64_t pkey;  // pending (finished) entry
+  double pq;
 };
 
+__device__ __forceinline__ DepAcc dep_init() { return DepAcc{kEmptyKey, 0.0, kEmptyKey, 0.0}; }
+
+template <typename T>
+__device__ __forceinline__ void dep_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
+  if (key == kEmptyKey || q == 0.0) return;
+  if (a.mode == 0) {
+    tally_insert(a, key, q, ls);
+  } else if (a.mode == 1) {
+    const uint32_t v = uint32_t(key & 0xFFFFFFFFull);
+    const uint64_t h = (key >> 32) - a.cnt->run_first;
+    unsafeAtomicAdd(&a.adj_q[h], a.adj_w[v] * q);
+  }
+}
+
+// insert the pending entry (call at one convergent point per step)
+template <typename T>
+__device__ __forceinline__ void dep_flush_pending(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
+  dep_insert(a, acc.pkey, acc.pq, ls);
+  acc.pkey = kEmptyKey;
+  acc.pq = 0.0;
+}
+
+// insert everything (end of a kernel)
 template <typename T>
 __device__ __forceinline__ void dep_flush(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
-  if (acc.key != kEmptyKey && acc.q != 0.0) {
-    if (a.mode == 0) {
-      tally_insert(a, acc.key, acc.q, ls);
-    } else if (a.mode == 1) {
-      const uint32_t v = uint32_t(acc.key & 0xFFFFFFFFull);
-      const uint64_t h = (acc.key >> 32) - a.cnt->run_first;
-      unsafeAtomicAdd(&a.adj_q[h], a.adj_w[v] * acc.q);
-    }
-  }
+  dep_flush_pending(a, acc, ls);
+  dep_insert(a, acc.key, acc.q, ls);
   acc.key = kEmptyKey;
   acc.q = 0.0;
 }
@@ -337,8 +359,14 @@ __device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStat
   if (e == T(0)) return;
   const uint64_t key = (uint64_t(p.hist) << 32) | vlin(a, p.ix);
   if (key != acc.key) {
-    dep_flush(a, acc, ls);
+    if (acc.pkey != kEmptyKey) {
+      // a second voxel change before the caller flushed: insert now
+      dep_insert(a, acc.pkey, acc.pq, ls);
+    }
+    acc.pkey = acc.key;
+    acc.pq = acc.q;
     acc.key = key;
+    acc.q = 0.0;
   }
   acc.q += double(e);
   ls.deposits++;

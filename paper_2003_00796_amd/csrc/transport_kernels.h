@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
     c1.on = false;
     c2.on = false;
     bool keep = false;
-    DepAcc acc{kEmptyKey, 0.0};
+    DepAcc acc = dep_init();
     if (i < ntot) {
       const int q = i < n0 ? 0 : (i < e1 ? 1 : (i < e2 ? 2 : 3));
       const uint32_t j = i - (q == 0 ? 0u : (q == 1 ? n0 : (q == 2 ? e1 : e2)));
@@ -454,18 +454,21 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
     return false;
   }
-  if (db <= th) {
-    // the face comes first: soft loss over db, cross, start a new step
-    T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * db)), g.i);
-    if (!(e1 < e)) e1 = e;
-    deposit(a, acc, ls, p, e - e1);
+  // soft loss over the geometric length travelled: db when the face comes
+  // before the hinge (then the step ends at the face), else the whole step
+  // charged at the hinge; one range inversion serves both cases
+  const bool face_first = db <= th;
+  T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * (face_first ? db : len))), g.i);
+  if (!(e1 < e)) e1 = e;
+  deposit(a, acc, ls, p, e - e1);
+  p.e = e1;
+  if (face_first) {
     if (a.mode == 1 && e1 < e) {
       // replay A: d(loss over the geometric length db)/d rho = db S_soft(E')
       const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
       const T s1 = interp(tab, nt, base + O_LS, g1, e1, T(0));
       unsafeAtomicAdd(&a.adj_grad[v], a.adj_w[v] * db * double(s1));
     }
-    p.e = e1;
     event(a, p, EV_CROSS, v);
     if (cross(a, p, db, ax, ls)) {
       e_escape(a, p, v, bs);
@@ -473,12 +476,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     }
     return true;
   }
-  // hinge: the soft energy loss of the whole step is charged here
   move(p, th);
-  T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * len)), g.i);
-  if (!(e1 < e)) e1 = e;
-  deposit(a, acc, ls, p, e - e1);
-  p.e = e1;
   if (!(e1 > eabs)) {
     e_absorb(a, p, c1, c2, acc, ls, bs);
     return false;
@@ -601,7 +599,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
   const Bank<T>& in = a.q[q_ein(par)];
   const int ge = q_eout(par), gg = q_gout(par);
   Part<T> p;
-  DepAcc acc{kEmptyKey, 0.0};
+  DepAcc acc = dep_init();
   bool alive = false, taking = true;
   uint32_t used = 0;
   for (;;) {
@@ -626,6 +624,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
       alive = e_step(a, tab, p, c1, c2, acc, ls, &bs);
       ++used;
     }
+    dep_flush_pending(a, acc, ls);
     // secondaries of this step, wavefront-aggregated
     const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
     const uint32_t se = append(a, ge, c1e);
