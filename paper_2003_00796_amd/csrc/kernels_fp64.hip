@@ -28,11 +28,10 @@ hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   return hipGetLastError();
 }
 
-hipError_t launch_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, uint64_t nslot, double* sum_q,
-                        double* sum_q2, Counters* cnt, int test_mode, double* hist_led, uint64_t n_run,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_flush<double>, dim3(4096), dim3(256), 0, s, keys, vals, occ_list, nslot, sum_q, sum_q2, cnt,
-                     test_mode, hist_led, n_run);
+hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
+                        int test_mode, double* hist_led, uint64_t n_run, hipStream_t s) {
+  hipLaunchKernelGGL(k_flush<double>, dim3(8192), dim3(256), 0, s, keys, vals, nslot, sum_q, sum_q2, cnt, test_mode,
+                     hist_led, n_run);
   return hipGetLastError();
 }
 

@@ -17,9 +17,8 @@ hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int
                             hipEvent_t* ev);
 hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm,
                              hipStream_t s);
-hipError_t launch_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, uint64_t nslot, double* sum_q,
-                        double* sum_q2, Counters* cnt, int test_mode, double* hist_led, uint64_t n_run,
-                        hipStream_t s);
+hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
+                        int test_mode, double* hist_led, uint64_t n_run, hipStream_t s);
 hipError_t launch_dose(const double* sum_q, const double* sum_q2, const double* rho, uint64_t nvox, double vol,
                        double nhist, double* dose, double* sigma, hipStream_t s);
 hipError_t launch_dose(const double* sum_q, const double* sum_q2, const float* rho, uint64_t nvox, double vol,

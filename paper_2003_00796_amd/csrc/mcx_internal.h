@@ -8,9 +8,9 @@
 //  - particle queues: Q_NQ structure-of-arrays banks of `cap` records each
 //    (positions f64 x3, direction T x3, energy T, uid u64, history u32, draw
 //    counter u32, packed voxel u32, type/child-count u32, event hash u64);
-//  - tally: open-addressing table of (history-in-chunk, voxel) keys with an
-//    FP64 score each, flushed per chunk into Sum q / Sum q^2 (FP64, one per
-//    voxel) -- the per-history estimator of Eq. (1)-(3) of the paper.
+//  - tally: open-addressing table of (history, voxel) keys with an FP64 score
+//    each, flushed per chunk into Sum q / Sum q^2 (FP64, one per voxel) --
+//    the per-history estimator of Eq. (1)-(3) of the paper.
 #pragma once
 
 #include <stdint.h>
@@ -86,7 +86,6 @@ struct Counters {
   uint64_t stat[S_NSTAT];
   double e_dep, e_esc;
   uint64_t occupied;       // tally pairs seen by the last flush
-  uint64_t n_occ;          // tally slots claimed in the current chunk (list length)
 };
 
 template <typename T>
@@ -114,6 +113,7 @@ struct Tab {
   const T* t;        // channel-major block, T_NCH * n
   int n;
   T lemin, inv_dl;   // ln of the first node, 1 / log spacing
+  T dl;              // log spacing
   T emin;
   T thr_pp, thr_in[2], thr_br;
   T k_coef;          // n_mol pi r_e^2 sum Z(Z+1): K(E) = k_coef (mc^2 / pv)^2
@@ -139,7 +139,6 @@ struct KArgs {
   uint64_t* hkeys;
   double* hvals;
   uint64_t hmask;
-  uint32_t* occ_list;    // slots claimed in this chunk, in claim order
   double* sum_q;
   double* sum_q2;
   // test mode per-history outputs (indexed by history - cnt->run_first)

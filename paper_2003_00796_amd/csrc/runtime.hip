@@ -58,7 +58,7 @@ struct mcx_ctx {
   Counters* h_cnt = nullptr;  // pinned
   // tally table
   uint64_t hslots = 1ull << 27;
-  DevBuf d_hkeys, d_hvals, d_occ;
+  DevBuf d_hkeys, d_hvals;
   double pairs_per_hist = 0.0;
   bool table_dirty = false;  // a failed run may have left entries behind
   // test mode
@@ -188,7 +188,6 @@ int ensure_workspace(mcx_ctx* c) {
   if (!c->d_hkeys.p) {
     if ((rc = dalloc(c, c->d_hkeys, c->hslots * sizeof(uint64_t), "tally keys"))) return rc;
     if ((rc = dalloc(c, c->d_hvals, c->hslots * sizeof(double), "tally values"))) return rc;
-    if ((rc = dalloc(c, c->d_occ, c->hslots * sizeof(uint32_t), "tally slot list"))) return rc;
     hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, c->hslots * sizeof(double), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -205,6 +204,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.tb.n = b.n;
   a.tb.lemin = T(b.lemin);
   a.tb.inv_dl = T(1.0 / b.dl);
+  a.tb.dl = T(b.dl);
   a.tb.emin = T(c->tr.e_min);
   a.tb.thr_pp = T(b.thr_pp);
   a.tb.thr_in[0] = T(b.thr_in[0]);
@@ -228,7 +228,6 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.hkeys = static_cast<uint64_t*>(c->d_hkeys.p);
   a.hvals = static_cast<double*>(c->d_hvals.p);
   a.hmask = c->hslots - 1;
-  a.occ_list = static_cast<uint32_t*>(c->d_occ.p);
   a.sum_q = static_cast<double*>(c->d_sumq.p);
   a.sum_q2 = static_cast<double*>(c->d_sumq2.p);
   a.test_mode = c->test_mode;
@@ -333,7 +332,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       continue;
     }
     auto tf = std::chrono::steady_clock::now();
-    e = launch_flush(a.hkeys, a.hvals, a.occ_list, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+    e = launch_flush(a.hkeys, a.hvals, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "tally flush");
@@ -388,7 +387,7 @@ void mcx_destroy(mcx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
-                    &c->d_hvals, &c->d_occ, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad, &c->d_adj_dl, &c->d_adj_out,
+                    &c->d_hvals, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad, &c->d_adj_dl, &c->d_adj_out,
                     &c->d_adj_sum, &c->d_hhash, &c->d_hled})
     dfree(*b);
   if (c->h_cnt) (void)hipHostFree(c->h_cnt);

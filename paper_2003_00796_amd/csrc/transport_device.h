@@ -280,24 +280,17 @@ __device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long lon
 // ---------------------------------------------------------------------------
 // tally: (history, voxel) -> score, open addressing with linear probing
 // ---------------------------------------------------------------------------
+// One global round trip per insertion: compare-and-swap the key into its
+// slot (an empty slot is claimed, a slot holding this key is found), then add
+// the score without waiting for the result.  The flush scans the table.
 template <typename T>
 __device__ __forceinline__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
   ls.inserts++;
   uint64_t slot = mix64(key) & a.hmask;
   for (int probe = 0; probe < 4096; ++probe) {
-    uint64_t k = __hip_atomic_load(&a.hkeys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (k == kEmptyKey) {
-      k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
-                    (unsigned long long)key);
-      if (k == kEmptyKey) {
-        // this lane claimed the slot: record it for the flush (at most one
-        // entry per slot and chunk, so the list never exceeds the table)
-        const unsigned long long idx = atomicAdd((unsigned long long*)&a.cnt->n_occ, 1ull);
-        a.occ_list[idx] = uint32_t(slot);
-        k = key;
-      }
-    }
-    if (k == key) {
+    const uint64_t k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
+                                 (unsigned long long)key);
+    if (k == kEmptyKey || k == key) {
       unsafeAtomicAdd(&a.hvals[slot], q);
       return;
     }
@@ -419,11 +412,12 @@ __device__ __forceinline__ double face_dist(const KArgs<T>& a, const Part<T>& p,
   int ax = -1;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double dk = double(p.d[k]);
-    double s;
-    if (dk > 0.0) s = (o[k] + double(p.ix[k] + 1) * dd[k] - p.x[k]) / dk;
-    else if (dk < 0.0) s = (o[k] + double(p.ix[k]) * dd[k] - p.x[k]) / dk;
-    else continue;
+    const T dk = p.d[k];
+    if (dk == T(0)) continue;
+    const double face = dk > T(0) ? o[k] + double(p.ix[k] + 1) * dd[k] : o[k] + double(p.ix[k]) * dd[k];
+    // FP64 path: exact FP64 division; mixed path: the FP64 offset to the face
+    // (a few millimetres at most) divided in FP32
+    double s = is_fp64<T>() ? (face - p.x[k]) / double(dk) : double(T(face - p.x[k]) / dk);
     if (s < 0.0) s = 0.0;
     if (s < best) { best = s; ax = k; }
   }
@@ -521,9 +515,9 @@ __device__ __forceinline__ T interp(const T* s, int n, int ch, const Grid<T>& g,
   return M<T>::exp(l0 + g.f * (l1 - l0));
 }
 
-// range R(E): R_i + Int_{E_i}^{E} dE/S on the power-law segment
+// range R(E): R_i + Int_{E_i}^{E} dE/S on the power-law segment; `le` is ln E
 template <typename T>
-__device__ __forceinline__ T range_at(const T* s, int n, int base, const Grid<T>& g, T e) {
+__device__ __forceinline__ T range_at(const T* s, int n, int base, const Grid<T>& g, T e, T le, T lemin, T dl) {
   const T ei = s[T_ENODE * n + g.i];
   const T si = s[(base + O_S) * n + g.i];
   const T q = s[(base + O_Q) * n + g.i];
@@ -533,7 +527,8 @@ __device__ __forceinline__ T range_at(const T* s, int n, int base, const Grid<T>
     seg = (q > T(-1e-10) && q < T(1e-10)) ? (ei / si) * M<T>::log(e / ei)
                                           : (ei / si) * (M<T>::pow(e / ei, q) - T(1)) / q;
   } else {
-    seg = (ei / si) * ((q > T(-1e-10) && q < T(1e-10)) ? M<T>::log(e / ei) : M<T>::expm1(q * M<T>::log(e / ei)) / q);
+    const T lr = le - (lemin + T(g.i) * dl);  // ln(E/E_i)
+    seg = (ei / si) * ((q > T(-1e-10) && q < T(1e-10)) ? lr : M<T>::expm1(q * lr) / q);
   }
   return ri + seg;
 }

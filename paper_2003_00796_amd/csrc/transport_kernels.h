@@ -435,10 +435,11 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const uint32_t v = vlin(a, p.ix);
   const T rho = a.rho[v];
   // step control: maximum mass step and hard-event majorant over [elo, e]
-  const Grid<T> g = grid_at(tb, M<T>::log(e));
+  const T le = M<T>::log(e);
+  const Grid<T> g = grid_at(tb, le);
   const T ss = interp(tab, nt, base + O_LS, g, e, T(0));
   const T tau_max = a.c2 * e / ss;
-  const T r0 = range_at(tab, nt, base, g, e);
+  const T r0 = range_at(tab, nt, base, g, e, le, tb.lemin, tb.dl);
   T elo = r0 - tau_max > T(0) ? range_inv(tab, nt, base, r0 - tau_max, g.i) : tb.emin;
   if (elo > e) elo = e;
   const T smaj = majorant(tb, tab, base, lep, elo, g, e);
@@ -680,7 +681,6 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   c->run_first = run_first;
   c->adm = adm;
   c->occupied = 0ull;
-  c->n_occ = 0ull;
   c->take_e = 0u;
 }
 
@@ -689,13 +689,13 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
 // Sum q^2 += q^2 (Eq. (1)-(3)); slots are cleared for the next chunk
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, uint64_t nslot, double* sum_q,
-                        double* sum_q2, Counters* cnt, int test_mode, double* hist_led, uint64_t n_run) {
-  const uint64_t n = min(cnt->n_occ, nslot);
+__global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
+                        int test_mode, double* hist_led, uint64_t n_run) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint64_t s = occ_list[i];
+  uint32_t occ = 0;
+  for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
     const uint64_t k = keys[s];
+    if (k == kEmptyKey) continue;
     const double q = vals[s];
     const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
     unsafeAtomicAdd(&sum_q[v], q);
@@ -706,8 +706,10 @@ __global__ void k_flush(uint64_t* keys, double* vals, const uint32_t* occ_list, 
     }
     keys[s] = kEmptyKey;
     vals[s] = 0.0;
+    ++occ;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->occupied = n;
+  occ = wave_sum(occ);
+  if (__lane_id() == 0 && occ) atomicAdd((unsigned long long*)&cnt->occupied, (unsigned long long)occ);
 }
 
 // density gradient helpers: loss weights per MeV, mean of Q_h, final terms
