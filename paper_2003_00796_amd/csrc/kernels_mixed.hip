@@ -1,6 +1,8 @@
 // kernels_mixed.hip -- FP32-physics instantiation of the transport kernels
 // (positions, boundary distances, remaining mass thickness and tallies stay
 // FP64).  Multiply-add contraction is allowed here.
+// the FP32 step kernel fits 128 registers: bound it to 4 waves per SIMD
+#define MCX_ESTEP_WAVES 4
 #include "transport_kernels.h"
 
 namespace mcx {
