@@ -2,7 +2,9 @@
 // (positions, boundary distances, remaining mass thickness and tallies stay
 // FP64).  Multiply-add contraction is allowed here.
 // the FP32 step kernel fits 128 registers: bound it to 4 waves per SIMD
+#ifndef MCX_ESTEP_WAVES
 #define MCX_ESTEP_WAVES 4
+#endif
 #include "transport_kernels.h"
 
 namespace mcx {

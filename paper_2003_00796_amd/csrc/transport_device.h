@@ -64,13 +64,37 @@ constexpr bool is_fp64() { return std::is_same<T, double>::value; }
 // ---------------------------------------------------------------------------
 // counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11)
 // key = (seed, history id); counter = (draw / 2, uid_lo, uid_hi, 0);
-// draw d is 64-bit word d % 2 of the call.  One call is cached per particle.
+// draw d is 64-bit word d % 2 of the call.
+//
+// A particle holds up to kRngPairs calls (2 kRngPairs draws) starting at an
+// even draw index.  The e+- step refills all of them at once at the start of
+// a step (`rng_refill`), so that the one inlined Philox site there runs with
+// every live lane; a draw that is not held computes its own call (the rest of
+// the kernels draw only this way).  FP32 paths keep only the upper 32 bits of
+// each 64-bit draw word: their uniforms use its top 23 bits.
 // ---------------------------------------------------------------------------
+#ifndef MCX_RNG_PAIRS
+#define MCX_RNG_PAIRS 4
+#endif
+constexpr int kRngPairs = MCX_RNG_PAIRS;
+
+template <typename T>
+struct RngWord {
+  using type = uint64_t;
+};
+template <>
+struct RngWord<float> {
+  using type = uint32_t;
+};
+
+template <typename T>
 struct Rng {
+  using W = typename RngWord<T>::type;
   uint32_t k0, k1, u0, u1;
-  uint32_t ctr;     // next draw index
-  uint32_t cpair;   // Philox call held in w[] (~0u: none)
-  uint32_t w0, w1, w2, w3;
+  uint32_t ctr;   // next draw index
+  uint32_t base;  // draw index of w[0] (even)
+  uint32_t nw;    // draws held in w[] (0 or an even number <= 2 kRngPairs)
+  W w[2 * kRngPairs];
 };
 
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
@@ -89,29 +113,69 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
   o[0] = c0; o[1] = c1; o[2] = c2; o[3] = c3;
 }
 
-__device__ __forceinline__ uint64_t rng_word(Rng& r) {
-  const uint32_t pair = r.ctr >> 1;
-  if (pair != r.cpair) {
-    uint32_t o[4];
-    philox10(pair, r.u0, r.u1, 0u, r.k0, r.k1, o);
-    r.w0 = o[0]; r.w1 = o[1]; r.w2 = o[2]; r.w3 = o[3];
-    r.cpair = pair;
-  }
-  const uint64_t w = (r.ctr & 1u) ? ((uint64_t(r.w3) << 32) | r.w2) : ((uint64_t(r.w1) << 32) | r.w0);
-  r.ctr++;
-  return w;
+// the two draw words of one call
+__device__ __forceinline__ void pair_words(const uint32_t* o, uint64_t* w0, uint64_t* w1) {
+  *w0 = (uint64_t(o[1]) << 32) | o[0];
+  *w1 = (uint64_t(o[3]) << 32) | o[2];
+}
+__device__ __forceinline__ void pair_words(const uint32_t* o, uint32_t* w0, uint32_t* w1) {
+  *w0 = o[1];
+  *w1 = o[3];
 }
 
 template <typename T>
-__device__ __forceinline__ T uni(Rng& r);
-template <>
-__device__ __forceinline__ double uni<double>(Rng& r) {
-  return (double(rng_word(r) >> 11) + 0.5) * 0x1.0p-53;
+__device__ __forceinline__ void rng_init(Rng<T>& r, uint32_t seed, uint32_t hist, uint64_t uid, uint32_t ctr) {
+  r.k0 = seed; r.k1 = hist;
+  r.u0 = uint32_t(uid); r.u1 = uint32_t(uid >> 32);
+  r.ctr = ctr;
+  r.base = 0u;
+  r.nw = 0u;
 }
-// FP32: top 23 bits of the same word, ((w >> 41) + 1/2) 2^-23, exact in FP32
+
+// compute the kRngPairs calls from the one holding draw ctr on
+template <typename T>
+__device__ __forceinline__ void rng_refill(Rng<T>& r) {
+  const uint32_t pair = r.ctr >> 1;
+#pragma unroll
+  for (int j = 0; j < kRngPairs; ++j) {
+    uint32_t o[4];
+    philox10(pair + uint32_t(j), r.u0, r.u1, 0u, r.k0, r.k1, o);
+    pair_words(o, &r.w[2 * j], &r.w[2 * j + 1]);
+  }
+  r.base = pair << 1;
+  r.nw = 2u * kRngPairs;
+}
+
+// next draw word (unrolled selects: no runtime-indexed private array)
+template <typename T>
+__device__ __forceinline__ typename RngWord<T>::type rng_next(Rng<T>& r) {
+  uint32_t off = r.ctr - r.base;
+  if (!(off < r.nw)) {
+    uint32_t o[4];
+    const uint32_t pair = r.ctr >> 1;
+    philox10(pair, r.u0, r.u1, 0u, r.k0, r.k1, o);
+    pair_words(o, &r.w[0], &r.w[1]);
+    r.base = pair << 1;
+    r.nw = 2u;
+    off = r.ctr & 1u;
+  }
+  typename RngWord<T>::type v = r.w[0];
+#pragma unroll
+  for (int j = 1; j < 2 * kRngPairs; ++j) v = off == uint32_t(j) ? r.w[j] : v;
+  r.ctr++;
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T uni(Rng<T>& r);
 template <>
-__device__ __forceinline__ float uni<float>(Rng& r) {
-  return (float(uint32_t(rng_word(r) >> 41)) + 0.5f) * 0x1.0p-23f;
+__device__ __forceinline__ double uni<double>(Rng<double>& r) {
+  return (double(rng_next(r) >> 11) + 0.5) * 0x1.0p-53;
+}
+// FP32: top 23 bits of the same 64-bit word, ((w >> 41) + 1/2) 2^-23, exact in FP32
+template <>
+__device__ __forceinline__ float uni<float>(Rng<float>& r) {
+  return (float(rng_next(r) >> 9) + 0.5f) * 0x1.0p-23f;
 }
 
 // SplitMix64 finaliser (Steele et al., OOPSLA'14)
@@ -138,7 +202,7 @@ struct Part {
   uint32_t hist;
   uint64_t uid;
   uint64_t hash;
-  Rng rng;
+  Rng<T> rng;
 };
 
 template <typename T>
@@ -154,10 +218,7 @@ __device__ __forceinline__ void load_part(const KArgs<T>& a, const Bank<T>& b, u
   p.type = fl & 3u;
   p.nchild = fl >> 2;
   p.hash = a.test_mode ? b.hash[i] : 0ull;
-  p.rng.k0 = a.seed; p.rng.k1 = p.hist;
-  p.rng.u0 = uint32_t(p.uid); p.rng.u1 = uint32_t(p.uid >> 32);
-  p.rng.ctr = b.ctr[i];
-  p.rng.cpair = ~0u;
+  rng_init(p.rng, a.seed, p.hist, p.uid, b.ctr[i]);
 }
 
 template <typename T>

@@ -12,6 +12,15 @@
 #ifndef MCX_ESTEP_WAVES
 #define MCX_ESTEP_WAVES 1
 #endif
+// tail of the e+- kernel: once the input queue is empty, a wavefront keeps
+// stepping its particles for at least MCX_TAIL_MIN more steps, then writes
+// them all back as soon as fewer than MCX_TAIL_ALIVE of its lanes hold one
+#ifndef MCX_TAIL_MIN
+#define MCX_TAIL_MIN 8
+#endif
+#ifndef MCX_TAIL_ALIVE
+#define MCX_TAIL_ALIVE 16
+#endif
 
 namespace mcx {
 
@@ -59,16 +68,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
       p.uid = 1ull;
       p.nchild = 0u;
       p.hash = 0ull;
-      p.rng.k0 = a.seed; p.rng.k1 = p.hist; p.rng.u0 = 1u; p.rng.u1 = 0u;
-      p.rng.ctr = 0u; p.rng.cpair = ~0u;
+      rng_init(p.rng, a.seed, p.hist, 1ull, 0u);
       p.x[0] = s.pos[0]; p.x[1] = s.pos[1]; p.x[2] = s.pos[2];
       p.d[0] = T(s.dir[0]); p.d[1] = T(s.dir[1]); p.d[2] = T(s.dir[2]);
       if (s.kind == 1) {
-        // rectangle: both offsets use FP64 words so that the start point is
-        // the same in both precisions
-        Rng& r = p.rng;
-        const double ux = (double(rng_word(r) >> 11) + 0.5) * 0x1.0p-53;
-        const double uy = (double(rng_word(r) >> 11) + 0.5) * 0x1.0p-53;
+        // rectangle: both offsets use the FP64 words of draws 0 and 1 so that
+        // the start point is the same in both precisions
+        uint32_t o[4];
+        philox10(0u, 1u, 0u, 0u, a.seed, p.hist, o);
+        uint64_t w0, w1;
+        pair_words(o, &w0, &w1);
+        const double ux = (double(w0 >> 11) + 0.5) * 0x1.0p-53;
+        const double uy = (double(w1 >> 11) + 0.5) * 0x1.0p-53;
+        p.rng.ctr = 2u;
         p.x[0] = s.pos[0] + (ux - 0.5) * s.width[0];
         p.x[1] = s.pos[1] + (uy - 0.5) * s.width[1];
       }
@@ -228,7 +240,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
 // so that (except at the three boundaries) each wavefront runs one type
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T sample_kn(Rng& r, T e, T* cost) {
+__device__ __forceinline__ T sample_kn(Rng<T>& r, T e, T* cost) {
   const T k = e / T(kMc2);
   const T kmin = T(1) / (T(1) + T(2) * k);
   const T a1 = M<T>::log(T(1) + T(2) * k);
@@ -248,7 +260,7 @@ __device__ __forceinline__ T sample_kn(Rng& r, T e, T* cost) {
 }
 
 template <typename T>
-__device__ __forceinline__ T sample_rayleigh(Rng& r, T e, T ray_a) {
+__device__ __forceinline__ T sample_rayleigh(Rng<T>& r, T e, T ray_a) {
   const T U = (e / T(kHc)) * (e / T(kHc));
   const T c3 = -M<T>::expm1(T(-3) * M<T>::log1p(ray_a * U));
   T ct = T(1);
@@ -431,6 +443,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     return false;
   }
   ls.esteps++;
+  rng_refill(p.rng);
   const T e = p.e;
   const uint32_t v = vlin(a, p.ix);
   const T rho = a.rho[v];
@@ -508,13 +521,22 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     event(a, p, EV_STEP, v);
     return true;
   }
-  // hard event or delta: elastic, inelastic, bremsstrahlung in this order
+  // hard event or delta: elastic, inelastic, bremsstrahlung in this order.
+  // Each kind samples its own variables, then all share the azimuth draw,
+  // the rotations and the secondary (one inlined copy each).
   const T u = uni<T>(p.rng) * smaj;
   const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
   const T s_el = interp(tab, nt, base + O_LEL, g1, e1, T(0));
   const T s_in = interp(tab, nt, base + O_LIN, g1, e1, tb.thr_in[lep]);
   const T s_br = interp(tab, nt, base + O_LBR, g1, e1, tb.thr_br);
-  if (u < s_el) {
+  const int kind = u < s_el ? 1 : (u < s_el + s_in ? 2 : (u < s_el + s_in + s_br ? 3 : 0));
+  if (kind == 0) {
+    ls.delta++;
+    event(a, p, EV_STEP, v);
+    return true;
+  }
+  T cos_p = T(1), cos_c = T(1), w = T(0);  // primary and secondary polar cosines, energy lost
+  if (kind == 1) {
     ls.hard_el++;
     // screened Rutherford restricted to [mu_c, 1]
     const T p2 = e1 * (e1 + T(2.0 * kMc2));
@@ -528,64 +550,65 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     const T ia = T(1) / (muc + eta), ib = T(1) / (T(1) + eta);
     T m = T(1) / (ia - uni<T>(p.rng) * (ia - ib)) - eta;
     m = m < T(0) ? T(0) : (m > T(1) ? T(1) : m);
-    const T ph = T(2.0 * kPi) * uni<T>(p.rng);
-    rotate(p.d, T(1) - T(2) * m, ph);
-    event(a, p, EV_HARD_EL, v);
-  } else if (u < s_el + s_in) {
+    cos_p = T(1) - T(2) * m;
+  } else if (kind == 2) {
     stat_add(bs, S_HARD_IN);
+    // Moller (e-) or Bhabha (e+) energy transfer k = W/E above kc = Wcc/E:
+    // proposal ~ 1/k^2 on [kc, 1/2] (e-) or [kc, 1] (e+), then rejection
     const T kc = a.wcc / e1;
     const T gm = T(1) + e1 / T(kMc2);
     const T aa = ((gm - T(1)) / gm) * ((gm - T(1)) / gm);
+    const T gp = gm + T(1);
+    const T b1 = aa * (T(2) * gp * gp - T(1)) / (gm * gm - T(1));
+    const T b2 = aa * (T(3) * gp * gp + T(1)) / (gp * gp);
+    const T b3 = aa * T(2) * (gm - T(1)) * gm / (gp * gp);
+    const T b4 = aa * (gm - T(1)) * (gm - T(1)) / (gp * gp);
+    const T span = lep == 0 ? T(1) - T(2) * kc : T(1) - kc;
     T k = kc;
-    if (lep == 0) {
-      for (int tries = 0; tries < kMaxTries; ++tries) {
-        const T uu = uni<T>(p.rng), ua = uni<T>(p.rng);
-        k = kc / (T(1) - uu * (T(1) - T(2) * kc));
+    for (int tries = 0; tries < kMaxTries; ++tries) {
+      const T uu = uni<T>(p.rng), ua = uni<T>(p.rng);
+      k = kc / (T(1) - uu * span);
+      bool ok;
+      if (lep == 0) {
         const T f = T(1) / (k * k) + T(1) / ((T(1) - k) * (T(1) - k)) + aa - (T(1) - aa) / (k * (T(1) - k));
-        if (ua * T(2.25) <= k * k * f) break;
-      }
-    } else {
-      const T gp = gm + T(1);
-      const T b1 = aa * (T(2) * gp * gp - T(1)) / (gm * gm - T(1));
-      const T b2 = aa * (T(3) * gp * gp + T(1)) / (gp * gp);
-      const T b3 = aa * T(2) * (gm - T(1)) * gm / (gp * gp);
-      const T b4 = aa * (gm - T(1)) * (gm - T(1)) / (gp * gp);
-      for (int tries = 0; tries < kMaxTries; ++tries) {
-        const T uu = uni<T>(p.rng), ua = uni<T>(p.rng);
-        k = kc / (T(1) - uu * (T(1) - kc));
+        ok = ua * T(2.25) <= k * k * f;
+      } else {
         const T gg = T(1) - b1 * k + b2 * k * k - b3 * k * k * k + b4 * k * k * k * k;
-        if (ua <= gg) break;
+        ok = ua <= gg;
       }
+      if (ok) break;
     }
-    const T ph = T(2.0 * kPi) * uni<T>(p.rng);
-    const T w = k * e1;
-    const T cp = binary_cos(e1, w, true), cs = binary_cos(e1, w, false);
-    T ds[3] = {p.d[0], p.d[1], p.d[2]};
-    rotate(ds, cs, ph + T(kPi));
-    rotate(p.d, cp, ph);
-    p.e = e1 - w;
-    make_child(a, p, c1, ELECTRON, w, ds, acc, ls, bs);
-    event(a, p, EV_HARD_IN, v);
-  } else if (u < s_el + s_in + s_br) {
-    stat_add(bs, S_HARD_BR);
-    const T w = a.wcr * M<T>::pow(e1 / a.wcr, uni<T>(p.rng));
-    const T ct = leading_angle(beta_of(e1), uni<T>(p.rng));
-    const T ph = T(2.0 * kPi) * uni<T>(p.rng);
-    T dg[3] = {p.d[0], p.d[1], p.d[2]};
-    rotate(dg, ct, ph);
-    p.e = e1 - w;
-    make_child(a, p, c1, PHOTON, w, dg, acc, ls, bs);
-    event(a, p, EV_HARD_BR, v);
+    w = k * e1;
+    cos_p = binary_cos(e1, w, true);
+    cos_c = binary_cos(e1, w, false);
   } else {
-    ls.delta++;
-    event(a, p, EV_STEP, v);
+    stat_add(bs, S_HARD_BR);
+    w = a.wcr * M<T>::pow(e1 / a.wcr, uni<T>(p.rng));
+    cos_c = leading_angle(beta_of(e1), uni<T>(p.rng));
   }
+  const T ph = T(2.0 * kPi) * uni<T>(p.rng);
+  if (kind != 1) {
+    // the secondary leaves from the direction before the event: the knock-on
+    // electron on the opposite azimuth, the photon on the drawn one
+    T dc[3] = {p.d[0], p.d[1], p.d[2]};
+    rotate(dc, cos_c, kind == 2 ? ph + T(kPi) : ph);
+    if (kind == 2) rotate(p.d, cos_p, ph);
+    p.e = e1 - w;
+    make_child(a, p, c1, kind == 2 ? ELECTRON : PHOTON, w, dc, acc, ls, bs);
+  } else {
+    rotate(p.d, cos_p, ph);
+  }
+  event(a, p, kind == 1 ? EV_HARD_EL : (kind == 2 ? EV_HARD_IN : EV_HARD_BR), v);
   return true;
 }
 
 // The e+- kernel keeps its lanes busy: a lane whose particle is gone (or has
 // used its step budget and is written back to the output queue) takes the
-// next record of the input queue, until the queue is exhausted.
+// next record of the input queue, until the queue is exhausted.  Track lengths
+// are long-tailed, so a wavefront whose queue has run dry would otherwise run
+// its few longest tracks to the end with most lanes idle: after a short tail
+// it writes them back instead, and they continue, among full wavefronts, in
+// the next iteration.
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a, int par) {
   const uint32_t n = min(a.cnt->n[q_ein(par)], a.cap);
@@ -602,7 +625,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
   Part<T> p;
   DepAcc acc = dep_init();
   bool alive = false, taking = true;
-  uint32_t used = 0;
+  uint32_t used = 0, dry = 0;
   for (;;) {
     // lanes without a particle take the next input records (one atomic per wave)
     if (taking) {
@@ -616,6 +639,8 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
         used = 0;
         ls.visits++;
       }
+    } else {
+      ++dry;
     }
     if (!__any(alive)) break;
     Child<T> c1, c2;
@@ -636,7 +661,8 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     if (c2.on && s2 != ~0u) store_child(a, a.q[gg], s2, p, c2);
     ls.writes += uint32_t(c1.on) + uint32_t(c2.on);
     // a particle that used its budget goes back to the output queue
-    const bool park = alive && used >= a.steps;
+    const bool tail = dry >= MCX_TAIL_MIN && __popcll(__ballot(alive)) < MCX_TAIL_ALIVE;  // wave-uniform
+    const bool park = alive && (used >= a.steps || tail);
     const uint32_t so = append(a, ge, park);
     if (park && so != ~0u) store_part(a, a.q[ge], so, p);
     ls.writes += uint32_t(park);
