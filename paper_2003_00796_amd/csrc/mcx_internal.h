@@ -73,13 +73,20 @@ enum Overflow : uint32_t { OVF_QUEUE = 1u, OVF_TALLY = 2u, OVF_SOURCE = 4u, OVF_
 // bound on rejection-sampling attempts (acceptance is >= 0.3 for every sampler)
 constexpr int kMaxTries = 1000;
 
+// a counter alone on its 128-byte cache line: the queue counters take atomics
+// from every wavefront of a launch, and counters sharing a line would queue
+// behind each other in one L2 channel
+struct alignas(128) LineCount {
+  uint32_t v;
+};
+
 struct Counters {
-  uint32_t n[Q_NQ];        // queue occupancy
+  LineCount n[Q_NQ];       // queue occupancy
+  LineCount take_e;        // records of the e+- input queue reserved in this iteration
   uint32_t overflow;       // Overflow bits
   uint32_t done;           // chunk finished
   uint32_t adm;            // histories admitted by the next source launch
   uint32_t iter;
-  uint32_t take_e;         // records of the e+- input queue taken in this iteration
   uint64_t cursor;         // next history id to admit
   uint64_t chunk_end;      // end of the current chunk (exclusive)
   uint64_t run_first;      // first history id of the current mcx_run call

@@ -341,38 +341,55 @@ __device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long lon
 // ---------------------------------------------------------------------------
 // tally: (history, voxel) -> score, open addressing with linear probing
 // ---------------------------------------------------------------------------
-// One global round trip per insertion: compare-and-swap the key into its
-// slot (an empty slot is claimed, a slot holding this key is found), then add
-// the score without waiting for the result.  The flush scans the table.
+// An insertion is a compare-and-swap of the key into its slot (an empty slot
+// is claimed, a slot holding this key is found), then an add of the score
+// that nobody waits for.  The flush scans the table.
 template <typename T>
-__device__ __forceinline__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
-  ls.inserts++;
-  uint64_t slot = mix64(key) & a.hmask;
+__device__ __forceinline__ void tally_probe(const KArgs<T>& a, uint64_t key, double q, uint64_t slot, uint64_t k) {
   for (int probe = 0; probe < 4096; ++probe) {
-    const uint64_t k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
-                                 (unsigned long long)key);
     if (k == kEmptyKey || k == key) {
       unsafeAtomicAdd(&a.hvals[slot], q);
       return;
     }
     slot = (slot + 1) & a.hmask;
+    k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey, (unsigned long long)key);
   }
   atomicOr(&a.cnt->overflow, uint32_t(OVF_TALLY));
 }
 
-// deposits of one particle are summed in registers while they stay in one
+template <typename T>
+__device__ __forceinline__ uint64_t tally_slot(const KArgs<T>& a, uint64_t key) {
+  return mix64(key) & a.hmask;
+}
+
+template <typename T>
+__device__ __forceinline__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
+  ls.inserts++;
+  const uint64_t slot = tally_slot(a, key);
+  const uint64_t k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
+                               (unsigned long long)key);
+  tally_probe(a, key, q, slot, k);
+}
+
+// Deposits of one particle are summed in registers while they stay in one
 // voxel; when the voxel (or history) changes, the finished sum becomes
-// `pending` and is inserted at the caller's next flush point, so each kernel
-// has one inlined copy of the table insertion (all deposits of one Class II
-// step or one photon interaction fall in the same voxel)
+// `pending`.  In the e+- kernel the pending entry's compare-and-swap is
+// issued at the end of a step and its result examined at the start of the
+// next one, so the round trip overlaps the rest of the iteration; the other
+// kernels insert at their end.  All deposits of one Class II step or one
+// photon interaction fall in the same voxel.
+constexpr uint32_t kNotIssued = ~0u;
+
 struct DepAcc {
   uint64_t key;
   double q;
-  uint64_t pkey;  // pending (finished) entry
+  uint64_t pkey;   // pending (finished) entry
   double pq;
+  uint64_t fres;   // result of the pending entry's compare-and-swap
+  uint32_t fslot;  // its slot, or kNotIssued
 };
 
-__device__ __forceinline__ DepAcc dep_init() { return DepAcc{kEmptyKey, 0.0, kEmptyKey, 0.0}; }
+__device__ __forceinline__ DepAcc dep_init() { return DepAcc{kEmptyKey, 0.0, kEmptyKey, 0.0, kEmptyKey, kNotIssued}; }
 
 template <typename T>
 __device__ __forceinline__ void dep_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
@@ -386,18 +403,41 @@ __device__ __forceinline__ void dep_insert(const KArgs<T>& a, uint64_t key, doub
   }
 }
 
-// insert the pending entry (call at one convergent point per step)
+// complete the pending entry whose compare-and-swap is in flight
 template <typename T>
-__device__ __forceinline__ void dep_flush_pending(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
-  dep_insert(a, acc.pkey, acc.pq, ls);
+__device__ __forceinline__ void dep_resolve(const KArgs<T>& a, DepAcc& acc) {
+  if (acc.fslot == kNotIssued) return;
+  tally_probe(a, acc.pkey, acc.pq, uint64_t(acc.fslot), acc.fres);
   acc.pkey = kEmptyKey;
   acc.pq = 0.0;
+  acc.fslot = kNotIssued;
+}
+
+// start the insertion of the pending entry (call at one convergent point per
+// step, after dep_resolve earlier in the same step)
+template <typename T>
+__device__ __forceinline__ void dep_flush_pending(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
+  if (acc.pkey == kEmptyKey) return;
+  if (a.mode != 0 || acc.pq == 0.0) {
+    dep_insert(a, acc.pkey, acc.pq, ls);
+    acc.pkey = kEmptyKey;
+    acc.pq = 0.0;
+    return;
+  }
+  ls.inserts++;
+  const uint64_t slot = tally_slot(a, acc.pkey);
+  acc.fslot = uint32_t(slot);
+  acc.fres = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
+                       (unsigned long long)acc.pkey);
 }
 
 // insert everything (end of a kernel)
 template <typename T>
 __device__ __forceinline__ void dep_flush(const KArgs<T>& a, DepAcc& acc, LaneStats& ls) {
-  dep_flush_pending(a, acc, ls);
+  dep_resolve(a, acc);
+  dep_insert(a, acc.pkey, acc.pq, ls);
+  acc.pkey = kEmptyKey;
+  acc.pq = 0.0;
   dep_insert(a, acc.key, acc.q, ls);
   acc.key = kEmptyKey;
   acc.q = 0.0;
@@ -415,7 +455,11 @@ __device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStat
   if (key != acc.key) {
     if (acc.pkey != kEmptyKey) {
       // a second voxel change before the caller flushed: insert now
-      dep_insert(a, acc.pkey, acc.pq, ls);
+      if (acc.fslot != kNotIssued) {
+        dep_resolve(a, acc);
+      } else {
+        dep_insert(a, acc.pkey, acc.pq, ls);
+      }
     }
     acc.pkey = acc.key;
     acc.pq = acc.q;

@@ -32,7 +32,7 @@ __device__ __forceinline__ int q_eout(int par) { return Q_E0 + 1 - par; }
 
 template <typename T>
 __device__ __forceinline__ uint32_t append(const KArgs<T>& a, int q, bool pred) {
-  const uint32_t slot = wave_append(&a.cnt->n[q], pred);
+  const uint32_t slot = wave_append(&a.cnt->n[q].v, pred);
   if (pred && slot >= a.cap) {
     atomicOr(&a.cnt->overflow, uint32_t(OVF_QUEUE));
     return ~0u;
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
-  const uint32_t n = min(a.cnt->n[q_gin(par)], a.cap);
+  const uint32_t n = min(a.cnt->n[q_gin(par)].v, a.cap);
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* tab = reinterpret_cast<T*>(smem);
@@ -296,8 +296,8 @@ __device__ __forceinline__ void make_child(const KArgs<T>& a, Part<T>& p, Child<
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
   Counters* C = a.cnt;
-  const uint32_t n0 = min(C->n[Q_KC], a.cap), n1 = min(C->n[Q_KP], a.cap);
-  const uint32_t n2 = min(C->n[Q_KR], a.cap), n3 = min(C->n[Q_KX], a.cap);
+  const uint32_t n0 = min(C->n[Q_KC].v, a.cap), n1 = min(C->n[Q_KP].v, a.cap);
+  const uint32_t n2 = min(C->n[Q_KR].v, a.cap), n3 = min(C->n[Q_KX].v, a.cap);
   const uint32_t e1 = n0 + n1, e2 = e1 + n2, ntot = e2 + n3;
   if (blockIdx.x * blockDim.x >= ntot) return;
   __shared__ BlockStats bs;
@@ -604,14 +604,17 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
 
 // The e+- kernel keeps its lanes busy: a lane whose particle is gone (or has
 // used its step budget and is written back to the output queue) takes the
-// next record of the input queue, until the queue is exhausted.  Track lengths
-// are long-tailed, so a wavefront whose queue has run dry would otherwise run
-// its few longest tracks to the end with most lanes idle: after a short tail
-// it writes them back instead, and they continue, among full wavefronts, in
-// the next iteration.
+// next record of the input queue, until the queue is exhausted.  A wavefront
+// reserves input records kTakeBatch at a time and hands them to its lanes
+// over the following iterations.  Track lengths are long-tailed, so a
+// wavefront whose queue has run dry would otherwise run its few longest tracks
+// to the end with most lanes idle: after a short tail it writes them back
+// instead, and they continue, among full wavefronts, in the next iteration.
+constexpr uint32_t kTakeBatch = 32;
+
 template <typename T>
 __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a, int par) {
-  const uint32_t n = min(a.cnt->n[q_ein(par)], a.cap);
+  const uint32_t n = min(a.cnt->n[q_ein(par)].v, a.cap);
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* tab = reinterpret_cast<T*>(smem);
@@ -622,17 +625,33 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
   __syncthreads();
   const Bank<T>& in = a.q[q_ein(par)];
   const int ge = q_eout(par), gg = q_gout(par);
+  const uint32_t lane = __lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
   Part<T> p;
   DepAcc acc = dep_init();
   bool alive = false, taking = true;
   uint32_t used = 0, dry = 0;
+  uint32_t rbase = 0, rleft = 0;  // the wavefront's reserved input records [rbase, rbase + rleft)
   for (;;) {
-    // lanes without a particle take the next input records (one atomic per wave)
     if (taking) {
+      const uint64_t needm = __ballot(!alive);
+      const uint32_t cnt = uint32_t(__popcll(needm));
+      const uint32_t rank = uint32_t(__popcll(needm & below));
+      uint32_t idx = rbase + rank;
+      if (cnt > rleft) {  // wave-uniform: reserve more
+        const uint32_t r = max(cnt - rleft, kTakeBatch);
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(&a.cnt->take_e.v, r);
+        b = __shfl(b, 0);
+        if (rank >= rleft) idx = b + (rank - rleft);
+        rbase = b + (cnt - rleft);
+        rleft = r - (cnt - rleft);
+      } else {
+        rbase += cnt;
+        rleft -= cnt;
+      }
       const bool need = !alive;
-      const uint32_t idx = wave_append(&a.cnt->take_e, need);
-      const uint32_t first = __shfl(idx, int(__ffsll((unsigned long long)__ballot(need)) - 1));
-      if (__ballot(need) != 0ull && first >= n) taking = false;  // wave-uniform
+      if (__ballot(need && idx >= n) != 0ull) taking = false;  // wave-uniform
       if (need && idx < n) {
         load_part(a, in, idx, p);
         alive = true;
@@ -643,6 +662,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
       ++dry;
     }
     if (!__any(alive)) break;
+    dep_resolve(a, acc);  // the insertion issued in the previous step
     Child<T> c1, c2;
     c1.on = false;
     c2.on = false;
@@ -651,21 +671,32 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
       ++used;
     }
     dep_flush_pending(a, acc, ls);
-    // secondaries of this step, wavefront-aggregated
-    const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
-    const uint32_t se = append(a, ge, c1e);
-    if (c1e && se != ~0u) store_child(a, a.q[ge], se, p, c1);
-    const uint32_t sg = append(a, gg, c1g);
-    if (c1g && sg != ~0u) store_child(a, a.q[gg], sg, p, c1);
-    const uint32_t s2 = append(a, gg, c2.on);
-    if (c2.on && s2 != ~0u) store_child(a, a.q[gg], s2, p, c2);
-    ls.writes += uint32_t(c1.on) + uint32_t(c2.on);
-    // a particle that used its budget goes back to the output queue
+    // secondaries of this step and particles written back: one atomic per
+    // output queue and wavefront, both in flight together
     const bool tail = dry >= MCX_TAIL_MIN && __popcll(__ballot(alive)) < MCX_TAIL_ALIVE;  // wave-uniform
     const bool park = alive && (used >= a.steps || tail);
-    const uint32_t so = append(a, ge, park);
-    if (park && so != ~0u) store_part(a, a.q[ge], so, p);
-    ls.writes += uint32_t(park);
+    const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
+    const uint64_t me1 = __ballot(c1e), mep = __ballot(park), mg1 = __ballot(c1g), mg2 = __ballot(c2.on);
+    const uint32_t ne1 = uint32_t(__popcll(me1)), ng1 = uint32_t(__popcll(mg1));
+    const uint32_t ne = ne1 + uint32_t(__popcll(mep)), ng = ng1 + uint32_t(__popcll(mg2));
+    if (ne + ng != 0u) {  // wave-uniform
+      uint32_t be = 0, bg = 0;
+      if (lane == 0) {
+        if (ne) be = atomicAdd(&a.cnt->n[ge].v, ne);
+        if (ng) bg = atomicAdd(&a.cnt->n[gg].v, ng);
+      }
+      be = __shfl(be, 0);
+      bg = __shfl(bg, 0);
+      const uint32_t s1 = c1e ? be + uint32_t(__popcll(me1 & below)) : bg + uint32_t(__popcll(mg1 & below));
+      const uint32_t s2 = bg + ng1 + uint32_t(__popcll(mg2 & below));
+      const uint32_t so = be + ne1 + uint32_t(__popcll(mep & below));
+      const bool ov = (c1.on && s1 >= a.cap) || (c2.on && s2 >= a.cap) || (park && so >= a.cap);
+      if (ov) atomicOr(&a.cnt->overflow, uint32_t(OVF_QUEUE));
+      if (c1.on && s1 < a.cap) store_child(a, a.q[c1e ? ge : gg], s1, p, c1);
+      if (c2.on && s2 < a.cap) store_child(a, a.q[gg], s2, p, c2);
+      if (park && so < a.cap) store_part(a, a.q[ge], so, p);
+    }
+    ls.writes += uint32_t(c1.on) + uint32_t(c2.on) + uint32_t(park);
     if (park) alive = false;
   }
   dep_flush(a, acc, ls);
@@ -678,14 +709,14 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
 template <typename T>
 __global__ void k_advance(Counters* c, int par, uint32_t target, uint32_t cap) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  c->n[Q_G0 + 1 - par] = min(c->n[Q_G0 + 1 - par], cap);
-  c->n[Q_E0 + 1 - par] = min(c->n[Q_E0 + 1 - par], cap);
-  c->n[Q_G0 + par] = 0u;
-  c->n[Q_E0 + par] = 0u;
-  c->n[Q_KC] = c->n[Q_KP] = c->n[Q_KR] = c->n[Q_KX] = 0u;
-  c->take_e = 0u;
+  c->n[Q_G0 + 1 - par].v = min(c->n[Q_G0 + 1 - par].v, cap);
+  c->n[Q_E0 + 1 - par].v = min(c->n[Q_E0 + 1 - par].v, cap);
+  c->n[Q_G0 + par].v = 0u;
+  c->n[Q_E0 + par].v = 0u;
+  c->n[Q_KC].v = c->n[Q_KP].v = c->n[Q_KR].v = c->n[Q_KX].v = 0u;
+  c->take_e.v = 0u;
   c->cursor += c->adm;
-  const uint32_t pop = c->n[Q_G0 + 1 - par] + c->n[Q_E0 + 1 - par];
+  const uint32_t pop = c->n[Q_G0 + 1 - par].v + c->n[Q_E0 + 1 - par].v;
   const uint64_t rem = c->chunk_end - c->cursor;
   uint64_t adm = target > pop ? uint64_t(target - pop) : 0ull;
   if (adm > rem) adm = rem;
@@ -698,7 +729,7 @@ __global__ void k_advance(Counters* c, int par, uint32_t target, uint32_t cap) {
 template <typename T>
 __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int q = 0; q < Q_NQ; ++q) c->n[q] = 0u;
+  for (int q = 0; q < Q_NQ; ++q) c->n[q].v = 0u;
   c->overflow = 0u;
   c->done = 0u;
   c->iter = 0u;
@@ -707,7 +738,7 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   c->run_first = run_first;
   c->adm = adm;
   c->occupied = 0ull;
-  c->take_e = 0u;
+  c->take_e.v = 0u;
 }
 
 // ---------------------------------------------------------------------------
