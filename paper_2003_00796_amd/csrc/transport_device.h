@@ -66,7 +66,7 @@ constexpr bool is_fp64() { return std::is_same<T, double>::value; }
 // key = (seed, history id); counter = (draw / 2, uid_lo, uid_hi, 0);
 // draw d is 64-bit word d % 2 of the call.
 //
-// A particle holds up to kRngPairs calls (2 kRngPairs draws) starting at an
+// A particle holds up to rng_pairs<T>() calls (two draws each) starting at an
 // even draw index.  The e+- step refills all of them at once at the start of
 // a step (`rng_refill`), so that the one inlined Philox site there runs with
 // every live lane; a draw that is not held computes its own call (the rest of
@@ -76,7 +76,12 @@ constexpr bool is_fp64() { return std::is_same<T, double>::value; }
 #ifndef MCX_RNG_PAIRS
 #define MCX_RNG_PAIRS 4
 #endif
-constexpr int kRngPairs = MCX_RNG_PAIRS;
+#ifndef MCX_RNG_PAIRS_FP64
+#define MCX_RNG_PAIRS_FP64 2
+#endif
+// calls held per particle: FP64 draw words take twice the registers
+template <typename T>
+constexpr int rng_pairs() { return std::is_same<T, double>::value ? MCX_RNG_PAIRS_FP64 : MCX_RNG_PAIRS; }
 
 template <typename T>
 struct RngWord {
@@ -93,8 +98,8 @@ struct Rng {
   uint32_t k0, k1, u0, u1;
   uint32_t ctr;   // next draw index
   uint32_t base;  // draw index of w[0] (even)
-  uint32_t nw;    // draws held in w[] (0 or an even number <= 2 kRngPairs)
-  W w[2 * kRngPairs];
+  uint32_t nw;    // draws held in w[] (0 or an even number <= 2 rng_pairs<T>())
+  W w[2 * rng_pairs<T>()];
 };
 
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
@@ -132,18 +137,18 @@ __device__ __forceinline__ void rng_init(Rng<T>& r, uint32_t seed, uint32_t hist
   r.nw = 0u;
 }
 
-// compute the kRngPairs calls from the one holding draw ctr on
+// compute the rng_pairs<T>() calls from the one holding draw ctr on
 template <typename T>
 __device__ __forceinline__ void rng_refill(Rng<T>& r) {
   const uint32_t pair = r.ctr >> 1;
 #pragma unroll
-  for (int j = 0; j < kRngPairs; ++j) {
+  for (int j = 0; j < rng_pairs<T>(); ++j) {
     uint32_t o[4];
     philox10(pair + uint32_t(j), r.u0, r.u1, 0u, r.k0, r.k1, o);
     pair_words(o, &r.w[2 * j], &r.w[2 * j + 1]);
   }
   r.base = pair << 1;
-  r.nw = 2u * kRngPairs;
+  r.nw = 2u * rng_pairs<T>();
 }
 
 // next draw word (unrolled selects: no runtime-indexed private array)
@@ -161,7 +166,7 @@ __device__ __forceinline__ typename RngWord<T>::type rng_next(Rng<T>& r) {
   }
   typename RngWord<T>::type v = r.w[0];
 #pragma unroll
-  for (int j = 1; j < 2 * kRngPairs; ++j) v = off == uint32_t(j) ? r.w[j] : v;
+  for (int j = 1; j < 2 * rng_pairs<T>(); ++j) v = off == uint32_t(j) ? r.w[j] : v;
   r.ctr++;
   return v;
 }
@@ -281,19 +286,19 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
 // ---------------------------------------------------------------------------
 struct BlockStats {
   unsigned long long c[S_NSTAT];
-  double e_dep, e_esc;
+  double e_esc;
 };
 
+// per-lane registers for the counters of every step or flight; the rest go
+// through LDS (stat_add), and the deposited energy is summed by the flush
 struct LaneStats {
-  uint32_t esteps, deposits, crossings, hard_el, delta, flights, inserts, visits, writes;
-  double e_dep;
+  uint32_t esteps, deposits, flights, crossings, inserts;
 };
 
 __device__ __forceinline__ void stats_init(BlockStats* s, LaneStats& l) {
   for (int i = threadIdx.x; i < S_NSTAT; i += blockDim.x) s->c[i] = 0ull;
-  if (threadIdx.x == 0) { s->e_dep = 0.0; s->e_esc = 0.0; }
-  l.esteps = l.deposits = l.crossings = l.hard_el = l.delta = l.flights = l.inserts = l.visits = l.writes = 0u;
-  l.e_dep = 0.0;
+  if (threadIdx.x == 0) s->e_esc = 0.0;
+  l.esteps = l.deposits = l.flights = l.crossings = l.inserts = 0u;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -309,29 +314,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // every thread of the block must call this (after its last event)
 __device__ __forceinline__ void stats_flush(BlockStats* s, const LaneStats& l, Counters* cnt) {
-  const uint32_t es = wave_sum(l.esteps), de = wave_sum(l.deposits), cr = wave_sum(l.crossings);
-  const uint32_t he = wave_sum(l.hard_el), dl = wave_sum(l.delta), fl = wave_sum(l.flights);
-  const uint32_t in = wave_sum(l.inserts), vi = wave_sum(l.visits), wr = wave_sum(l.writes);
-  const double ed = wave_sum(l.e_dep);
+  const uint32_t es = wave_sum(l.esteps), de = wave_sum(l.deposits);
+  const uint32_t fl = wave_sum(l.flights), cr = wave_sum(l.crossings), in = wave_sum(l.inserts);
   if (__lane_id() == 0) {
+    if (in) atomicAdd(&s->c[S_INSERTS], (unsigned long long)in);
     if (es) atomicAdd(&s->c[S_ESTEPS], (unsigned long long)es);
     if (de) atomicAdd(&s->c[S_DEPOSITS], (unsigned long long)de);
-    if (cr) atomicAdd(&s->c[S_CROSSINGS], (unsigned long long)cr);
-    if (he) atomicAdd(&s->c[S_HARD_EL], (unsigned long long)he);
-    if (dl) atomicAdd(&s->c[S_DELTA], (unsigned long long)dl);
     if (fl) atomicAdd(&s->c[S_FLIGHTS], (unsigned long long)fl);
-    if (in) atomicAdd(&s->c[S_INSERTS], (unsigned long long)in);
-    if (vi) atomicAdd(&s->c[S_EVISITS], (unsigned long long)vi);
-    if (wr) atomicAdd(&s->c[S_EWRITES], (unsigned long long)wr);
-    if (ed != 0.0) atomicAdd(&s->e_dep, ed);
+    if (cr) atomicAdd(&s->c[S_CROSSINGS], (unsigned long long)cr);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < S_NSTAT; i += blockDim.x)
     if (s->c[i]) atomicAdd((unsigned long long*)&cnt->stat[i], s->c[i]);
-  if (threadIdx.x == 0) {
-    if (s->e_dep != 0.0) unsafeAtomicAdd(&cnt->e_dep, s->e_dep);
-    if (s->e_esc != 0.0) unsafeAtomicAdd(&cnt->e_esc, s->e_esc);
-  }
+  if (threadIdx.x == 0 && s->e_esc != 0.0) unsafeAtomicAdd(&cnt->e_esc, s->e_esc);
 }
 
 __device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long long v = 1ull) {
@@ -468,7 +463,6 @@ __device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStat
   }
   acc.q += double(e);
   ls.deposits++;
-  ls.e_dep += double(e);
 }
 
 // ---------------------------------------------------------------------------

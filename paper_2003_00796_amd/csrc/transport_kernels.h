@@ -460,7 +460,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const T tau_h = smaj > T(0) ? -M<T>::log(u1) / smaj : M<T>::inf();
   const bool capped = !(tau_h <= tau_max);
   const T tau_s = capped ? tau_max : tau_h;
-  const double len = double(tau_s) / double(rho);
+  const double len = double(tau_s / rho);
   const double th = double(uni<T>(p.rng)) * len;
   int ax;
   const double db = face_dist(a, p, &ax);
@@ -531,13 +531,13 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const T s_br = interp(tab, nt, base + O_LBR, g1, e1, tb.thr_br);
   const int kind = u < s_el ? 1 : (u < s_el + s_in ? 2 : (u < s_el + s_in + s_br ? 3 : 0));
   if (kind == 0) {
-    ls.delta++;
+    stat_add(bs, S_DELTA);
     event(a, p, EV_STEP, v);
     return true;
   }
   T cos_p = T(1), cos_c = T(1), w = T(0);  // primary and secondary polar cosines, energy lost
   if (kind == 1) {
-    ls.hard_el++;
+    stat_add(bs, S_HARD_EL);
     // screened Rutherford restricted to [mu_c, 1]
     const T p2 = e1 * (e1 + T(2.0 * kMc2));
     const T et = e1 + T(kMc2);
@@ -571,7 +571,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
       bool ok;
       if (lep == 0) {
         const T f = T(1) / (k * k) + T(1) / ((T(1) - k) * (T(1) - k)) + aa - (T(1) - aa) / (k * (T(1) - k));
-        ok = ua * T(2.25) <= k * k * f;
+        ok = ua * (T(1) + T(1.25) * aa) <= k * k * f;  // k^2 f <= its value at k = 1/2
       } else {
         const T gg = T(1) - b1 * k + b2 * k * k - b3 * k * k * k + b4 * k * k * k * k;
         ok = ua <= gg;
@@ -652,11 +652,12 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
       }
       const bool need = !alive;
       if (__ballot(need && idx >= n) != 0ull) taking = false;  // wave-uniform
+      const uint64_t got = __ballot(need && idx < n);
+      if (lane == 0 && got) atomicAdd(&bs.c[S_EVISITS], (unsigned long long)__popcll(got));
       if (need && idx < n) {
         load_part(a, in, idx, p);
         alive = true;
         used = 0;
-        ls.visits++;
       }
     } else {
       ++dry;
@@ -682,6 +683,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     if (ne + ng != 0u) {  // wave-uniform
       uint32_t be = 0, bg = 0;
       if (lane == 0) {
+        atomicAdd(&bs.c[S_EWRITES], (unsigned long long)(ne + ng));
         if (ne) be = atomicAdd(&a.cnt->n[ge].v, ne);
         if (ng) bg = atomicAdd(&a.cnt->n[gg].v, ng);
       }
@@ -696,7 +698,6 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
       if (c2.on && s2 < a.cap) store_child(a, a.q[gg], s2, p, c2);
       if (park && so < a.cap) store_part(a, a.q[ge], so, p);
     }
-    ls.writes += uint32_t(c1.on) + uint32_t(c2.on) + uint32_t(park);
     if (park) alive = false;
   }
   dep_flush(a, acc, ls);
@@ -750,10 +751,12 @@ __global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* su
                         int test_mode, double* hist_led, uint64_t n_run) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   uint32_t occ = 0;
+  double dep = 0.0;  // deposited energy, for the run statistics
   for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
     const uint64_t k = keys[s];
     if (k == kEmptyKey) continue;
     const double q = vals[s];
+    dep += q;
     const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
     unsafeAtomicAdd(&sum_q[v], q);
     unsafeAtomicAdd(&sum_q2[v], q * q);
@@ -766,7 +769,9 @@ __global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* su
     ++occ;
   }
   occ = wave_sum(occ);
+  dep = wave_sum(dep);
   if (__lane_id() == 0 && occ) atomicAdd((unsigned long long*)&cnt->occupied, (unsigned long long)occ);
+  if (__lane_id() == 0 && dep != 0.0) unsafeAtomicAdd(&cnt->e_dep, dep);
 }
 
 // density gradient helpers: loss weights per MeV, mean of Q_h, final terms

@@ -170,14 +170,19 @@ def test_hard_inelastic_closed_forms_vs_quadrature(p):
         assert ds == pytest.approx(pref * sh, rel=1e-7)
 
 
-def test_bhabha_rejection_envelope_bounded():
-    """The Bhabha sampler accepts with k^2 * DCS bracket, which must be <= 1."""
+def test_inelastic_rejection_envelopes_bounded():
+    """The Bhabha sampler accepts with k^2 * DCS bracket, which must be <= 1;
+    the Moller sampler with k^2 * DCS bracket / (1 + 5a/4), a = ((g-1)/g)^2,
+    which must be <= 1 on [0, 1/2] (equality at k = 1/2)."""
     k = np.linspace(1e-6, 1.0, 20001)
+    kk = np.linspace(1e-6, 0.5, 20001)
     for e in np.geomspace(0.011, 100.0, 40):
         g = 1 + e / MC2
         assert np.max(k**2 * _bhabha(k, g)) <= 1.0 + 1e-12
-        kk = np.linspace(1e-6, 0.5, 20001)
-        assert np.max(kk**2 * _moller(kk, g)) <= 2.25
+        a = ((g - 1) / g) ** 2
+        m = kk**2 * _moller(kk, g)
+        assert np.max(m) <= (1 + 1.25 * a) * (1 + 1e-12)
+        assert m[-1] == pytest.approx(1 + 1.25 * a, rel=1e-9)
 
 
 def test_elastic_closed_forms_vs_quadrature(tb):
