@@ -46,18 +46,29 @@ def build(verbose: bool = False, defines=(), lib: str = LIB, out: str = OUT) -> 
     """Compile and link; `defines` are extra -D flags for the device code."""
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     os.makedirs(out, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src, extra in UNITS:
         obj = os.path.join(out, src + ".o")
-        cmd = [hipcc] + COMMON + [f"-D{d}" for d in defines] + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
-        if verbose:
-            print(" ".join(cmd))
-        _run(cmd)
+        cmds.append([hipcc] + COMMON + [f"-D{d}" for d in defines] + extra + ["-c", "-o", obj, os.path.join(CSRC, src)])
         objs.append(obj)
     tobj = os.path.join(out, "tables.o")
-    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include"),
-          "-I", CSRC, "-c", "-o", tobj, os.path.join(CSRC, "tables.cpp")])
+    cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include"),
+                 "-I", CSRC, "-c", "-o", tobj, os.path.join(CSRC, "tables.cpp")])
     objs.append(tobj)
+    # the units are independent: compile them side by side
+    procs = []
+    for cmd in cmds:
+        if verbose:
+            print(" ".join(cmd))
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    failed = None
+    for cmd, pr in procs:
+        so, se = pr.communicate()
+        if pr.returncode != 0 and failed is None:
+            sys.stderr.write(" ".join(cmd) + "\n" + so + se)
+            failed = os.path.basename(cmd[-1])
+    if failed:
+        raise RuntimeError(f"build step failed: {failed}")
     tmp = lib + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, lib)

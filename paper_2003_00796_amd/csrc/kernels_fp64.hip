@@ -5,21 +5,31 @@
 
 namespace mcx {
 
-hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
-                            hipEvent_t* ev) {
+template <int F>
+static hipError_t launch_flavor(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                                hipEvent_t* ev) {
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(double);
   const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(double);
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_source<double, F>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(k_flight<double>, dim3(grid), dim3(block), sm_f, s, a, par);
+  hipLaunchKernelGGL((k_flight<double, F>), dim3(grid), dim3(block), sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL(k_knock<double>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_knock<double, F>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_estep<double>, dim3(grid), dim3(block), sm_e, s, a, par);
+  hipLaunchKernelGGL((k_estep<double, F>), dim3(grid), dim3(block), sm_e, s, a, par);
   if (ev) (void)hipEventRecord(ev[4], s);
   hipLaunchKernelGGL(k_advance<double>, dim3(1), dim3(64), 0, s, a.cnt, par, target, a.cap);
   return hipGetLastError();
+}
+
+hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                            hipEvent_t* ev) {
+  // replays never write the test outputs
+  if (a.mode == 1) return launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev);
+  if (a.mode == 2) return launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev);
+  if (a.test_mode) return launch_flavor<FL_TEST>(a, par, target, grid, block, s, ev);
+  return launch_flavor<FL_FWD>(a, par, target, grid, block, s, ev);
 }
 
 hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm,
@@ -51,8 +61,15 @@ size_t estep_lds_bytes(int n, bool fp64) {
 
 hipError_t configure_fp64(int n_grid) {
   const int bytes = int(estep_lds_bytes(n_grid, true));
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_estep<double>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* k[kFlavors] = {reinterpret_cast<const void*>(&k_estep<double, FL_FWD>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_TEST>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_ADJ_A>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_ADJ_B>)};
+  for (const void* f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_adjoint_weights(const double* dl_ddose, const double* rho, uint64_t nvox, double vol, double* w,

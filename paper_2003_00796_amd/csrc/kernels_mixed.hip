@@ -9,21 +9,31 @@
 
 namespace mcx {
 
-hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
-                            hipEvent_t* ev) {
+template <int F>
+static hipError_t launch_flavor(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                                hipEvent_t* ev) {
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(float);
   const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(float);
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_source<float, F>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(k_flight<float>, dim3(grid), dim3(block), sm_f, s, a, par);
+  hipLaunchKernelGGL((k_flight<float, F>), dim3(grid), dim3(block), sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL(k_knock<float>, dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_knock<float, F>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_estep<float>, dim3(grid), dim3(block), sm_e, s, a, par);
+  hipLaunchKernelGGL((k_estep<float, F>), dim3(grid), dim3(block), sm_e, s, a, par);
   if (ev) (void)hipEventRecord(ev[4], s);
   hipLaunchKernelGGL(k_advance<float>, dim3(1), dim3(64), 0, s, a.cnt, par, target, a.cap);
   return hipGetLastError();
+}
+
+hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
+                            hipEvent_t* ev) {
+  // replays never write the test outputs
+  if (a.mode == 1) return launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev);
+  if (a.mode == 2) return launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev);
+  if (a.test_mode) return launch_flavor<FL_TEST>(a, par, target, grid, block, s, ev);
+  return launch_flavor<FL_FWD>(a, par, target, grid, block, s, ev);
 }
 
 hipError_t launch_dose(const double* sum_q, const double* sum_q2, const float* rho, uint64_t nvox, double vol,
@@ -41,8 +51,15 @@ hipError_t configure_fp64(int n_grid);
 hipError_t configure_kernels(int n_grid, bool fp64) {
   if (fp64) return configure_fp64(n_grid);
   const int bytes = int(estep_lds_bytes(n_grid, false));
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_estep<float>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* k[kFlavors] = {reinterpret_cast<const void*>(&k_estep<float, FL_FWD>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_TEST>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_ADJ_A>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_ADJ_B>)};
+  for (const void* f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_adjoint_weights(const double* dl_ddose, const float* rho, uint64_t nvox, double vol, double* w,

@@ -30,6 +30,24 @@ __device__ __forceinline__ int q_gout(int par) { return Q_G0 + 1 - par; }
 __device__ __forceinline__ int q_ein(int par) { return Q_E0 + par; }
 __device__ __forceinline__ int q_eout(int par) { return Q_E0 + 1 - par; }
 
+// Kernel flavours: the transport kernels are compiled once per flavour, and
+// each tells the compiler the values of the run-time switches of its
+// argument block (the host launches the flavour that matches them), so the
+// forward kernels carry no test-output or replay code (nor its registers).
+enum Flavor : int {
+  FL_FWD = 0,    // forward transport
+  FL_TEST = 1,   // forward transport with the per-history test outputs
+  FL_ADJ_A = 2,  // first density-gradient replay (per-history weighted score)
+  FL_ADJ_B = 3   // second replay (likelihood-ratio scores of photon flights)
+};
+constexpr int kFlavors = 4;
+
+template <int F, typename T>
+__device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
+  __builtin_assume(a.test_mode == (F == FL_TEST ? 1 : 0));
+  __builtin_assume(a.mode == (F == FL_ADJ_A ? 1 : (F == FL_ADJ_B ? 2 : 0)));
+}
+
 template <typename T>
 __device__ __forceinline__ uint32_t append(const KArgs<T>& a, int q, bool pred) {
   const uint32_t slot = wave_append(&a.cnt->n[q].v, pred);
@@ -43,8 +61,9 @@ __device__ __forceinline__ uint32_t append(const KArgs<T>& a, int q, bool pred) 
 // ---------------------------------------------------------------------------
 // source: primaries for history ids [cursor, cursor + adm)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
+  set_flavor<F>(a);
   const uint32_t adm = a.cnt->adm;
   const uint64_t first = a.cnt->cursor;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -108,8 +127,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
 // photon JUMP + STEP: free path in mass thickness, DDA through the voxels;
 // escaped photons end here, the others are sorted by interaction type
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
+  set_flavor<F>(a);
   const uint32_t n = min(a.cnt->n[q_gin(par)].v, a.cap);
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -293,8 +313,9 @@ __device__ __forceinline__ void make_child(const KArgs<T>& a, Part<T>& p, Child<
   c.uid = child_uid(p.uid, k);
 }
 
-template <typename T>
+template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
+  set_flavor<F>(a);
   Counters* C = a.cnt;
   const uint32_t n0 = min(C->n[Q_KC].v, a.cap), n1 = min(C->n[Q_KP].v, a.cap);
   const uint32_t n2 = min(C->n[Q_KR].v, a.cap), n3 = min(C->n[Q_KX].v, a.cap);
@@ -612,8 +633,9 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
 // instead, and they continue, among full wavefronts, in the next iteration.
 constexpr uint32_t kTakeBatch = 32;
 
-template <typename T>
+template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a, int par) {
+  set_flavor<F>(a);
   const uint32_t n = min(a.cnt->n[q_ein(par)].v, a.cap);
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
