@@ -51,7 +51,7 @@ struct mcx_ctx {
   DevBuf d_sumq, d_sumq2;
   uint64_t n_done = 0;
   // event queues
-  uint32_t cap = 1u << 22, block = 256, steps = 128;
+  uint32_t cap = 1u << 24, block = 256, steps = 128;
   DevBuf d_queues;
   size_t queue_cap_built = 0;
   DevBuf d_cnt;
@@ -645,7 +645,7 @@ int mcx_autotune(mcx_ctx* c, uint64_t n_sample, const char* cache_path, uint32_t
       std::fclose(f);
     }
   }
-  const uint32_t banks[] = {1u << 21, 1u << 22, 1u << 23};
+  const uint32_t banks[] = {1u << 22, 1u << 23, 1u << 24};
   const uint32_t blocks[] = {128u, 256u};
   const uint32_t steps[] = {32u, 128u, 512u};
   double best = 0.0;
