@@ -338,7 +338,9 @@ __device__ __forceinline__ void stat_add(BlockStats* s, int k, unsigned long lon
 // ---------------------------------------------------------------------------
 // An insertion is a compare-and-swap of the key into its slot (an empty slot
 // is claimed, a slot holding this key is found), then an add of the score
-// that nobody waits for.  The flush scans the table.
+// that nobody waits for.  The score is added to the voxel's Sum q at once
+// (Eq. (1) needs no per-history total); the flush scans the table for the
+// per-history totals that Sum q^2 needs and clears it.
 template <typename T>
 __device__ __forceinline__ void tally_probe(const KArgs<T>& a, uint64_t key, double q, uint64_t slot, uint64_t k) {
   for (int probe = 0; probe < 4096; ++probe) {
@@ -360,6 +362,7 @@ __device__ __forceinline__ uint64_t tally_slot(const KArgs<T>& a, uint64_t key) 
 template <typename T>
 __device__ __forceinline__ void tally_insert(const KArgs<T>& a, uint64_t key, double q, LaneStats& ls) {
   ls.inserts++;
+  unsafeAtomicAdd(&a.sum_q[uint32_t(key & 0xFFFFFFFFull)], q);
   const uint64_t slot = tally_slot(a, key);
   const uint64_t k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
                                (unsigned long long)key);
@@ -420,6 +423,7 @@ __device__ __forceinline__ void dep_flush_pending(const KArgs<T>& a, DepAcc& acc
     return;
   }
   ls.inserts++;
+  unsafeAtomicAdd(&a.sum_q[uint32_t(acc.pkey & 0xFFFFFFFFull)], acc.pq);
   const uint64_t slot = tally_slot(a, acc.pkey);
   acc.fslot = uint32_t(slot);
   acc.fres = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,

@@ -765,8 +765,9 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// tally flush: each (history, voxel) score q becomes Sum q += q and
-// Sum q^2 += q^2 (Eq. (1)-(3)); slots are cleared for the next chunk
+// tally flush: each (history, voxel) score q, complete now that its history
+// is, adds q^2 to Sum q^2 (Eq. (1)-(3); Sum q was formed at insertion);
+// slots are cleared for the next chunk
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
@@ -780,8 +781,7 @@ __global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* su
     const double q = vals[s];
     dep += q;
     const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
-    unsafeAtomicAdd(&sum_q[v], q);
-    unsafeAtomicAdd(&sum_q2[v], q * q);
+    unsafeAtomicAdd(&sum_q2[v], q * q);  // Sum q was formed at insertion
     if (test_mode) {
       const uint64_t h = (k >> 32) - cnt->run_first;
       if (h < n_run) unsafeAtomicAdd(&hist_led[3 * h], q);
