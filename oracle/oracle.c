@@ -21,8 +21,9 @@
  *     straggling), one hinge per step at a uniform fraction of the step, soft
  *     angular deflection from a one-parameter (mu + A)^-2 law whose mean
  *     matches the soft transport cross section, hard events by the delta
- *     method with an exact majorant over the step's energy interval; every
- *     voxel face ends a step;
+ *     method with a majorant over the step's energy interval (the log-log
+ *     chord of the node sums of the hard cross sections, an upper bound of
+ *     their sum); every voxel face ends a step;
  *  R5 positrons annihilate at rest only;
  *  R6 per-particle counter-based random streams (Philox4x32-10, Salmon et
  *     al. SC'11) keyed by (seed, history) with counter (draw pair, uid), so
@@ -437,12 +438,39 @@ static double sig_hard(const orc_tables* tb, int p, double e) {
          interp(tb, tb->el[p][CH_BR], tb->thr_el[p][CH_BR], e);
 }
 
-/* Every channel is, segment by segment, a convex function of ln E (a power
- * law, or max(0, increasing linear) at a threshold), so the total hard cross
- * section attains its maximum over [elo, e] at elo, e or a node in between. */
+/* ln of the node sum H_j of the three hard cross sections, and the same or
+ * -inf where segment j starts a channel's threshold (zero at node j,
+ * positive at node j + 1) */
+static double lnh(const orc_tables* tb, int p, int j) {
+  return log(tb->el[p][CH_EL][j] + tb->el[p][CH_IN][j] + tb->el[p][CH_BR][j]);
+}
+static double lnh_chord(const orc_tables* tb, int p, int j) {
+  const int ch[3] = {CH_EL, CH_IN, CH_BR};
+  for (int k = 0; k < 3; ++k)
+    if (!(tb->el[p][ch[k]][j] > 0.0) && tb->el[p][ch[k]][j + 1] > 0.0) return -INFINITY;
+  return lnh(tb, p, j);
+}
+
+/* Upper bound of the hard cross section at e.  On a segment without a
+ * threshold every channel is a power law, so ln of their sum is a
+ * log-sum-exp of affine functions of ln E, convex, and lies below its chord:
+ * exp of the log-log chord of the node sums bounds the sum.  On a threshold
+ * segment, the sum itself. */
+static double sig_hard_bound(const orc_tables* tb, int p, double e) {
+  double f;
+  int i = grid_pos(tb, e, &f);
+  double l0 = lnh_chord(tb, p, i);
+  if (l0 > -INFINITY) return exp(l0 + f * (lnh(tb, p, i + 1) - l0));
+  return sig_hard(tb, p, e);
+}
+
+/* Majorant of the hard cross section over [elo, e]: the maximum of the bound
+ * above, which is monotone on each segment (exp of a linear function of ln E;
+ * on a threshold segment a convex function of ln E, as every channel is), so
+ * it is attained at elo, e or a node in between. */
 double orc_sigma_majorant(const orc_tables* tb, int p, double elo, double e) {
-  double m = sig_hard(tb, p, e);
-  double a = sig_hard(tb, p, elo);
+  double m = sig_hard_bound(tb, p, e);
+  double a = sig_hard_bound(tb, p, elo);
   if (a > m) m = a;
   for (int j = 0; j < tb->n; ++j) {
     double ej = tb->e[j];

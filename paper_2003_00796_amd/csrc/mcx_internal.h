@@ -34,11 +34,13 @@ enum Particle : uint32_t { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
 // type p (0 = e-, 1 = e+) at T_E + p*T_ES: ln soft stopping power, soft
 // stopping power, range, range-segment exponent q = 1 - dlnS/dlnE, ln hard
 // elastic, ln hard inelastic, ln hard bremsstrahlung, ln soft transport
-// coefficient, node sum of the three hard coefficients.  Zero values are
-// stored as ln 0 = -inf.
+// coefficient, node sum of the three hard coefficients, its ln, and its ln
+// again but -inf where a channel's threshold falls in the segment above the
+// node.  Zero values are stored as ln 0 = -inf.
 // Initial guess of the soft angular law parameter: ln A at kSoftN points
-// uniform in ln <mu> over [ln kSoftMLo, ln kSoftMHi], stored after the
-// channel block (offset T_NCH * n).
+// uniform in y = ln(<mu> / (1/2 - <mu>)) over [y(kSoftMLo), y(kSoftMHi)],
+// stored after the channel block (offset T_NCH * n).  ln A is close to
+// linear in y at both ends (<mu> -> 0 and <mu> -> 1/2).
 constexpr int kSoftN = 256;
 constexpr double kSoftMLo = 1e-9;
 constexpr double kSoftMHi = 0.49;
@@ -49,7 +51,9 @@ enum TabChannel : int {
   T_PHOTON_END = 5,  // channels [0, 5) serve the photon kernels
   T_E = 5,
   O_LS = 0, O_S = 1, O_R = 2, O_Q = 3, O_LEL = 4, O_LIN = 5, O_LBR = 6, O_LT1S = 7, O_HSUM = 8,
-  T_ES = 9,
+  O_LH = 9,    // ln of the node sum of the hard cross sections
+  O_LHC = 10,  // the same, or -inf where the segment starting at the node holds a threshold
+  T_ES = 11,
   T_NCH = T_E + 2 * T_ES
 };
 

@@ -22,6 +22,15 @@
 #include "mcx_internal.h"
 #include "tables.h"
 
+// tally table: 2^MCX_TALLY_LOG2 slots, a chunk of histories sized so that at
+// most 1/MCX_TALLY_LOAD_DIV of them are occupied
+#ifndef MCX_TALLY_LOG2
+#define MCX_TALLY_LOG2 29
+#endif
+#ifndef MCX_TALLY_LOAD_DIV
+#define MCX_TALLY_LOAD_DIV 4
+#endif
+
 using namespace mcx;
 
 struct DevBuf {
@@ -57,7 +66,7 @@ struct mcx_ctx {
   DevBuf d_cnt;
   Counters* h_cnt = nullptr;  // pinned
   // tally table
-  uint64_t hslots = 1ull << 29;  // 8 GiB of keys and scores, kept at load <= 1/4
+  uint64_t hslots = 1ull << MCX_TALLY_LOG2;  // keys and scores, 16 B a slot
   DevBuf d_hkeys, d_hvals;
   double pairs_per_hist = 0.0;
   bool table_dirty = false;  // a failed run may have left entries behind
@@ -255,7 +264,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   const uint32_t target = c->cap / 4;
   int grid = int((std::min<uint64_t>(c->cap, 2ull * target) + c->block - 1) / c->block);
   grid = std::max(grid, 1);
-  const uint64_t table_budget = c->hslots / 4;  // keep the load factor <= 1/4 (few second probes)
+  const uint64_t table_budget = c->hslots / MCX_TALLY_LOAD_DIV;  // bounded load factor: few second probes
   uint64_t done = 0;
   auto t0 = std::chrono::steady_clock::now();
   double flush_ms = 0.0;

@@ -226,6 +226,16 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
       ch(base + O_LBR)[i] = ln_or_inf(sig_br);
       ch(base + O_LT1S)[i] = ln_or_inf(sig1s);
       ch(base + O_HSUM)[i] = sig_h + sig_in + sig_br;
+      ch(base + O_LH)[i] = std::log(sig_h + sig_in + sig_br);
+    }
+    // the log-log chord of the node sums bounds the sum on a segment where no
+    // channel starts (ln of a sum of power laws is convex in ln E)
+    for (int i = 0; i < n; ++i) {
+      bool thr = false;
+      if (i + 1 < n)
+        for (int c : {O_LEL, O_LIN, O_LBR})
+          if (!(ch(base + c)[i] > -HUGE_VAL) && ch(base + c)[i + 1] > -HUGE_VAL) thr = true;
+      ch(base + O_LHC)[i] = thr ? -HUGE_VAL : ch(base + O_LH)[i];
     }
     // range: Int dE / S over each power-law segment S = S_i (E/E_i)^(1-q)
     double r = 0.0;
@@ -247,9 +257,10 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
   // by bisection in ln A (initial guesses for the device's Newton steps)
   {
     double* soft = b.block.data() + size_t(T_NCH) * n;
-    const double x0 = std::log(kSoftMLo), x1 = std::log(kSoftMHi);
+    const double y0 = std::log(kSoftMLo / (0.5 - kSoftMLo)), y1 = std::log(kSoftMHi / (0.5 - kSoftMHi));
     for (int j = 0; j < kSoftN; ++j) {
-      const double m = std::exp(x0 + (x1 - x0) * j / (kSoftN - 1));
+      const double y = y0 + (y1 - y0) * j / (kSoftN - 1);
+      const double m = 0.5 / (1.0 + std::exp(-y));
       double lo = -700.0, hi = std::log(1e6);
       for (int it = 0; it < 200; ++it) {
         const double mid = 0.5 * (lo + hi), a = std::exp(mid);

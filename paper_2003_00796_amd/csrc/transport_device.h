@@ -662,15 +662,28 @@ __device__ __forceinline__ T hard_sum(const Tab<T>& tb, const T* s, int base, in
          interp(s, n, base + O_LBR, g, e, tb.thr_br);
 }
 
-// maximum of the hard cross section over [elo, e]: every channel is convex
-// in ln E on each segment, so the maximum sits at elo, e or a node between
+// upper bound of the hard cross section at e: on a segment without a
+// channel threshold, exp of the log-log chord of the node sums (ln of a sum
+// of power laws is convex in ln E and lies below its chord); elsewhere the
+// sum of the channels
+template <typename T>
+__device__ __forceinline__ T hard_bound(const Tab<T>& tb, const T* s, int base, int lep, const Grid<T>& g, T e) {
+  const int n = tb.n;
+  const T l0 = s[(base + O_LHC) * n + g.i];
+  if (l0 > -M<T>::inf()) return M<T>::exp(l0 + g.f * (s[(base + O_LH) * n + g.i + 1] - l0));
+  return hard_sum(tb, s, base, lep, g, e);
+}
+
+// majorant over [elo, e]: the bound above is monotone on each segment (or
+// convex in ln E on a threshold segment, as every channel is), so its
+// maximum sits at elo, e or a node between
 template <typename T>
 __device__ __forceinline__ T majorant(const Tab<T>& tb, const T* s, int base, int lep, T elo, const Grid<T>& ge,
                                       T e) {
   const int n = tb.n;
-  T m = hard_sum(tb, s, base, lep, ge, e);
+  T m = hard_bound(tb, s, base, lep, ge, e);
   const Grid<T> gl = grid_at(tb, M<T>::log(elo));
-  const T a = hard_sum(tb, s, base, lep, gl, elo);
+  const T a = hard_bound(tb, s, base, lep, gl, elo);
   if (a > m) m = a;
   for (int j = gl.i; j <= ge.i + 1 && j < n; ++j) {
     const T ej = s[T_ENODE * n + j];
@@ -684,28 +697,29 @@ __device__ __forceinline__ T majorant(const Tab<T>& tb, const T* s, int base, in
 
 // A of the soft angular law p(mu) ~ (mu + A)^-2 on [0,1] whose mean
 // A (1 + A) ln(1 + 1/A) - A equals mbar (clamped to 0.49).  Start from the
-// tabulated ln A (linear in ln mbar) or, below the table, from the small-A
-// expansion A (ln(1/A) - 1) = mbar; then a fixed number of Newton steps on
-// ln A (quadratic convergence: FP32 needs one, FP64 three).
+// tabulated ln A (linear in y = ln(mbar / (1/2 - mbar)), within 1e-4 of the
+// root) or, below the table, from the small-A expansion A (ln(1/A) - 1) =
+// mbar; then Newton steps on ln A: none in FP32, two in FP64 (quadratic
+// convergence to the rounding limit of the mean's evaluation).
 template <typename T>
 __device__ __forceinline__ T soft_a(T mbar, const T* soft) {
   if (!(mbar > T(0))) return T(0);
   if (mbar > T(kSoftMHi)) mbar = T(kSoftMHi);
-  const T lm = M<T>::log(mbar);
-  const T x0 = T(-20.72326583694641);  // ln 1e-9
-  const T inv_dx = T(double(kSoftN - 1) / (-0.7133498878774648 + 20.72326583694641));
   T s;
   if (mbar < T(kSoftMLo)) {
+    const T lm = M<T>::log(mbar);
     const T a0 = mbar / (-lm);
     s = M<T>::log(mbar / (-M<T>::log(a0) - T(1)));
   } else {
-    T x = (lm - x0) * inv_dx;
+    const T y0 = T(-20.030118654386467);  // y(1e-9)
+    const T inv_dy = T(double(kSoftN - 1) / (3.8918202981106256 + 20.030118654386467));  // y(0.49) = 3.89...
+    const T x = (M<T>::log(mbar / (T(0.5) - mbar)) - y0) * inv_dy;
     int j = int(x);
     j = j < 0 ? 0 : (j > kSoftN - 2 ? kSoftN - 2 : j);
     const T f = x - T(j);
     s = soft[j] + f * (soft[j + 1] - soft[j]);
   }
-  const int steps = is_fp64<T>() ? 3 : 1;
+  const int steps = is_fp64<T>() ? 2 : 0;
   for (int it = 0; it < steps; ++it) {
     const T A = M<T>::exp(s);
     const T L = M<T>::log1p(T(1) / A);

@@ -239,7 +239,9 @@ def test_majorant_is_max_over_interval_brute_force(tb_hi, p):
         sig = np.array([sum(tb_hi.eval(O.ech(p, c), x) for c in (2, 3, 4)) for x in es])
         maj = tb_hi.majorant(p, elo, e)
         assert sig.max() <= maj * (1 + 1e-12)
-        assert maj <= sig.max() * (1 + 1e-9) + 1e-300
+        # the chord bound exceeds the sum by the curvature of ln(sum) over one
+        # segment: at most ~(slope spread * dlnE)^2 / 32
+        assert maj <= sig.max() * (1 + 2e-4) + 1e-300
 
 
 def test_soft_law_parameter_reproduces_mean():
