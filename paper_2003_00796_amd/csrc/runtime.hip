@@ -93,7 +93,17 @@ struct mcx_ctx {
   uint64_t timed_iterations = 0;
 };
 
-static constexpr int kBatch = 8;  // iterations between completion checks
+#ifndef MCX_BATCH
+#define MCX_BATCH 8
+#endif
+#ifndef MCX_GRID_WAVES
+#define MCX_GRID_WAVES 8192
+#endif
+static constexpr int kBatch = MCX_BATCH;  // iterations between completion checks
+// wavefronts launched per transport kernel: the kernels loop over their queue
+// (grid stride, or persistent lanes), so a grid that fills the chip twice
+// over serves any queue length, and blocks that find no work cost launch time
+static constexpr int kGridWaves = MCX_GRID_WAVES;
 
 namespace {
 
@@ -263,6 +273,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   fill_args(c, a, seed, mode, qbar);
   const uint32_t target = c->cap / 4;
   int grid = int((std::min<uint64_t>(c->cap, 2ull * target) + c->block - 1) / c->block);
+  grid = std::min(grid, int(uint64_t(kGridWaves) * 64 / c->block));
   grid = std::max(grid, 1);
   const uint64_t table_budget = c->hslots / MCX_TALLY_LOAD_DIV;  // bounded load factor: few second probes
   uint64_t done = 0;
