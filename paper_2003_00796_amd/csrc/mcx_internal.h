@@ -99,17 +99,25 @@ struct Counters {
   uint64_t occupied;       // tally pairs seen by the last flush
 };
 
+// A queue record is 4 (FP32 physics) or 5 (FP64) chunks of 16 bytes; chunk k
+// of every record of a queue is one array, so a wavefront moves a record with
+// one 16-byte access per chunk and lane, each instruction reading or writing
+// 1 KiB of contiguous memory.  FP32: {x, y} {z, uid} {u, v, w, E} {meta};
+// FP64: {x, y} {z, uid} {u, v} {w, E} {meta}, with meta = {history id, draw
+// counter, voxel ix | iy << 10 | iz << 20, type | children << 2}.
+struct alignas(16) Chunk {
+  uint32_t x, y, z, w;
+};
+constexpr int kMaxChunks = 5;
+template <typename T>
+constexpr int rec_chunks() {
+  return sizeof(T) == 8 ? 5 : 4;
+}
+
 template <typename T>
 struct Bank {
-  double* x; double* y; double* z;
-  T* u; T* v; T* w;
-  T* e;
-  uint64_t* uid;
-  uint32_t* hist;
-  uint32_t* ctr;
-  uint32_t* vox;    // ix | iy << 10 | iz << 20
-  uint32_t* flags;  // type | nchild << 2
-  uint64_t* hash;
+  Chunk* c[kMaxChunks];
+  uint64_t* hash;  // event hash (test mode)
 };
 
 struct SourceDev {

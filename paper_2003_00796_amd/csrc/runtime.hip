@@ -145,11 +145,6 @@ bool fp64(const mcx_ctx* c) { return c->precision == MCX_FP64; }
 size_t tsize(const mcx_ctx* c) { return fp64(c) ? sizeof(double) : sizeof(float); }
 uint64_t nvox(const mcx_ctx* c) { return uint64_t(c->nx) * c->ny * c->nz; }
 
-// bytes of one queue record (structure of arrays)
-size_t record_bytes(const mcx_ctx* c) {
-  return 3 * sizeof(double) + 4 * tsize(c) + sizeof(uint64_t) * 2 + sizeof(uint32_t) * 4;
-}
-
 template <typename T>
 void carve_banks(mcx_ctx* c, KArgs<T>& a) {
   char* p = static_cast<char*>(c->d_queues.p);
@@ -161,26 +156,15 @@ void carve_banks(mcx_ctx* c, KArgs<T>& a) {
   };
   for (int q = 0; q < Q_NQ; ++q) {
     Bank<T>& b = a.q[q];
-    b.x = reinterpret_cast<double*>(take(n * sizeof(double)));
-    b.y = reinterpret_cast<double*>(take(n * sizeof(double)));
-    b.z = reinterpret_cast<double*>(take(n * sizeof(double)));
-    b.u = reinterpret_cast<T*>(take(n * sizeof(T)));
-    b.v = reinterpret_cast<T*>(take(n * sizeof(T)));
-    b.w = reinterpret_cast<T*>(take(n * sizeof(T)));
-    b.e = reinterpret_cast<T*>(take(n * sizeof(T)));
-    b.uid = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
-    b.hist = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
-    b.ctr = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
-    b.vox = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
-    b.flags = reinterpret_cast<uint32_t*>(take(n * sizeof(uint32_t)));
+    for (int k = 0; k < kMaxChunks; ++k)
+      b.c[k] = k < rec_chunks<T>() ? reinterpret_cast<Chunk*>(take(n * sizeof(Chunk))) : nullptr;
     b.hash = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
   }
 }
 
 size_t queue_bytes(const mcx_ctx* c) {
   const size_t n = c->cap;
-  const size_t per = (n * sizeof(double) + 255) / 256 * 256 * 3 + (n * tsize(c) + 255) / 256 * 256 * 4 +
-                     (n * 8 + 255) / 256 * 256 * 2 + (n * 4 + 255) / 256 * 256 * 4;
+  const size_t per = ((n * sizeof(Chunk) + 255) / 256 * 256) * (fp64(c) ? 5 : 4) + (n * 8 + 255) / 256 * 256;
   return per * Q_NQ;
 }
 

@@ -210,33 +210,93 @@ struct Part {
   Rng<T> rng;
 };
 
+__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) { return uint64_t(lo) | (uint64_t(hi) << 32); }
+__device__ __forceinline__ double join_f64(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double(static_cast<long long>(join64(lo, hi)));
+}
+__device__ __forceinline__ void split64(uint64_t v, uint32_t& lo, uint32_t& hi) {
+  lo = uint32_t(v);
+  hi = uint32_t(v >> 32);
+}
+__device__ __forceinline__ void split_f64(double d, uint32_t& lo, uint32_t& hi) {
+  split64(static_cast<uint64_t>(__double_as_longlong(d)), lo, hi);
+}
+__device__ __forceinline__ uint32_t pack_vox(const int ix[3]) {
+  return uint32_t(ix[0]) | (uint32_t(ix[1]) << 10) | (uint32_t(ix[2]) << 20);
+}
+
+// write a record: position and voxel of `p`, then direction, energy, uid,
+// draw counter and type/children given
+template <typename T>
+__device__ __forceinline__ void store_record(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
+                                             const T d[3], T e, uint64_t uid, uint32_t ctr, uint32_t flags,
+                                             uint64_t hash) {
+  Chunk c0, c1, cm;
+  split_f64(p.x[0], c0.x, c0.y);
+  split_f64(p.x[1], c0.z, c0.w);
+  split_f64(p.x[2], c1.x, c1.y);
+  split64(uid, c1.z, c1.w);
+  cm.x = p.hist;
+  cm.y = ctr;
+  cm.z = pack_vox(p.ix);
+  cm.w = flags;
+  b.c[0][i] = c0;
+  b.c[1][i] = c1;
+  if constexpr (sizeof(T) == 8) {
+    Chunk c2, c3;
+    split_f64(double(d[0]), c2.x, c2.y);
+    split_f64(double(d[1]), c2.z, c2.w);
+    split_f64(double(d[2]), c3.x, c3.y);
+    split_f64(double(e), c3.z, c3.w);
+    b.c[2][i] = c2;
+    b.c[3][i] = c3;
+    b.c[4][i] = cm;
+  } else {
+    Chunk c2;
+    c2.x = __float_as_uint(float(d[0]));
+    c2.y = __float_as_uint(float(d[1]));
+    c2.z = __float_as_uint(float(d[2]));
+    c2.w = __float_as_uint(float(e));
+    b.c[2][i] = c2;
+    b.c[3][i] = cm;
+  }
+  if (a.test_mode) b.hash[i] = hash;
+}
+
 template <typename T>
 __device__ __forceinline__ void load_part(const KArgs<T>& a, const Bank<T>& b, uint32_t i, Part<T>& p) {
-  p.x[0] = b.x[i]; p.x[1] = b.y[i]; p.x[2] = b.z[i];
-  p.d[0] = b.u[i]; p.d[1] = b.v[i]; p.d[2] = b.w[i];
-  p.e = b.e[i];
-  p.uid = b.uid[i];
-  p.hist = b.hist[i];
-  const uint32_t vx = b.vox[i];
-  p.ix[0] = int(vx & 1023u); p.ix[1] = int((vx >> 10) & 1023u); p.ix[2] = int(vx >> 20);
-  const uint32_t fl = b.flags[i];
-  p.type = fl & 3u;
-  p.nchild = fl >> 2;
+  const Chunk c0 = b.c[0][i], c1 = b.c[1][i];
+  Chunk cm;
+  p.x[0] = join_f64(c0.x, c0.y);
+  p.x[1] = join_f64(c0.z, c0.w);
+  p.x[2] = join_f64(c1.x, c1.y);
+  p.uid = join64(c1.z, c1.w);
+  if constexpr (sizeof(T) == 8) {
+    const Chunk c2 = b.c[2][i], c3 = b.c[3][i];
+    cm = b.c[4][i];
+    p.d[0] = T(join_f64(c2.x, c2.y));
+    p.d[1] = T(join_f64(c2.z, c2.w));
+    p.d[2] = T(join_f64(c3.x, c3.y));
+    p.e = T(join_f64(c3.z, c3.w));
+  } else {
+    const Chunk c2 = b.c[2][i];
+    cm = b.c[3][i];
+    p.d[0] = T(__uint_as_float(c2.x));
+    p.d[1] = T(__uint_as_float(c2.y));
+    p.d[2] = T(__uint_as_float(c2.z));
+    p.e = T(__uint_as_float(c2.w));
+  }
+  p.hist = cm.x;
+  p.ix[0] = int(cm.z & 1023u); p.ix[1] = int((cm.z >> 10) & 1023u); p.ix[2] = int(cm.z >> 20);
+  p.type = cm.w & 3u;
+  p.nchild = cm.w >> 2;
   p.hash = a.test_mode ? b.hash[i] : 0ull;
-  rng_init(p.rng, a.seed, p.hist, p.uid, b.ctr[i]);
+  rng_init(p.rng, a.seed, p.hist, p.uid, cm.y);
 }
 
 template <typename T>
 __device__ __forceinline__ void store_part(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p) {
-  b.x[i] = p.x[0]; b.y[i] = p.x[1]; b.z[i] = p.x[2];
-  b.u[i] = p.d[0]; b.v[i] = p.d[1]; b.w[i] = p.d[2];
-  b.e[i] = p.e;
-  b.uid[i] = p.uid;
-  b.hist[i] = p.hist;
-  b.ctr[i] = p.rng.ctr;
-  b.vox[i] = uint32_t(p.ix[0]) | (uint32_t(p.ix[1]) << 10) | (uint32_t(p.ix[2]) << 20);
-  b.flags[i] = p.type | (p.nchild << 2);
-  if (a.test_mode) b.hash[i] = p.hash;
+  store_record(a, b, i, p, p.d, p.e, p.uid, p.rng.ctr, p.type | (p.nchild << 2), p.hash);
 }
 
 // a secondary waiting to be appended: shares position/voxel/history with its parent
@@ -252,15 +312,7 @@ struct Child {
 template <typename T>
 __device__ __forceinline__ void store_child(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
                                             const Child<T>& c) {
-  b.x[i] = p.x[0]; b.y[i] = p.x[1]; b.z[i] = p.x[2];
-  b.u[i] = c.d[0]; b.v[i] = c.d[1]; b.w[i] = c.d[2];
-  b.e[i] = c.e;
-  b.uid[i] = c.uid;
-  b.hist[i] = p.hist;
-  b.ctr[i] = 0u;
-  b.vox[i] = uint32_t(p.ix[0]) | (uint32_t(p.ix[1]) << 10) | (uint32_t(p.ix[2]) << 20);
-  b.flags[i] = c.type;
-  if (a.test_mode) b.hash[i] = 0ull;
+  store_record(a, b, i, p, c.d, c.e, c.uid, 0u, c.type, 0ull);
 }
 
 // ---------------------------------------------------------------------------
