@@ -172,14 +172,57 @@ def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
                 same_dose_rel_max=float(np.max(np.abs(d_all[hi] - d_each[hi]) / d_all[hi])))
 
 
-def cpu_baseline(wl, n_sample: int) -> dict:
+def _oracle_shard(args):
+    """One history range of the workload through the oracle (own process)."""
+    name, first, n = args
     import oracle as O
+    import workloads as W
+    wl = W.workload(name)
     tb = O.Tables(wl["material"], wl["transport"])
     t0 = time.perf_counter()
-    O.run(tb, wl["phantom"], wl["sources"], wl["seed"], 0, n_sample)
-    dt = time.perf_counter() - t0
-    return dict(value=n_sample / dt, unit="histories/s", cores=1, kind="oracle",
-                sample=f"histories [0, {n_sample}) of the same workload, single-thread FP64 oracle, {dt:.1f} s")
+    O.run(tb, wl["phantom"], wl["sources"], wl["seed"], first, n)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(name: str, n_per_proc: int, procs: int) -> dict:
+    """The oracle on the host cores, sharded by history range over `procs`
+    processes (independent histories, as the paper's multi-process runs): the
+    rate is the histories over the slowest shard's time (setup excluded)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    jobs = [(name, k * n_per_proc, n_per_proc) for k in range(procs)]
+    with cf.ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
+        times = list(ex.map(_oracle_shard, jobs))
+    rate = procs * n_per_proc / max(times)
+    return dict(value=rate, unit="histories/s", cores=procs, kind="oracle",
+                single_core=n_per_proc / (sum(times) / len(times)),
+                sample=f"histories [0, {procs * n_per_proc}) of the same workload in {procs} single-thread FP64 "
+                       f"oracle processes of {n_per_proc} histories each ({max(times):.1f} s the slowest, "
+                       f"{sum(times):.0f} s of CPU work)")
+
+
+def electron_comparison(mcx, W, sync, n: int = 1_000_000) -> dict:
+    """20 MeV electron pencil on a 200^3 x 1 mm water cube: mixed and FP64 on
+    the same streams."""
+    wl = W.workload("electron_200", n)
+    out = {}
+    doses = {}
+    for name, prec in (("mixed", mcx.MIXED), ("fp64", mcx.FP64)):
+        sim = mcx.Simulator(prec, 0).setup(wl)
+        sim.run(777, 0, min(n, 100_000))
+        sim.reset()
+        sync()
+        t0 = time.perf_counter()
+        sim.run(1, 0, n)
+        sync()
+        dt = time.perf_counter() - t0
+        doses[name], _ = sim.dose()
+        sim.close()
+        out[name] = dict(value=n / dt, ms=1e3 * dt)
+    out["mixed_over_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    out["high_dose_deviation"] = high_dose_deviation(doses["mixed"], doses["fp64"])
+    out["workload"] = "electron_200: 20 MeV e- pencil, 200^3 x 1 mm water, 1e6 histories"
+    return out
 
 
 def main():
@@ -188,7 +231,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hist", type=int, default=10_000_000, help="histories per step")
-    ap.add_argument("--cpu-sample", type=int, default=30_000)
+    ap.add_argument("--cpu-sample", type=int, default=6_000, help="oracle histories per host process")
+    ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes (host cores used)")
+    ap.add_argument("--electron", action="store_true", help="also time the 20 MeV electron workload")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
@@ -276,8 +321,10 @@ def main():
     if args.beamlets:
         out["beamlets"] = beamlet_comparison(mcx, W, sync, args.beamlets,
                                              os.path.join(ROOT, "gpurun_out", "autotune_cache.jsonl"))
+    if args.electron:
+        out["electron"] = electron_comparison(mcx, W, sync)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline("hetero_broad_128", args.cpu_sample, args.cpu_procs)
     print(json.dumps(out))
 
 
