@@ -880,9 +880,10 @@ static double sample_moller(stream* s, double e, double wcc) {
   for (;;) {
     double u = draw(s), ua = draw(s);
     double k = kc / (1.0 - u * (1.0 - 2.0 * kc));
-    double f = 1.0 / (k * k) + 1.0 / ((1.0 - k) * (1.0 - k)) + cf.a - (1.0 - cf.a) / (k * (1.0 - k));
-    /* k^2 f rises to its maximum 1 + 5a/4 at k = 1/2 on [0, 1/2] */
-    if (ua * (1.0 + 1.25 * cf.a) <= k * k * f) return k;
+    /* k^2 times the bracket 1/k^2 + 1/(1-k)^2 + a - (1-a)/(k(1-k)), written
+     * with r = k/(1-k); it rises to its maximum 1 + 5a/4 at k = 1/2 */
+    double r = k / (1.0 - k);
+    if (ua * (1.0 + 1.25 * cf.a) <= 1.0 + r * r + cf.a * k * k - (1.0 - cf.a) * r) return k;
   }
 }
 

@@ -41,7 +41,7 @@ enum Particle : uint32_t { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
 // uniform in y = ln(<mu> / (1/2 - <mu>)) over [y(kSoftMLo), y(kSoftMHi)],
 // stored after the channel block (offset T_NCH * n).  ln A is close to
 // linear in y at both ends (<mu> -> 0 and <mu> -> 1/2).
-constexpr int kSoftN = 256;
+constexpr int kSoftN = 1024;
 constexpr double kSoftMLo = 1e-9;
 constexpr double kSoftMHi = 0.49;
 

@@ -579,11 +579,14 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     const T kc = a.wcc / e1;
     const T gm = T(1) + e1 / T(kMc2);
     const T aa = ((gm - T(1)) / gm) * ((gm - T(1)) / gm);
-    const T gp = gm + T(1);
-    const T b1 = aa * (T(2) * gp * gp - T(1)) / (gm * gm - T(1));
-    const T b2 = aa * (T(3) * gp * gp + T(1)) / (gp * gp);
-    const T b3 = aa * T(2) * (gm - T(1)) * gm / (gp * gp);
-    const T b4 = aa * (gm - T(1)) * (gm - T(1)) / (gp * gp);
+    T b1 = T(0), b2 = T(0), b3 = T(0), b4 = T(0);
+    if (lep) {
+      const T gp = gm + T(1);
+      b1 = aa * (T(2) * gp * gp - T(1)) / (gm * gm - T(1));
+      b2 = aa * (T(3) * gp * gp + T(1)) / (gp * gp);
+      b3 = aa * T(2) * (gm - T(1)) * gm / (gp * gp);
+      b4 = aa * (gm - T(1)) * (gm - T(1)) / (gp * gp);
+    }
     const T span = lep == 0 ? T(1) - T(2) * kc : T(1) - kc;
     T k = kc;
     for (int tries = 0; tries < kMaxTries; ++tries) {
@@ -591,8 +594,10 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
       k = kc / (T(1) - uu * span);
       bool ok;
       if (lep == 0) {
-        const T f = T(1) / (k * k) + T(1) / ((T(1) - k) * (T(1) - k)) + aa - (T(1) - aa) / (k * (T(1) - k));
-        ok = ua * (T(1) + T(1.25) * aa) <= k * k * f;  // k^2 f <= its value at k = 1/2
+        // k^2 times the bracket, 1 + r^2 + a k^2 - (1 - a) r with r = k/(1-k),
+        // is at most its value 1 + 5a/4 at k = 1/2
+        const T r = k / (T(1) - k);
+        ok = ua * (T(1) + T(1.25) * aa) <= T(1) + r * r + aa * k * k - (T(1) - aa) * r;
       } else {
         const T gg = T(1) - b1 * k + b2 * k * k - b3 * k * k * k + b4 * k * k * k * k;
         ok = ua <= gg;
