@@ -26,10 +26,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.
 UNITS = [
     # FP64 path: IEEE division and square root, no multiply-add fusion
     ("kernels_fp64.hip", ["-ffp-contract=off"]),
-    # mixed path: FP32 physics may use reciprocal-based division and flush
-    # FP32 denormals; infinities and NaNs keep their IEEE meaning
+    # mixed path: FP32 physics may use reciprocal-based division (v_rcp, 1 ulp)
+    # and the hardware square root, and flushes FP32 denormals; infinities and
+    # NaNs keep their IEEE meaning
     ("kernels_mixed.hip", ["-freciprocal-math", "-fno-signed-zeros", "-fno-trapping-math", "-fno-math-errno",
-                           "-fgpu-flush-denormals-to-zero"]),
+                           "-fgpu-flush-denormals-to-zero", "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("runtime.hip", []),
 ]
 

@@ -50,9 +50,18 @@ struct M<float> {
   static __device__ __forceinline__ float log(float x) { return __logf(x); }
   static __device__ __forceinline__ float exp(float x) { return __expf(x); }
   static __device__ __forceinline__ float sqrt(float x) { return ::sqrtf(x); }
-  static __device__ __forceinline__ float pow(float a, float b) { return __powf(a, b); }
-  static __device__ __forceinline__ float log1p(float x) { return ::log1pf(x); }
-  static __device__ __forceinline__ float expm1(float x) { return ::expm1f(x); }
+  static __device__ __forceinline__ float pow(float a, float b) { return __expf(b * __logf(a)); }
+  // log(1 + x) accurate for small x: log(u) x / (u - 1) with u = 1 + x
+  // (the rounding of u cancels in the ratio)
+  static __device__ __forceinline__ float log1p(float x) {
+    const float u = 1.0f + x;
+    return u == 1.0f ? x : __logf(u) * (x / (u - 1.0f));
+  }
+  // exp(x) - 1 accurate for small x: (u - 1) x / log(u) with u = exp(x)
+  static __device__ __forceinline__ float expm1(float x) {
+    const float u = __expf(x);
+    return u == 1.0f ? x : (u - 1.0f) * (x / __logf(u));
+  }
   static __device__ __forceinline__ float floor(float x) { return ::floorf(x); }
   static __device__ __forceinline__ void sincos(float x, float* s, float* c) { __sincosf(x, s, c); }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
