@@ -84,8 +84,16 @@ struct alignas(128) LineCount {
   uint32_t v;
 };
 
+// The photon and e+- ping-pong queues (Q_G0 .. Q_E1) take appends from every
+// wavefront of three kernels: each is split into kStripes stripes of cap /
+// kStripes records with a counter each (a block appends to stripe
+// blockIdx % kStripes), so the atomics spread over as many cache lines.
+constexpr int kStripes = 8;
+constexpr int kStripedQueues = 4;
+
 struct Counters {
-  LineCount n[Q_NQ];       // queue occupancy
+  LineCount n[Q_NQ];       // occupancy of the interaction queues Q_KC .. Q_KX
+  LineCount ns[kStripedQueues][kStripes];  // occupancy of each stripe of Q_G0 .. Q_E1
   LineCount take_e;        // records of the e+- input queue reserved in this iteration
   uint32_t overflow;       // Overflow bits
   uint32_t done;           // chunk finished

@@ -48,14 +48,51 @@ __device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
   __builtin_assume(a.mode == (F == FL_ADJ_A ? 1 : (F == FL_ADJ_B ? 2 : 0)));
 }
 
+// striped queues: this block's stripe, the records of a stripe, the prefix
+// sums of the stripe occupancies (wave-uniform) and the record of the i-th
+// queued particle
+__device__ __forceinline__ uint32_t my_stripe() { return blockIdx.x & uint32_t(kStripes - 1); }
+
+template <typename T>
+__device__ __forceinline__ uint32_t stripe_cap(const KArgs<T>& a) {
+  return a.cap / uint32_t(kStripes);
+}
+
+struct StripeSums {
+  uint32_t pre[kStripes + 1];
+};
+
+__device__ __forceinline__ StripeSums stripe_sums(const Counters* c, int q, uint32_t cs) {
+  StripeSums t;
+  t.pre[0] = 0u;
+#pragma unroll
+  for (int k = 0; k < kStripes; ++k) t.pre[k + 1] = t.pre[k] + min(c->ns[q][k].v, cs);
+  return t;
+}
+
+__device__ __forceinline__ uint32_t striped_record(const StripeSums& t, uint32_t i, uint32_t cs) {
+  uint32_t s = 0u, base = 0u;
+#pragma unroll
+  for (int k = 1; k < kStripes; ++k) {
+    const bool in = i >= t.pre[k];
+    s = in ? uint32_t(k) : s;
+    base = in ? t.pre[k] : base;
+  }
+  return s * cs + (i - base);
+}
+
+// wavefront-aggregated append; returns the record index, ~0u on overflow
 template <typename T>
 __device__ __forceinline__ uint32_t append(const KArgs<T>& a, int q, bool pred) {
-  const uint32_t slot = wave_append(&a.cnt->n[q].v, pred);
-  if (pred && slot >= a.cap) {
+  const bool striped = q < kStripedQueues;
+  const uint32_t st = my_stripe();
+  const uint32_t cap = striped ? stripe_cap(a) : a.cap;
+  const uint32_t slot = wave_append(striped ? &a.cnt->ns[q][st].v : &a.cnt->n[q].v, pred);
+  if (pred && slot >= cap) {
     atomicOr(&a.cnt->overflow, uint32_t(OVF_QUEUE));
     return ~0u;
   }
-  return slot;
+  return striped ? st * cap + slot : slot;
 }
 
 // ---------------------------------------------------------------------------
@@ -130,7 +167,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
   set_flavor<F>(a);
-  const uint32_t n = min(a.cnt->n[q_gin(par)].v, a.cap);
+  const uint32_t cs = stripe_cap(a);
+  const StripeSums sums = stripe_sums(a.cnt, q_gin(par), cs);
+  const uint32_t n = sums.pre[kStripes];
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* tab = reinterpret_cast<T*>(smem);
@@ -147,7 +186,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
     int ch = -1;
     Part<T> p;
     if (i < n) {
-      load_part(a, in, i, p);
+      load_part(a, in, striped_record(sums, i, cs), p);
       const T e = p.e;
       const Grid<T> g = grid_at(a.tb, M<T>::log(e));
       T mu[4];
@@ -641,7 +680,9 @@ constexpr uint32_t kTakeBatch = 32;
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a, int par) {
   set_flavor<F>(a);
-  const uint32_t n = min(a.cnt->n[q_ein(par)].v, a.cap);
+  const uint32_t cs = stripe_cap(a);
+  const StripeSums sums = stripe_sums(a.cnt, q_ein(par), cs);
+  const uint32_t n = sums.pre[kStripes];
   if (blockIdx.x * blockDim.x >= n) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* tab = reinterpret_cast<T*>(smem);
@@ -682,7 +723,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
       const uint64_t got = __ballot(need && idx < n);
       if (lane == 0 && got) atomicAdd(&bs.c[S_EVISITS], (unsigned long long)__popcll(got));
       if (need && idx < n) {
-        load_part(a, in, idx, p);
+        load_part(a, in, striped_record(sums, idx, cs), p);
         alive = true;
         used = 0;
       }
@@ -709,21 +750,23 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     const uint32_t ne = ne1 + uint32_t(__popcll(mep)), ng = ng1 + uint32_t(__popcll(mg2));
     if (ne + ng != 0u) {  // wave-uniform
       uint32_t be = 0, bg = 0;
+      const uint32_t st = my_stripe();
       if (lane == 0) {
         atomicAdd(&bs.c[S_EWRITES], (unsigned long long)(ne + ng));
-        if (ne) be = atomicAdd(&a.cnt->n[ge].v, ne);
-        if (ng) bg = atomicAdd(&a.cnt->n[gg].v, ng);
+        if (ne) be = atomicAdd(&a.cnt->ns[ge][st].v, ne);
+        if (ng) bg = atomicAdd(&a.cnt->ns[gg][st].v, ng);
       }
       be = __shfl(be, 0);
       bg = __shfl(bg, 0);
+      // slots within this block's stripe of each output queue
       const uint32_t s1 = c1e ? be + uint32_t(__popcll(me1 & below)) : bg + uint32_t(__popcll(mg1 & below));
       const uint32_t s2 = bg + ng1 + uint32_t(__popcll(mg2 & below));
       const uint32_t so = be + ne1 + uint32_t(__popcll(mep & below));
-      const bool ov = (c1.on && s1 >= a.cap) || (c2.on && s2 >= a.cap) || (park && so >= a.cap);
+      const bool ov = (c1.on && s1 >= cs) || (c2.on && s2 >= cs) || (park && so >= cs);
       if (ov) atomicOr(&a.cnt->overflow, uint32_t(OVF_QUEUE));
-      if (c1.on && s1 < a.cap) store_child(a, a.q[c1e ? ge : gg], s1, p, c1);
-      if (c2.on && s2 < a.cap) store_child(a, a.q[gg], s2, p, c2);
-      if (park && so < a.cap) store_part(a, a.q[ge], so, p);
+      if (c1.on && s1 < cs) store_child(a, a.q[c1e ? ge : gg], st * cs + s1, p, c1);
+      if (c2.on && s2 < cs) store_child(a, a.q[gg], st * cs + s2, p, c2);
+      if (park && so < cs) store_part(a, a.q[ge], st * cs + so, p);
     }
     if (park) alive = false;
   }
@@ -737,14 +780,16 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
 template <typename T>
 __global__ void k_advance(Counters* c, int par, uint32_t target, uint32_t cap) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  c->n[Q_G0 + 1 - par].v = min(c->n[Q_G0 + 1 - par].v, cap);
-  c->n[Q_E0 + 1 - par].v = min(c->n[Q_E0 + 1 - par].v, cap);
-  c->n[Q_G0 + par].v = 0u;
-  c->n[Q_E0 + par].v = 0u;
+  const uint32_t cs = cap / uint32_t(kStripes);
+  uint32_t pop = 0u;
+  for (int k = 0; k < kStripes; ++k) {
+    pop += min(c->ns[Q_G0 + 1 - par][k].v, cs) + min(c->ns[Q_E0 + 1 - par][k].v, cs);
+    c->ns[Q_G0 + par][k].v = 0u;
+    c->ns[Q_E0 + par][k].v = 0u;
+  }
   c->n[Q_KC].v = c->n[Q_KP].v = c->n[Q_KR].v = c->n[Q_KX].v = 0u;
   c->take_e.v = 0u;
   c->cursor += c->adm;
-  const uint32_t pop = c->n[Q_G0 + 1 - par].v + c->n[Q_E0 + 1 - par].v;
   const uint64_t rem = c->chunk_end - c->cursor;
   uint64_t adm = target > pop ? uint64_t(target - pop) : 0ull;
   if (adm > rem) adm = rem;
@@ -758,6 +803,8 @@ template <typename T>
 __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int q = 0; q < Q_NQ; ++q) c->n[q].v = 0u;
+  for (int q = 0; q < kStripedQueues; ++q)
+    for (int k = 0; k < kStripes; ++k) c->ns[q][k].v = 0u;
   c->overflow = 0u;
   c->done = 0u;
   c->iter = 0u;
