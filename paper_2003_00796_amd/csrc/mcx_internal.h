@@ -88,7 +88,10 @@ struct alignas(128) LineCount {
 // wavefront of three kernels: each is split into kStripes stripes of cap /
 // kStripes records with a counter each (a block appends to stripe
 // blockIdx % kStripes), so the atomics spread over as many cache lines.
-constexpr int kStripes = 8;
+#ifndef MCX_STRIPES
+#define MCX_STRIPES 8
+#endif
+constexpr int kStripes = MCX_STRIPES;
 constexpr int kStripedQueues = 4;
 
 struct Counters {
