@@ -164,6 +164,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
 // photon JUMP + STEP: free path in mass thickness, DDA through the voxels;
 // escaped photons end here, the others are sorted by interaction type
 // ---------------------------------------------------------------------------
+// voxels the photon walk computes ahead of the mass-thickness sum
+#ifndef MCX_WALK
+#define MCX_WALK 4
+#endif
+constexpr int kWalk = MCX_WALK;
+
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
   set_flavor<F>(a);
@@ -235,39 +241,76 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
       // of this free flight (-mu l_j per voxel, +1/rho at the interaction)
       const double cq = a.mode == 2 ? a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar : 0.0;
       const double mud = double(mt);
-      for (;;) {
-        const int ax = (t0 <= t1 && t0 <= t2) ? 0 : (t1 <= t2 ? 1 : 2);
-        const double tf = ax == 0 ? t0 : (ax == 1 ? t1 : t2);
-        const double s = tf - t;
-        const double rho = double(a.rho[v]);
-        if (rho * s >= tau) {
-          if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[v], cq * (-mud * (tau / rho) + 1.0 / rho));
-          t += tau / rho;
-          break;
-        }
-        if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[v], cq * (-mud * s));
-        tau -= rho * s;
-        t = tf;
-        bool out = false;
+      // The walk runs kWalk voxels ahead of the mass-thickness sum: the
+      // geometry of the next kWalk segments needs no density, so their
+      // densities are requested together and their latencies overlap.
+      bool ended = false;
+      while (!ended) {
+        double seg[kWalk], tend[kWalk];
+        uint32_t vs[kWalk];
+        int axs[kWalk];
+        bool outs[kWalk];
+        {
+          double u0 = t0, u1 = t1, u2 = t2, tc = t;
+          int j0 = p.ix[0], j1 = p.ix[1], j2 = p.ix[2];
+          uint32_t vc = v;
+          bool gone = false;  // an earlier segment of this batch leaves the phantom
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          if (k == ax) {
-            p.ix[k] += stp[k];
-            out = p.ix[k] < 0 || p.ix[k] >= nn[k];
+          for (int j = 0; j < kWalk; ++j) {
+            const int ax = (u0 <= u1 && u0 <= u2) ? 0 : (u1 <= u2 ? 1 : 2);
+            const double tf = ax == 0 ? u0 : (ax == 1 ? u1 : u2);
+            seg[j] = tf - tc;
+            tend[j] = tf;
+            vs[j] = vc;
+            axs[j] = ax;
+            if (ax == 0) { j0 += stp[0]; u0 += dt[0]; }
+            else if (ax == 1) { j1 += stp[1]; u1 += dt[1]; }
+            else { j2 += stp[2]; u2 += dt[2]; }
+            const bool out = j0 < 0 || j0 >= nn[0] || j1 < 0 || j1 >= nn[1] || j2 < 0 || j2 >= nn[2];
+            outs[j] = out;
+            gone = gone || out;
+            if (!gone) {
+              const int jx[3] = {j0, j1, j2};
+              vc = vlin(a, jx);
+            }
+            tc = tf;
           }
         }
-        if (ax == 0) t0 += dt[0];
-        else if (ax == 1) t1 += dt[1];
-        else t2 += dt[2];
-        ls.crossings++;
-        if (out) {
-          ledger_escape(a, &bs, p);
-          event(a, p, EV_PH_ESCAPE, v);
-          finish(a, p);
-          escaped = true;
-          break;
+        double rr[kWalk];
+#pragma unroll
+        for (int j = 0; j < kWalk; ++j) rr[j] = double(a.rho[vs[j]]);
+#pragma unroll
+        for (int j = 0; j < kWalk; ++j) {
+          if (!ended) {
+            const double rho = rr[j], sj = seg[j];
+            if (rho * sj >= tau) {
+              if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[vs[j]], cq * (-mud * (tau / rho) + 1.0 / rho));
+              t += tau / rho;
+              ended = true;
+            } else {
+              if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[vs[j]], cq * (-mud * sj));
+              tau -= rho * sj;
+              t = tend[j];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                if (k == axs[j]) p.ix[k] += stp[k];
+              }
+              if (axs[j] == 0) t0 += dt[0];
+              else if (axs[j] == 1) t1 += dt[1];
+              else t2 += dt[2];
+              ls.crossings++;
+              if (outs[j]) {
+                ledger_escape(a, &bs, p);
+                event(a, p, EV_PH_ESCAPE, vs[j]);
+                finish(a, p);
+                escaped = true;
+                ended = true;
+              } else {
+                v = vlin(a, p.ix);
+              }
+            }
+          }
         }
-        v = vlin(a, p.ix);
       }
       move(p, t);
       if (!escaped) {
