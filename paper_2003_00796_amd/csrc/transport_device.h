@@ -37,7 +37,7 @@ struct M<double> {
   static __device__ __forceinline__ double log(double x) { return ::log(x); }
   static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
   static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-  static __device__ __forceinline__ double pow(double a, double b) { return ::pow(a, b); }
+  static __device__ __forceinline__ double pow(double a, double b) { return ::exp(b * ::log(a)); }
   static __device__ __forceinline__ double log1p(double x) { return ::log1p(x); }
   static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
   static __device__ __forceinline__ double floor(double x) { return ::floor(x); }
@@ -686,14 +686,10 @@ __device__ __forceinline__ T range_at(const T* s, int n, int base, const Grid<T>
   const T si = s[(base + O_S) * n + g.i];
   const T q = s[(base + O_Q) * n + g.i];
   const T ri = s[(base + O_R) * n + g.i];
-  T seg;
-  if (is_fp64<T>()) {
-    seg = (q > T(-1e-10) && q < T(1e-10)) ? (ei / si) * M<T>::log(e / ei)
-                                          : (ei / si) * (M<T>::pow(e / ei, q) - T(1)) / q;
-  } else {
-    const T lr = le - (lemin + T(g.i) * dl);  // ln(E/E_i)
-    seg = (ei / si) * ((q > T(-1e-10) && q < T(1e-10)) ? lr : M<T>::expm1(q * lr) / q);
-  }
+  // (E_i/S_i) ((E/E_i)^q - 1)/q, written with expm1 of q ln(E/E_i): no
+  // power function and no cancellation near the node
+  const T lr = le - (lemin + T(g.i) * dl);  // ln(E/E_i)
+  const T seg = (ei / si) * ((q > T(-1e-10) && q < T(1e-10)) ? lr : M<T>::expm1(q * lr) / q);
   return ri + seg;
 }
 
@@ -711,8 +707,8 @@ __device__ __forceinline__ T range_inv(const T* s, int n, int base, T r, int hin
   const T si = s[(base + O_S) * n + lo];
   const T q = s[(base + O_Q) * n + lo];
   const T d = r - rr[lo];
+  // E_i (1 + d q S_i/E_i)^(1/q), as exp(log1p(.)/q)
   if (q > T(-1e-10) && q < T(1e-10)) return ei * M<T>::exp(d * si / ei);
-  if (is_fp64<T>()) return ei * M<T>::pow(T(1) + d * q * si / ei, T(1) / q);
   return ei * M<T>::exp(M<T>::log1p(d * q * si / ei) / q);
 }
 
