@@ -167,9 +167,13 @@ int mcx_load_phantom(mcx_ctx* ctx, const mcx_phantom_desc* p);
 /* Copy n >= 1 sources; history ids are their concatenation. */
 int mcx_set_sources(mcx_ctx* ctx, const mcx_source* s, int n);
 
-/* Tuning knobs (0 keeps the current value): bank = particles in flight per
- * queue (capacity of each event queue), block = threads per block (multiple
- * of 64, <= 1024), steps = Class II steps per visit of the e+- kernel. */
+/* Tuning knobs (0 keeps the current value): bank = records per event queue,
+ * in [1024, 2^26], default 2^24 (the population target is a quarter of it;
+ * the photon and e+- queues are split into 8 stripes of bank/8 records, and
+ * a run fails with MCX_E_RANGE if one fills), block = threads per block
+ * (multiple of 64, <= 256, default 256), steps = Class II steps per visit of
+ * the e+- kernel (default 128).  Device memory of the queues: about
+ * 8 x bank x (72 B FP32 physics, 88 B FP64). */
 int mcx_set_launch(mcx_ctx* ctx, uint32_t bank, uint32_t block, uint32_t steps);
 /* Replay each batch of event-loop iterations as one captured HIP graph
  * (1, default) or launch its kernels one by one (0).  Graphs are used only

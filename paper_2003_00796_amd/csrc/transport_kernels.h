@@ -245,9 +245,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
       // geometry of the next kWalk segments needs no density, so their
       // densities are requested together and their latencies overlap.
       bool ended = false;
+      uint32_t esc_v = v;
       while (!ended) {
+        // branch-free: the lanes of a wavefront walk different axes
         double seg[kWalk], tend[kWalk];
-        uint32_t vs[kWalk];
+        uint32_t vs[kWalk + 1];
         int axs[kWalk];
         bool outs[kWalk];
         {
@@ -257,60 +259,60 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
           bool gone = false;  // an earlier segment of this batch leaves the phantom
 #pragma unroll
           for (int j = 0; j < kWalk; ++j) {
-            const int ax = (u0 <= u1 && u0 <= u2) ? 0 : (u1 <= u2 ? 1 : 2);
-            const double tf = ax == 0 ? u0 : (ax == 1 ? u1 : u2);
+            const bool a0 = (u0 <= u1) & (u0 <= u2);
+            const bool a1 = !a0 & (u1 <= u2);
+            const bool a2 = !a0 & !a1;
+            const double tf = a0 ? u0 : (a1 ? u1 : u2);
             seg[j] = tf - tc;
             tend[j] = tf;
             vs[j] = vc;
-            axs[j] = ax;
-            if (ax == 0) { j0 += stp[0]; u0 += dt[0]; }
-            else if (ax == 1) { j1 += stp[1]; u1 += dt[1]; }
-            else { j2 += stp[2]; u2 += dt[2]; }
-            const bool out = j0 < 0 || j0 >= nn[0] || j1 < 0 || j1 >= nn[1] || j2 < 0 || j2 >= nn[2];
+            axs[j] = a0 ? 0 : (a1 ? 1 : 2);
+            j0 += a0 ? stp[0] : 0;
+            j1 += a1 ? stp[1] : 0;
+            j2 += a2 ? stp[2] : 0;
+            u0 = a0 ? u0 + dt[0] : u0;
+            u1 = a1 ? u1 + dt[1] : u1;
+            u2 = a2 ? u2 + dt[2] : u2;
+            const bool out = (j0 < 0) | (j0 >= nn[0]) | (j1 < 0) | (j1 >= nn[1]) | (j2 < 0) | (j2 >= nn[2]);
             outs[j] = out;
-            gone = gone || out;
-            if (!gone) {
-              const int jx[3] = {j0, j1, j2};
-              vc = vlin(a, jx);
-            }
+            gone = gone | out;
+            const int jx[3] = {j0, j1, j2};
+            vc = gone ? vc : vlin(a, jx);
             tc = tf;
           }
+          vs[kWalk] = vc;
         }
         double rr[kWalk];
 #pragma unroll
         for (int j = 0; j < kWalk; ++j) rr[j] = double(a.rho[vs[j]]);
 #pragma unroll
         for (int j = 0; j < kWalk; ++j) {
-          if (!ended) {
-            const double rho = rr[j], sj = seg[j];
-            if (rho * sj >= tau) {
-              if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[vs[j]], cq * (-mud * (tau / rho) + 1.0 / rho));
-              t += tau / rho;
-              ended = true;
-            } else {
-              if (cq != 0.0) unsafeAtomicAdd(&a.adj_grad[vs[j]], cq * (-mud * sj));
-              tau -= rho * sj;
-              t = tend[j];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                if (k == axs[j]) p.ix[k] += stp[k];
-              }
-              if (axs[j] == 0) t0 += dt[0];
-              else if (axs[j] == 1) t1 += dt[1];
-              else t2 += dt[2];
-              ls.crossings++;
-              if (outs[j]) {
-                ledger_escape(a, &bs, p);
-                event(a, p, EV_PH_ESCAPE, vs[j]);
-                finish(a, p);
-                escaped = true;
-                ended = true;
-              } else {
-                v = vlin(a, p.ix);
-              }
-            }
-          }
+          const double rho = rr[j], sj = seg[j];
+          const bool act = !ended;
+          const bool hit = act & (rho * sj >= tau);
+          const bool pass = act & !hit;
+          if (cq != 0.0 && act)
+            unsafeAtomicAdd(&a.adj_grad[vs[j]], hit ? cq * (-mud * (tau / rho) + 1.0 / rho) : cq * (-mud * sj));
+          t = hit ? t + tau / rho : (pass ? tend[j] : t);
+          tau = pass ? tau - rho * sj : tau;
+          p.ix[0] += (pass & (axs[j] == 0)) ? stp[0] : 0;
+          p.ix[1] += (pass & (axs[j] == 1)) ? stp[1] : 0;
+          p.ix[2] += (pass & (axs[j] == 2)) ? stp[2] : 0;
+          t0 = (pass & (axs[j] == 0)) ? t0 + dt[0] : t0;
+          t1 = (pass & (axs[j] == 1)) ? t1 + dt[1] : t1;
+          t2 = (pass & (axs[j] == 2)) ? t2 + dt[2] : t2;
+          ls.crossings += pass ? 1u : 0u;
+          const bool esc = pass & outs[j];
+          esc_v = esc ? vs[j] : esc_v;
+          escaped = escaped | esc;
+          v = (pass & !outs[j]) ? vs[j + 1] : v;
+          ended = ended | hit | esc;
         }
+      }
+      if (escaped) {
+        ledger_escape(a, &bs, p);
+        event(a, p, EV_PH_ESCAPE, esc_v);
+        finish(a, p);
       }
       move(p, t);
       if (!escaped) {
