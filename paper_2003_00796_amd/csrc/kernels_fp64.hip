@@ -1,6 +1,8 @@
 // kernels_fp64.hip -- FP64 instantiation of the transport kernels.  Built with
 // -ffp-contract=off: no multiply-add fusion, so the arithmetic follows the
 // order of the source expressions.
+#include <algorithm>
+
 #include "transport_kernels.h"
 
 namespace mcx {
@@ -70,6 +72,17 @@ hipError_t configure_fp64(int n_grid) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_cube_map(const double* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s) {
+  const uint64_t nv = uint64_t(nx) * ny * nz;
+  const unsigned g = unsigned(std::min<uint64_t>((nv + 255) / 256, 65536));
+  // seed, then the x, y and z passes: tmp -> out -> tmp -> out
+  hipLaunchKernelGGL(k_cube_seed<double>, dim3(g), dim3(256), 0, s, rho, nx, ny, nz, tmp);
+  hipLaunchKernelGGL(k_cube_pass<double>, dim3(g), dim3(256), 0, s, tmp, out, nx, ny, nz, 0);
+  hipLaunchKernelGGL(k_cube_pass<double>, dim3(g), dim3(256), 0, s, out, tmp, nx, ny, nz, 1);
+  hipLaunchKernelGGL(k_cube_pass<double>, dim3(g), dim3(256), 0, s, tmp, out, nx, ny, nz, 2);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint_weights(const double* dl_ddose, const double* rho, uint64_t nvox, double vol, double* w,

@@ -35,6 +35,9 @@ hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddos
                                    const float* rho, uint64_t nvox, double vol, double nhist, double* out,
                                    hipStream_t s);
 hipError_t launch_sum(const double* q, uint64_t n, double* out, hipStream_t s);
+// same-density cube half-widths of every voxel into `out` (tmp: nvox bytes)
+hipError_t launch_cube_map(const double* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s);
+hipError_t launch_cube_map(const float* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s);
 // LDS bytes the e+- kernel stages for a grid of n nodes
 size_t estep_lds_bytes(int n, bool fp64);
 hipError_t configure_kernels(int n_grid, bool fp64);

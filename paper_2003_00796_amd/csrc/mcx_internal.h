@@ -157,7 +157,11 @@ struct KArgs {
   // geometry
   int nx, ny, nz;
   double dx, dy, dz, ox, oy, oz;
+  double idx, idy, idz;  // 1 / voxel size
   const T* rho;
+  // per voxel: half-width (in voxels) of the largest cube around it that lies
+  // in the phantom and has its density throughout
+  const uint8_t* cube;
   // transport
   T eabs[3];
   T c2, wcc, wcr;

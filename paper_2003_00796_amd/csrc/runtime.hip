@@ -52,6 +52,7 @@ struct mcx_ctx {
   int nx = 0, ny = 0, nz = 0;
   double vox[3] = {0, 0, 0}, org[3] = {0, 0, 0};
   DevBuf d_rho;
+  DevBuf d_cube;  // same-density cube half-widths, one byte per voxel
   // sources
   std::vector<SourceDev> src;
   DevBuf d_src;
@@ -220,7 +221,9 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
   a.dx = c->vox[0]; a.dy = c->vox[1]; a.dz = c->vox[2];
   a.ox = c->org[0]; a.oy = c->org[1]; a.oz = c->org[2];
+  a.idx = 1.0 / c->vox[0]; a.idy = 1.0 / c->vox[1]; a.idz = 1.0 / c->vox[2];
   a.rho = static_cast<const T*>(c->d_rho.p);
+  a.cube = static_cast<const uint8_t*>(c->d_cube.p);
   for (int i = 0; i < 3; ++i) a.eabs[i] = T(c->tr.eabs[i]);
   a.c2 = T(c->tr.c2);
   a.wcc = T(c->tr.wcc);
@@ -390,7 +393,7 @@ void mcx_destroy(mcx_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
-  for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
+  for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_cube, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
                     &c->d_hvals, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad, &c->d_adj_dl, &c->d_adj_out,
                     &c->d_adj_sum, &c->d_hhash, &c->d_hled})
     dfree(*b);
@@ -495,6 +498,20 @@ int mcx_load_phantom(mcx_ctx* c, const mcx_phantom_desc* p) {
     e = hipMemcpy(c->d_rho.p, f.data(), nv * sizeof(float), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(c, e, "copy densities");
+  // same-density cubes for the photon walk (a scratch byte per voxel while
+  // the map is built)
+  if ((rc = dalloc(c, c->d_cube, nv, "same-density cube map"))) return rc;
+  {
+    DevBuf tmp;
+    if ((rc = dalloc(c, tmp, nv, "cube map scratch"))) return rc;
+    e = fp64(c) ? launch_cube_map(static_cast<const double*>(c->d_rho.p), p->nx, p->ny, p->nz,
+                                  static_cast<uint8_t*>(c->d_cube.p), static_cast<uint8_t*>(tmp.p), c->stream)
+                : launch_cube_map(static_cast<const float*>(c->d_rho.p), p->nx, p->ny, p->nz,
+                                  static_cast<uint8_t*>(c->d_cube.p), static_cast<uint8_t*>(tmp.p), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(tmp);
+    if (e != hipSuccess) return hip_fail(c, e, "same-density cube map");
+  }
   if ((rc = dalloc(c, c->d_sumq, nv * sizeof(double), "Sum q"))) return rc;
   if ((rc = dalloc(c, c->d_sumq2, nv * sizeof(double), "Sum q^2"))) return rc;
   c->nx = p->nx; c->ny = p->ny; c->nz = p->nz;

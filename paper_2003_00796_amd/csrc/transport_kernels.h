@@ -170,6 +170,54 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
 #endif
 constexpr int kWalk = MCX_WALK;
 
+// Same-density cubes.  cube[v] is the largest r <= kCubeMax such that every
+// voxel within Chebyshev distance r of v lies in the grid and has v's density:
+// the L-infinity distance from v to the nearest boundary voxel (one with a
+// face, edge or corner neighbour of another density or outside the grid).
+// Inside such a cube the mass thickness along a ray is the density times the
+// length, so the walk crosses the cube's inner faces in one step.
+constexpr int kCubeMax = 31;
+// smallest half-width for which the walk takes the one-step crossing
+#ifndef MCX_CUBE_MIN
+#define MCX_CUBE_MIN 2
+#endif
+constexpr uint32_t kCubeMin = MCX_CUBE_MIN;
+
+template <typename T>
+__global__ void k_cube_seed(const T* rho, int nx, int ny, int nz, uint8_t* out) {
+  const uint64_t nv = uint64_t(nx) * ny * nz;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nv; v += stride) {
+    const int x = int(v % uint64_t(nx)), y = int((v / uint64_t(nx)) % uint64_t(ny)), z = int(v / (uint64_t(nx) * ny));
+    bool edge = x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1;
+    const T r0 = rho[v];
+    for (int dz = -1; dz <= 1 && !edge; ++dz)
+      for (int dy = -1; dy <= 1 && !edge; ++dy)
+        for (int dx = -1; dx <= 1 && !edge; ++dx)
+          edge = rho[(uint64_t(z + dz) * ny + uint64_t(y + dy)) * nx + uint64_t(x + dx)] != r0;
+    out[v] = edge ? uint8_t(0) : uint8_t(kCubeMax);
+  }
+}
+
+// one separable pass of the L-infinity distance along axis ax:
+// out[v] = min over |d| <= kCubeMax of max(|d|, in[v + d e_ax])
+template <typename T>
+__global__ void k_cube_pass(const uint8_t* in, uint8_t* out, int nx, int ny, int nz, int ax) {
+  const uint64_t nv = uint64_t(nx) * ny * nz;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  const int n = ax == 0 ? nx : (ax == 1 ? ny : nz);
+  const uint64_t step = ax == 0 ? 1ull : (ax == 1 ? uint64_t(nx) : uint64_t(nx) * ny);
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nv; v += stride) {
+    const int c = int((v / step) % uint64_t(n));
+    int best = in[v];
+    for (int d = 1; d < best; ++d) {  // a term at offset d is at least d
+      if (c - d >= 0) best = min(best, max(d, int(in[v - uint64_t(d) * step])));
+      if (c + d < n) best = min(best, max(d, int(in[v + uint64_t(d) * step])));
+    }
+    out[v] = uint8_t(best);
+  }
+}
+
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
   set_flavor<F>(a);
@@ -237,6 +285,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
       bool escaped = false;
       uint32_t v = vlin(a, p.ix);
       double t0 = tn[0], t1 = tn[1], t2 = tn[2];
+      // faces per unit length along each axis (|d_k| / pitch), for counting
+      // the faces a cube crossing passes
+      const double it[3] = {fabs(double(p.d[0])) * a.idx, fabs(double(p.d[1])) * a.idy, fabs(double(p.d[2])) * a.idz};
+      double rho_v = double(a.rho[v]);
+      uint32_t cube_v = a.cube[v];
       // replay B: the history's centred weighted score times d ln p / d rho_j
       // of this free flight (-mu l_j per voxel, +1/rho at the interaction)
       const double cq = a.mode == 2 ? a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar : 0.0;
@@ -247,6 +300,59 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
       bool ended = false;
       uint32_t esc_v = v;
       while (!ended) {
+        if (cube_v >= kCubeMin) {
+          // one step to the first of: the interaction, were the cube's density
+          // to continue, and the cube's boundary; it crosses every face strictly
+          // before that point (at most cube_v per axis, all inside the cube) and
+          // leaves the decision at the point to the walk below
+          const double r = double(cube_v);
+          const double te = fmin(fmin(t0 + r * dt[0], t1 + r * dt[1]), t2 + r * dt[2]);
+          const double tt = fmin(te, t + tau / rho_v);
+          const int lim = int(cube_v);
+          const int n0 = tt > t0 ? min(lim, int(ceil((tt - t0) * it[0]))) : 0;
+          const int n1 = tt > t1 ? min(lim, int(ceil((tt - t1) * it[1]))) : 0;
+          const int n2 = tt > t2 ? min(lim, int(ceil((tt - t2) * it[2]))) : 0;
+          if (n0 + n1 + n2 > 0) {
+            double tl = t;  // the last face crossed
+            if (n0 > 0) tl = fmax(tl, t0 + double(n0 - 1) * dt[0]);
+            if (n1 > 0) tl = fmax(tl, t1 + double(n1 - 1) * dt[1]);
+            if (n2 > 0) tl = fmax(tl, t2 + double(n2 - 1) * dt[2]);
+            if (cq != 0.0) {
+              // replay B: the same faces one by one, for each voxel's length
+              double u0 = t0, u1 = t1, u2 = t2, tc = t;
+              int m0 = n0, m1 = n1, m2 = n2;
+              int jx[3] = {p.ix[0], p.ix[1], p.ix[2]};
+              for (int left = n0 + n1 + n2; left > 0; --left) {
+                // next face among the axes with faces left; ties in x, y, z order
+                const bool a0 = m0 > 0 && (m1 <= 0 || u0 <= u1) && (m2 <= 0 || u0 <= u2);
+                const bool a1 = !a0 && m1 > 0 && (m2 <= 0 || u1 <= u2);
+                const bool a2 = !a0 && !a1;
+                const double uk = a0 ? u0 : (a1 ? u1 : u2);
+                unsafeAtomicAdd(&a.adj_grad[vlin(a, jx)], cq * (-mud * (uk - tc)));
+                tc = uk;
+                u0 = a0 ? u0 + dt[0] : u0;
+                u1 = a1 ? u1 + dt[1] : u1;
+                u2 = a2 ? u2 + dt[2] : u2;
+                jx[0] += a0 ? stp[0] : 0;
+                jx[1] += a1 ? stp[1] : 0;
+                jx[2] += a2 ? stp[2] : 0;
+                m0 -= a0 ? 1 : 0;
+                m1 -= a1 ? 1 : 0;
+                m2 -= a2 ? 1 : 0;
+              }
+            }
+            tau = fmax(tau - rho_v * (tl - t), 0.0);
+            t = tl;
+            p.ix[0] += stp[0] * n0;
+            p.ix[1] += stp[1] * n1;
+            p.ix[2] += stp[2] * n2;
+            t0 += double(n0) * dt[0];
+            t1 += double(n1) * dt[1];
+            t2 += double(n2) * dt[2];
+            ls.crossings += uint32_t(n0 + n1 + n2);
+            v = vlin(a, p.ix);
+          }
+        }
         // branch-free: the lanes of a wavefront walk different axes
         double seg[kWalk], tend[kWalk];
         uint32_t vs[kWalk + 1];
@@ -285,6 +391,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
         double rr[kWalk];
 #pragma unroll
         for (int j = 0; j < kWalk; ++j) rr[j] = double(a.rho[vs[j]]);
+        // the voxel after the last segment: where the next pass starts
+        const double rho_n = double(a.rho[vs[kWalk]]);
+        const uint32_t cube_n = a.cube[vs[kWalk]];
 #pragma unroll
         for (int j = 0; j < kWalk; ++j) {
           const double rho = rr[j], sj = seg[j];
@@ -308,6 +417,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
           v = (pass & !outs[j]) ? vs[j + 1] : v;
           ended = ended | hit | esc;
         }
+        rho_v = rho_n;
+        cube_v = cube_n;
       }
       if (escaped) {
         ledger_escape(a, &bs, p);

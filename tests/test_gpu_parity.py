@@ -114,7 +114,7 @@ def test_c0_event_counts_match(c0):
         assert abs(g["stats"][k] - o["stats"][k]) <= 1e-3 * max(o["stats"][k], 1000), k
 
 
-@pytest.mark.parametrize("case", ["photon8_pair", "electron20", "positron5", "rect_hetero"])
+@pytest.mark.parametrize("case", ["photon8_pair", "electron20", "positron5", "rect_hetero", "blocks"])
 def test_particle_types_parity(case):
     if case == "photon8_pair":
         wl = dict(W.workload("water_pencil_32"), phantom=W.water_cube(16, 10.0),
@@ -125,6 +125,11 @@ def test_particle_types_parity(case):
     elif case == "positron5":
         wl = dict(W.workload("water_pencil_32"), phantom=W.water_cube(20, 4.0),
                   sources=[W.pencil(2, 5.0, (2.0, 2.0, 0.0), 1000)])
+    elif case == "blocks":
+        # same-density cubes of every size: the photon walk's one-step
+        # crossings start and end next to density changes on every axis
+        wl = dict(W.workload("hetero_broad_64"), phantom=W.block_phantom(),
+                  sources=[W.rect_field(0, 6.0, (6.4, 8.0, 0.0), (8.0, 8.0), 3000)])
     else:
         wl = W.workload("hetero_broad_64", 3000)
     n = wl["sources"][0]["n_hist"]

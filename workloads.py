@@ -57,6 +57,22 @@ def slab_phantom(nz: int, dz: float, rho_z, nxy: int = 1, dxy: float = 100.0) ->
     return dict(shape=(nz, nxy, nxy), voxel=(dxy, dxy, dz), origin=(0.0, 0.0, 0.0), rho=rho)
 
 
+def block_phantom(n: int = 32, voxel=(0.4, 0.5, 0.6), seed: int = 6) -> dict:
+    """Boxes of 1-6 voxels a side with densities drawn from {0.3, 1.0, 1.85},
+    painted in random order over water, then 60 isolated voxels of density
+    1.2: same-density regions of every size with ragged edges, on
+    non-cubic voxels (x, y, z pitch 4, 5, 6 mm by default)."""
+    rng = np.random.default_rng(seed)
+    rho = np.ones((n, n, n))
+    for _ in range(200):
+        s = rng.integers(1, 7, size=3)
+        o = rng.integers(0, n, size=3)
+        rho[o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]] = rng.choice([0.3, 1.0, 1.85])
+    iso = rng.integers(0, n, size=(60, 3))
+    rho[iso[:, 0], iso[:, 1], iso[:, 2]] = 1.2
+    return dict(shape=(n, n, n), voxel=tuple(voxel), origin=(0.0, 0.0, 0.0), rho=rho)
+
+
 def pencil(particle: int, energy: float, pos, n_hist: int, direction=(0.0, 0.0, 1.0)) -> dict:
     return dict(particle=particle, kind=0, energy=energy, pos=tuple(pos), dir=tuple(direction),
                 width=(0.0, 0.0), n_hist=int(n_hist))
