@@ -1,9 +1,13 @@
 // kernels_mixed.hip -- FP32-physics instantiation of the transport kernels
 // (positions, boundary distances, remaining mass thickness and tallies stay
 // FP64).  Multiply-add contraction is allowed here.
-// the FP32 step kernel fits 128 registers: bound it to 4 waves per SIMD
+// the FP32 step and photon-walk kernels fit 128 registers: bound them to 4
+// waves per SIMD
 #ifndef MCX_ESTEP_WAVES
 #define MCX_ESTEP_WAVES 4
+#endif
+#ifndef MCX_FLIGHT_WAVES
+#define MCX_FLIGHT_WAVES 4
 #endif
 #include <algorithm>
 

@@ -75,12 +75,15 @@ constexpr bool is_fp64() { return std::is_same<T, double>::value; }
 // key = (seed, history id); counter = (draw / 2, uid_lo, uid_hi, 0);
 // draw d is 64-bit word d % 2 of the call.
 //
-// A particle holds up to rng_pairs<T>() calls (two draws each) starting at an
-// even draw index.  The e+- step refills all of them at once at the start of
-// a step (`rng_refill`), so that the one inlined Philox site there runs with
-// every live lane; a draw that is not held computes its own call (the rest of
-// the kernels draw only this way).  FP32 paths keep only the upper 32 bits of
-// each 64-bit draw word: their uniforms use its top 23 bits.
+// A particle holds the draws [base, base + nw) in w[].  The e+- step refills
+// them at the start of a step (`rng_refill`): the rng_pairs<T>() calls from
+// the one holding draw ctr on, aligned so that w[0] is draw ctr.  The step's
+// draws then sit at offsets the compiler knows along its straight-line path,
+// and the one inlined Philox site runs with every live lane.  A draw that is
+// not held computes its own call (the rest of the kernels draw only this
+// way).  FP32 paths keep only the upper 32 bits of each 64-bit draw word:
+// their uniforms use its top 23 bits.  The seed is the same for every
+// particle of a launch, so its key schedule runs on the scalar unit.
 // ---------------------------------------------------------------------------
 #ifndef MCX_RNG_PAIRS
 #define MCX_RNG_PAIRS 4
@@ -106,8 +109,8 @@ struct Rng {
   using W = typename RngWord<T>::type;
   uint32_t k0, k1, u0, u1;
   uint32_t ctr;   // next draw index
-  uint32_t base;  // draw index of w[0] (even)
-  uint32_t nw;    // draws held in w[] (0 or an even number <= 2 rng_pairs<T>())
+  uint32_t base;  // draw index of w[0]
+  uint32_t nw;    // draws held in w[]
   W w[2 * rng_pairs<T>()];
 };
 
@@ -145,22 +148,36 @@ __device__ __forceinline__ void rng_init(Rng<T>& r, uint32_t seed, uint32_t hist
   r.k0 = seed; r.k1 = hist;
   r.u0 = uint32_t(uid); r.u1 = uint32_t(uid >> 32);
   r.ctr = ctr;
-  r.base = 0u;
+  r.base = ctr;
   r.nw = 0u;
 }
 
-// compute the rng_pairs<T>() calls from the one holding draw ctr on
+// one Philox call of the particle's stream (the seed is wave-uniform)
+template <typename T>
+__device__ __forceinline__ void rng_call(const Rng<T>& r, uint32_t pair, uint32_t* o) {
+  philox10(pair, r.u0, r.u1, 0u, __builtin_amdgcn_readfirstlane(r.k0), r.k1, o);
+}
+
+// hold the draws from ctr on: rng_pairs<T>() calls from the one holding draw
+// ctr; when ctr is odd the first word of that call is already used
 template <typename T>
 __device__ __forceinline__ void rng_refill(Rng<T>& r) {
+  using W = typename RngWord<T>::type;
+  constexpr int kW = 2 * rng_pairs<T>();
   const uint32_t pair = r.ctr >> 1;
+  W raw[kW];
 #pragma unroll
   for (int j = 0; j < rng_pairs<T>(); ++j) {
     uint32_t o[4];
-    philox10(pair + uint32_t(j), r.u0, r.u1, 0u, r.k0, r.k1, o);
-    pair_words(o, &r.w[2 * j], &r.w[2 * j + 1]);
+    rng_call(r, pair + uint32_t(j), o);
+    pair_words(o, &raw[2 * j], &raw[2 * j + 1]);
   }
-  r.base = pair << 1;
-  r.nw = 2u * rng_pairs<T>();
+  const bool odd = (r.ctr & 1u) != 0u;
+#pragma unroll
+  for (int j = 0; j < kW - 1; ++j) r.w[j] = odd ? raw[j + 1] : raw[j];
+  r.w[kW - 1] = raw[kW - 1];
+  r.base = r.ctr;
+  r.nw = odd ? uint32_t(kW - 1) : uint32_t(kW);
 }
 
 // next draw word (unrolled selects: no runtime-indexed private array)
@@ -169,12 +186,15 @@ __device__ __forceinline__ typename RngWord<T>::type rng_next(Rng<T>& r) {
   uint32_t off = r.ctr - r.base;
   if (!(off < r.nw)) {
     uint32_t o[4];
-    const uint32_t pair = r.ctr >> 1;
-    philox10(pair, r.u0, r.u1, 0u, r.k0, r.k1, o);
-    pair_words(o, &r.w[0], &r.w[1]);
-    r.base = pair << 1;
-    r.nw = 2u;
-    off = r.ctr & 1u;
+    rng_call(r, r.ctr >> 1, o);
+    typename RngWord<T>::type w0, w1;
+    pair_words(o, &w0, &w1);
+    const bool odd = (r.ctr & 1u) != 0u;
+    r.w[0] = odd ? w1 : w0;
+    r.w[1] = w1;
+    r.base = r.ctr;
+    r.nw = odd ? 1u : 2u;
+    off = 0u;
   }
   typename RngWord<T>::type v = r.w[0];
 #pragma unroll

@@ -179,7 +179,7 @@ constexpr int kWalk = MCX_WALK;
 constexpr int kCubeMax = 31;
 // smallest half-width for which the walk takes the one-step crossing
 #ifndef MCX_CUBE_MIN
-#define MCX_CUBE_MIN 2
+#define MCX_CUBE_MIN 1
 #endif
 constexpr uint32_t kCubeMin = MCX_CUBE_MIN;
 
@@ -218,8 +218,11 @@ __global__ void k_cube_pass(const uint8_t* in, uint8_t* out, int nx, int ny, int
   }
 }
 
+#ifndef MCX_FLIGHT_WAVES
+#define MCX_FLIGHT_WAVES 1
+#endif
 template <typename T, int F>
-__global__ __launch_bounds__(kMaxBlock) void k_flight(KArgs<T> a, int par) {
+__global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T> a, int par) {
   set_flavor<F>(a);
   const uint32_t cs = stripe_cap(a);
   const StripeSums sums = stripe_sums(a.cnt, q_gin(par), cs);
