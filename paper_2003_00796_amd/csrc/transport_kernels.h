@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
 // ---------------------------------------------------------------------------
 // voxels the photon walk computes ahead of the mass-thickness sum
 #ifndef MCX_WALK
-#define MCX_WALK 4
+#define MCX_WALK 2
 #endif
 constexpr int kWalk = MCX_WALK;
 
@@ -176,7 +176,11 @@ constexpr int kWalk = MCX_WALK;
 // face, edge or corner neighbour of another density or outside the grid).
 // Inside such a cube the mass thickness along a ray is the density times the
 // length, so the walk crosses the cube's inner faces in one step.
-constexpr int kCubeMax = 31;
+#ifndef MCX_CUBE_MAX
+#define MCX_CUBE_MAX 31
+#endif
+constexpr int kCubeMax = MCX_CUBE_MAX;  // stored in a byte
+static_assert(kCubeMax >= 1 && kCubeMax <= 255, "cube half-width must fit a byte");
 // smallest half-width for which the walk takes the one-step crossing
 #ifndef MCX_CUBE_MIN
 #define MCX_CUBE_MIN 1
