@@ -172,12 +172,17 @@ __device__ __forceinline__ void rng_refill(Rng<T>& r) {
     rng_call(r, pair + uint32_t(j), o);
     pair_words(o, &raw[2 * j], &raw[2 * j + 1]);
   }
-  const bool odd = (r.ctr & 1u) != 0u;
+  // shift by one word when ctr is odd, as a bitwise blend: written as a
+  // select, the compiler turns the shift into an indexed load from a stack
+  // copy of raw[] (a scratch round trip per step); the bit-field extract
+  // keeps the mask opaque to that rewrite
+  const uint32_t odd = __builtin_amdgcn_ubfe(r.ctr, 0u, 1u);
+  const W m = W(0) - W(odd);
 #pragma unroll
-  for (int j = 0; j < kW - 1; ++j) r.w[j] = odd ? raw[j + 1] : raw[j];
+  for (int j = 0; j < kW - 1; ++j) r.w[j] = (raw[j] & ~m) | (raw[j + 1] & m);
   r.w[kW - 1] = raw[kW - 1];
   r.base = r.ctr;
-  r.nw = odd ? uint32_t(kW - 1) : uint32_t(kW);
+  r.nw = uint32_t(kW) - odd;
 }
 
 // next draw word (unrolled selects: no runtime-indexed private array)
