@@ -15,11 +15,12 @@
 // tail of the e+- kernel: once the input queue is empty, a wavefront keeps
 // stepping its particles for at least MCX_TAIL_MIN more steps, then writes
 // them all back as soon as fewer than MCX_TAIL_ALIVE of its lanes hold one
+// (64: as soon as one lane is idle)
 #ifndef MCX_TAIL_MIN
-#define MCX_TAIL_MIN 8
+#define MCX_TAIL_MIN 16
 #endif
 #ifndef MCX_TAIL_ALIVE
-#define MCX_TAIL_ALIVE 16
+#define MCX_TAIL_ALIVE 64
 #endif
 
 namespace mcx {
