@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes (host cores used)")
     ap.add_argument("--electron", action="store_true", help="also time the 20 MeV electron workload")
     ap.add_argument("--no-fp64", action="store_true")
+    # records per event queue: 2^26 puts a quarter of it, 16.8 M particles,
+    # in flight at once (all histories of a 1e7 step are admitted together)
+    ap.add_argument("--bank", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--beamlets", type=int, default=0, metavar="TOTAL",
@@ -272,6 +275,7 @@ def main():
     seeds = [1 + i for i in range(args.steps)]
 
     mix = mcx.Simulator(mcx.MIXED, 0).setup(wl)
+    mix.set_launch(args.bank, 256, 128)
     run_steps(mix, n, warm_seeds, sync)
     mix.set_timing(True)
     t_mix = run_steps(mix, n, seeds, sync)
@@ -282,6 +286,7 @@ def main():
     result_64 = None
     if not args.no_fp64:
         f64 = mcx.Simulator(mcx.FP64, 0).setup(wl)
+        f64.set_launch(args.bank, 256, 128)
         run_steps(f64, n, warm_seeds, sync)
         t_64 = run_steps(f64, n, seeds, sync)
         d_64, _ = f64.dose()
@@ -307,7 +312,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "hetero_broad_128: 6 MeV photon 10x10 cm field, 128^3 x 2 mm phantom "
                                "(water, lung slab 0.26, 8 bone spheres 1.85), mixed precision (FP32 physics, "
-                               "FP64 positions and tallies)", "histories_per_step": n, "parallelism": "single GPU"},
+                               "FP64 positions and tallies)", "histories_per_step": n, "parallelism": "single GPU",
+                   "launch": {"bank": args.bank, "block": 256, "steps": 128}},
         "fp64": result_64,
         "mixed_over_fp64": (value / result_64["value"]) if result_64 else None,
         "high_dose_deviation": dev if result_64 else None,

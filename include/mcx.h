@@ -168,7 +168,7 @@ int mcx_load_phantom(mcx_ctx* ctx, const mcx_phantom_desc* p);
 int mcx_set_sources(mcx_ctx* ctx, const mcx_source* s, int n);
 
 /* Tuning knobs (0 keeps the current value): bank = records per event queue,
- * in [1024, 2^26], default 2^24 (the population target is a quarter of it;
+ * in [1024, 2^26], default 2^25 (the population target is a quarter of it;
  * the photon and e+- queues are split into 8 stripes of bank/8 records, and
  * a run fails with MCX_E_RANGE if one fills), block = threads per block
  * (multiple of 64, <= 256, default 256), steps = Class II steps per visit of

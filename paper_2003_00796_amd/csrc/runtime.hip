@@ -61,7 +61,7 @@ struct mcx_ctx {
   DevBuf d_sumq, d_sumq2;
   uint64_t n_done = 0;
   // event queues
-  uint32_t cap = 1u << 24, block = 256, steps = 128;
+  uint32_t cap = 1u << 25, block = 256, steps = 128;
   DevBuf d_queues;
   size_t queue_cap_built = 0;
   DevBuf d_cnt;

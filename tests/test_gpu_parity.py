@@ -267,15 +267,16 @@ def test_autotune_picks_and_caches(tmp_path):
 
 def test_full_size_sampled_histories():
     """The benchmark workload at its full size (1e7 histories of the 6 MeV
-    field on the 128^3 heterogeneous phantom) in the default launch
-    configuration: a sample of histories spread over the whole range is
-    transported one by one by the oracle and compared with the GPU's
-    per-history results (FP64); every history of the run conserves energy, in
-    both precisions."""
+    field on the 128^3 heterogeneous phantom) in the launch configuration the
+    benchmark times (2^26 records per queue, blocks of 256, 128 steps per
+    visit): a sample of histories spread over the whole range is transported
+    one by one by the oracle and compared with the GPU's per-history results
+    (FP64); every history of the run conserves energy, in both precisions."""
     wl = W.workload("hetero_broad_128")
     n = wl["sources"][0]["n_hist"]
     assert n == 10_000_000
-    g64 = gpu_run(wl, n, precision=0)
+    launch = (1 << 26, 256, 128)
+    g64 = gpu_run(wl, n, precision=0, launch=launch)
     check_balance(g64["led"], 6.0, 1e-12)
     rng = np.random.default_rng(11)
     sample = np.sort(rng.choice(n, size=300, replace=False))
@@ -292,6 +293,6 @@ def test_full_size_sampled_histories():
     assert g64["stats"]["histories"] == n
     assert np.isclose(g64["q"].sum(), g64["led"][:, 0].sum(), rtol=1e-9)
     del g64
-    g32 = gpu_run(wl, n, precision=1)
+    g32 = gpu_run(wl, n, precision=1, launch=launch)
     check_balance(g32["led"], 6.0, 2e-5)
     assert g32["stats"]["histories"] == n
