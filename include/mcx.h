@@ -41,7 +41,7 @@ extern "C" {
 #define MCX_E_NOMEM (-3)       /* device or host allocation failed */
 #define MCX_E_DEVICE (-4)      /* HIP runtime error or device fault */
 #define MCX_E_RANGE (-5)       /* a capacity or energy range exceeded */
-#define MCX_E_CANCELLED (-6)   /* reserved: run stopped on request */
+#define MCX_E_CANCELLED (-6)   /* run stopped on request (mcx_cancel) */
 #define MCX_E_UNSUPPORTED (-7) /* feature not available in this build */
 
 #define MCX_FP64 0   /* all physics and sampling in FP64 */
@@ -146,6 +146,9 @@ typedef struct {
   uint64_t timed_iterations;
   /* host wall time of the two density-gradient replays */
   double ms_backward;
+  /* first history id the last mcx_run did not complete: first_hist + n_hist
+   * after a complete run, the cancellation watermark after MCX_E_CANCELLED */
+  uint64_t next_history;
 } mcx_stats;
 
 /* Create a context on HIP device `hip_device` computing in `precision`
@@ -198,7 +201,8 @@ int mcx_set_test_mode(mcx_ctx* ctx, int on);
  * complete when the call returns (kernels are queued on `stream`, the call
  * waits for them).  Deterministic event content for a given
  * (seed, history range).  first_hist + n_hist must not exceed the total of
- * the sources nor 2^32. */
+ * the sources nor 2^32.  Returns MCX_E_CANCELLED, with the histories before
+ * mcx_stats.next_history complete and tallied, when it honours mcx_cancel. */
 int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, void* stream);
 
 /* Gradient of a dose loss with respect to every voxel density.  dl_ddose
@@ -229,6 +233,57 @@ int mcx_get_tally(mcx_ctx* ctx, double* sum_q, double* sum_q2, int dst_on_device
 int mcx_reset_tallies(mcx_ctx* ctx);
 /* Statistics since the last reset. */
 int mcx_get_stats(mcx_ctx* ctx, mcx_stats* out);
+
+/* Wait for the work queued on the context's own stream and report a device
+ * fault or an earlier asynchronous HIP error as MCX_E_DEVICE.  (mcx_run and
+ * the result calls already wait for their own work before returning.) */
+int mcx_synchronize(mcx_ctx* ctx);
+
+/* Ask the run in progress to stop early; the only call that may come from
+ * another host thread while mcx_run executes.  The request stays pending
+ * until a forward run honours it at a completion check (after each batch of
+ * event-loop iterations; the density-gradient replays ignore it): the run
+ * starts no further history, completes the histories already started, adds
+ * them to the tallies and returns MCX_E_CANCELLED (or MCX_OK, the request
+ * dropped, if every history had started by then).  The completed histories
+ * are [first_hist, mcx_stats.next_history); a later mcx_run of the rest with
+ * the same seed gives the tallies of the uninterrupted run (histories are
+ * independent and their random streams depend only on (seed, history id);
+ * Sec. 4.3), up to the order of FP64 summation. */
+int mcx_cancel(mcx_ctx* ctx);
+
+/* Checkpoint of the accumulated result, to resume in another context or
+ * process: Sum q, Sum q^2, the history count, next_history and the
+ * statistics, with a format tag and a checksum.  With buf == NULL, *size
+ * receives the size in bytes (16 * nx*ny*nz plus a few hundred); otherwise
+ * buf (host memory, *size bytes, MCX_E_RANGE if too small) receives the
+ * checkpoint and *size its length. */
+int mcx_checkpoint(mcx_ctx* ctx, void* buf, size_t* size);
+/* Replace the tallies, history count and statistics of ctx by a checkpoint
+ * (host memory, size bytes).  The context must have the checkpoint's
+ * precision and phantom grid (MCX_E_INVALID otherwise, and for a buffer that
+ * is not an intact checkpoint).  Later runs accumulate onto it; the density
+ * gradient needs a run of its own context (MCX_E_STATE until then). */
+int mcx_restore(mcx_ctx* ctx, const void* buf, size_t size);
+
+/* Device bytes a run needs besides the tallies, tables and phantom: the
+ * event queues of the current bank size, the loop counters and the
+ * (history, voxel) tally table at its full 2^29 slots (16 B each). */
+int mcx_workspace_size(mcx_ctx* ctx, size_t* bytes);
+/* Run in caller-owned device memory (e.g. a torch tensor) instead of memory
+ * the library allocates: queues, loop counters and tally table are carved
+ * from [dev, dev + bytes), dev 256-byte aligned (MCX_E_INVALID otherwise).
+ * The table takes the largest power-of-two number of slots, up to 2^29, that
+ * fits after the queues; chunks of histories are sized to it.  bytes must
+ * leave room for 2^20 slots (MCX_E_RANGE otherwise, and the library's own
+ * memory is used again); mcx_workspace_size gives the size for the full
+ * table.  The call waits for the device to be idle, so the memory must only
+ * hold work queued before it; it must stay valid and unused by others until
+ * mcx_set_workspace(ctx, NULL, 0) (back to library memory) or mcx_destroy.
+ * A later bank size that does not fit makes mcx_run fail with MCX_E_RANGE.
+ * Statistics are kept across the change.  The per-history test outputs and
+ * the gradient's buffers are still allocated by the library. */
+int mcx_set_workspace(mcx_ctx* ctx, void* dev, size_t bytes);
 
 /* Per-history results of the LAST mcx_run (test mode only, else
  * MCX_E_STATE): hashes[n_hist] = order-independent hash of the history's

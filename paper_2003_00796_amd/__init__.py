@@ -31,7 +31,9 @@ ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM"
 ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport", "mcx_load_material",
                "mcx_load_phantom", "mcx_set_sources", "mcx_set_launch", "mcx_set_timing", "mcx_set_test_mode", "mcx_run",
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
-               "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune")
+               "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune",
+               "mcx_synchronize", "mcx_cancel", "mcx_checkpoint", "mcx_restore", "mcx_workspace_size",
+               "mcx_set_workspace")
 
 
 class MaterialDesc(C.Structure):
@@ -67,7 +69,7 @@ class Stats(C.Structure):
         ("chunks", C.c_uint64), ("tally_pairs", C.c_uint64), ("ms_transport", C.c_double),
         ("ms_flush", C.c_double), ("evisits", C.c_uint64), ("ewrites", C.c_uint64), ("inserts", C.c_uint64),
         ("ms_source", C.c_double), ("ms_flight", C.c_double), ("ms_knock", C.c_double), ("ms_estep", C.c_double),
-        ("timed_iterations", C.c_uint64), ("ms_backward", C.c_double)]
+        ("timed_iterations", C.c_uint64), ("ms_backward", C.c_double), ("next_history", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -75,6 +77,15 @@ class Stats(C.Structure):
 
 class MCXError(RuntimeError):
     pass
+
+
+class MCXCancelled(MCXError):
+    """mcx_run honoured mcx_cancel: histories [first, next_history) are
+    complete and in the tallies."""
+
+    def __init__(self, msg: str, next_history: int):
+        super().__init__(msg)
+        self.next_history = next_history
 
 
 _lib = None
@@ -117,6 +128,12 @@ def lib():
         L.mcx_dose_backward.argtypes = [vp, vp, vp, C.c_int, vp]
         L.mcx_set_graph.argtypes = [vp, C.c_int]
         L.mcx_autotune.argtypes = [vp, C.c_uint64, C.c_char_p, C.POINTER(C.c_uint32)]
+        L.mcx_synchronize.argtypes = [vp]
+        L.mcx_cancel.argtypes = [vp]
+        L.mcx_checkpoint.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.mcx_restore.argtypes = [vp, vp, C.c_size_t]
+        L.mcx_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.mcx_set_workspace.argtypes = [vp, vp, C.c_size_t]
         for f in ABI_SYMBOLS:
             if f not in ("mcx_destroy", "mcx_last_error"):
                 getattr(L, f).restype = C.c_int
@@ -147,6 +164,7 @@ class Simulator:
         self.precision = precision
         self.shape = None
         self.n_hist_total = 0
+        self._workspace = None  # device tensor the context carves its run memory from
 
     def close(self):
         if self._h:
@@ -240,8 +258,48 @@ class Simulator:
         return self
 
     def run(self, seed: int, first: int, n: int, stream=None):
+        """Histories [first, first + n); raises MCXCancelled (with the
+        watermark) when the run honoured a cancel request."""
         sp = C.c_void_p(stream) if stream else None
-        self._check(self._L.mcx_run(self._h, seed, first, n, sp), "run")
+        rc = self._L.mcx_run(self._h, seed, first, n, sp)
+        if rc == -6:
+            msg = self._L.mcx_last_error(self._h).decode(errors="replace")
+            raise MCXCancelled(f"run: MCX_E_CANCELLED: {msg}", self.stats()["next_history"])
+        self._check(rc, "run")
+
+    def cancel(self):
+        """Ask the run in progress (or the next one) to stop; thread-safe."""
+        self._check(self._L.mcx_cancel(self._h), "cancel")
+
+    def synchronize(self):
+        self._check(self._L.mcx_synchronize(self._h), "synchronize")
+
+    def checkpoint(self) -> bytes:
+        n = C.c_size_t(0)
+        self._check(self._L.mcx_checkpoint(self._h, None, C.byref(n)), "checkpoint")
+        buf = C.create_string_buffer(n.value)
+        self._check(self._L.mcx_checkpoint(self._h, buf, C.byref(n)), "checkpoint")
+        return buf.raw[:n.value]
+
+    def restore(self, data: bytes):
+        buf = C.create_string_buffer(bytes(data), len(data))
+        self._check(self._L.mcx_restore(self._h, buf, len(data)), "restore")
+
+    def workspace_size(self) -> int:
+        n = C.c_size_t(0)
+        self._check(self._L.mcx_workspace_size(self._h, C.byref(n)), "workspace_size")
+        return n.value
+
+    def set_workspace(self, buf=None):
+        """Carve the run's queues, counters and tally table from a device
+        tensor (kept referenced here); None returns to library memory."""
+        if buf is None:
+            self._check(self._L.mcx_set_workspace(self._h, None, 0), "set_workspace")
+            self._workspace = None
+            return
+        self._check(self._L.mcx_set_workspace(self._h, C.c_void_p(buf.data_ptr()),
+                                              buf.numel() * buf.element_size()), "set_workspace")
+        self._workspace = buf
 
     def reset(self):
         self._check(self._L.mcx_reset_tallies(self._h), "reset_tallies")

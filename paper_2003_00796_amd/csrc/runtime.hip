@@ -8,9 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -36,6 +38,7 @@ using namespace mcx;
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool ext = false;  // carved from the caller's workspace: never freed here
 };
 
 struct mcx_ctx {
@@ -71,6 +74,14 @@ struct mcx_ctx {
   DevBuf d_hkeys, d_hvals;
   double pairs_per_hist = 0.0;
   bool table_dirty = false;  // a failed run may have left entries behind
+  // caller-owned workspace (mcx_set_workspace): queues, counters and tally
+  // table are carved from it; ws_cap is the bank size of the current carve
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t ws_cap = 0;
+  // cancellation request (mcx_cancel may be called from another host thread)
+  std::atomic<int> cancel{0};
+  uint64_t next_history = 0;  // first history id not completed by the last run
   // test mode
   int test_mode = 0;
   DevBuf d_hhash, d_hled;
@@ -123,9 +134,10 @@ int hip_fail(mcx_ctx* c, hipError_t e, const char* what) {
 }
 
 void dfree(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+  if (b.p && !b.ext) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
+  b.ext = false;
 }
 
 int dalloc(mcx_ctx* c, DevBuf& b, size_t bytes, const char* what) {
@@ -169,9 +181,56 @@ size_t queue_bytes(const mcx_ctx* c) {
   return per * Q_NQ;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr uint64_t kTableSlots = 1ull << MCX_TALLY_LOG2;  // library-owned table
+constexpr uint64_t kMinWsSlots = 1ull << 20;              // smallest table in a workspace
+constexpr size_t kSlotBytes = sizeof(uint64_t) + sizeof(double);
+
+// queues and counters of a workspace carve (the table follows them)
+size_t ws_fixed_bytes(const mcx_ctx* c) { return align256(queue_bytes(c)) + align256(sizeof(Counters)); }
+
+// carve queues, counters and the largest power-of-two tally table that fits
+// from the caller's workspace, and clear counters and table
+int carve_workspace(mcx_ctx* c) {
+  const size_t fixed = ws_fixed_bytes(c);
+  if (c->ws_bytes < fixed + kMinWsSlots * kSlotBytes)
+    return fail(c, MCX_E_RANGE, "workspace of %zu bytes is too small for a bank of %u records (needs >= %zu)", c->ws_bytes,
+                c->cap, fixed + size_t(kMinWsSlots * kSlotBytes));
+  uint64_t slots = kTableSlots;
+  const uint64_t room = (c->ws_bytes - fixed) / kSlotBytes;
+  while (slots > room) slots >>= 1;
+  char* base = static_cast<char*>(c->ws);
+  const size_t qb = align256(queue_bytes(c));
+  c->d_queues = DevBuf{base, qb, true};
+  c->d_cnt = DevBuf{base + qb, sizeof(Counters), true};
+  c->d_hkeys = DevBuf{base + fixed, slots * sizeof(uint64_t), true};
+  c->d_hvals = DevBuf{base + fixed + slots * sizeof(uint64_t), slots * sizeof(double), true};
+  c->hslots = slots;
+  c->queue_cap_built = c->cap;
+  c->ws_cap = c->cap;
+  hipError_t e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_hkeys.p, 0xFF, slots * sizeof(uint64_t), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, slots * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "clear workspace");
+  c->table_dirty = false;
+  return MCX_OK;
+}
+
 int ensure_workspace(mcx_ctx* c) {
   int rc;
-  if (c->queue_cap_built != c->cap || !c->d_queues.p) {
+  if (c->ws && c->ws_cap != c->cap) {
+    // a new bank size moves everything after the queues: carry the
+    // statistics counters over
+    Counters saved;
+    const bool have_cnt = c->d_cnt.p != nullptr;
+    if (have_cnt && hipMemcpy(&saved, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(c, MCX_E_DEVICE, "read statistics");
+    if ((rc = carve_workspace(c))) return rc;
+    if (have_cnt && hipMemcpy(c->d_cnt.p, &saved, sizeof(Counters), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, MCX_E_DEVICE, "restore statistics");
+  }
+  if (!c->ws && (c->queue_cap_built != c->cap || !c->d_queues.p)) {
     dfree(c->d_queues);
     if ((rc = dalloc(c, c->d_queues, queue_bytes(c), "event queues"))) return rc;
     c->queue_cap_built = c->cap;
@@ -253,9 +312,36 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   }
 }
 
+// Checkpoint: this header, then Sum q and Sum q^2 (nvox doubles each), then
+// an FNV-1a hash of every byte before it.
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t precision;
+  int32_t nx, ny, nz;
+  uint32_t nstat;
+  uint32_t run_seed;
+  uint32_t run_known;
+  uint32_t reserved;
+  double voxel[3];
+  uint64_t n_done, next_history, run_first, run_n;
+  uint64_t iterations, chunks, tally_pairs;
+  double ms_transport, ms_flush;
+  uint64_t stat[S_NSTAT];
+  double e_dep, e_esc;
+};
+constexpr char kCkptMagic[8] = {'M', 'C', 'X', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+size_t ckpt_bytes(const mcx_ctx* c) { return sizeof(CkptHeader) + 2 * nvox(c) * sizeof(double) + sizeof(uint64_t); }
+
+// Histories [first, first + n) in chunks.  *completed receives the number of
+// histories transported: n, or fewer when a forward run honours a
+// cancellation request (then MCX_E_CANCELLED).
 template <typename T>
 int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t s, int mode = 0,
-             double qbar = 0.0) {
+             double qbar = 0.0, uint64_t* completed = nullptr) {
+  if (completed) *completed = 0;
   KArgs<T> a;
   fill_args(c, a, seed, mode, qbar);
   const uint32_t target = c->cap / 4;
@@ -290,10 +376,11 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       if (g) (void)hipGraphExecDestroy(g);
     }
   } guard{gexec};
-  while (done < n) {
+  bool cancelled = false;
+  while (done < n && !cancelled) {
     uint64_t chunk;
     if (c->pairs_per_hist > 0.0) chunk = uint64_t(double(table_budget) / (1.25 * c->pairs_per_hist));
-    else chunk = 1ull << 16;
+    else chunk = std::min<uint64_t>(1ull << 16, table_budget / 64);  // first chunk: up to 64 pairs a history
     chunk = std::max<uint64_t>(chunk, 1024);
     chunk = std::min<uint64_t>(chunk, n - done);
     const uint64_t cf = first + done, ce = cf + chunk;
@@ -333,7 +420,21 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       if (c->h_cnt->overflow & OVF_SOURCE) return fail(c, MCX_E_INVALID, "a source point lies outside the phantom");
       if (c->h_cnt->overflow & OVF_LOST) return fail(c, MCX_E_DEVICE, "a particle lost its direction (no exit face)");
       if (c->h_cnt->done) break;
+      if (mode == 0 && !cancelled && c->cancel.exchange(0) != 0) {
+        // close admission: the histories admitted so far, [cf, cursor), run
+        // to completion and are flushed as usual; no later one starts
+        cancelled = true;
+        c->h_cnt->chunk_end = c->h_cnt->cursor;
+        c->h_cnt->adm = 0u;
+        char* dc = reinterpret_cast<char*>(a.cnt);
+        e = hipMemcpyAsync(dc + offsetof(Counters, chunk_end), &c->h_cnt->chunk_end, sizeof(uint64_t),
+                           hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(dc + offsetof(Counters, adm), &c->h_cnt->adm, sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(c, e, "close admission");
+      }
     }
+    if (cancelled) chunk = c->h_cnt->chunk_end - cf;
     if (mode != 0) {  // replays leave the tally table untouched
       done += chunk;
       continue;
@@ -346,19 +447,23 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
     flush_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
     const double pairs = double(c->h_cnt->occupied);
     c->tally_pairs += c->h_cnt->occupied;
-    const double pph = pairs / double(chunk);
+    const double pph = chunk ? pairs / double(chunk) : 0.0;
     c->pairs_per_hist = std::max(c->pairs_per_hist * 0.5, pph);
     if (c->pairs_per_hist < 1.0) c->pairs_per_hist = 1.0;
     c->chunks++;
     done += chunk;
   }
   const double total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (completed) *completed = done;
   if (mode != 0) {
     c->ms_backward += total_ms;
     return MCX_OK;
   }
   c->ms_transport += total_ms - flush_ms;
   c->ms_flush += flush_ms;
+  if (cancelled && done < n)  // (a request that came too late to stop any history is dropped)
+    return fail(c, MCX_E_CANCELLED, "cancelled: histories [%llu, %llu) are complete", (unsigned long long)first,
+                (unsigned long long)(first + done));
   return MCX_OK;
 }
 
@@ -731,23 +836,27 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
     if (e == hipSuccess) e = hipMemsetAsync(c->d_hled.p, 0, 3 * n * sizeof(double), s);
     if (e != hipSuccess) return hip_fail(c, e, "clear history results");
   }
-  rc = fp64(c) ? run_impl<double>(c, uint32_t(seed), first, n, s) : run_impl<float>(c, uint32_t(seed), first, n, s);
-  if (rc) return rc;
+  uint64_t completed = 0;
+  rc = fp64(c) ? run_impl<double>(c, uint32_t(seed), first, n, s, 0, 0.0, &completed)
+               : run_impl<float>(c, uint32_t(seed), first, n, s, 0, 0.0, &completed);
+  if (rc && rc != MCX_E_CANCELLED) return rc;
+  // complete, or cancelled with [first, first + completed) done and flushed
   c->table_dirty = false;
-  c->n_done += n;
+  c->n_done += completed;
+  c->next_history = first + completed;
   c->run_seed = uint32_t(seed);
   c->run_first = first;
-  c->run_n = n;
-  c->run_known = c->n_done == n;
+  c->run_n = completed;
+  c->run_known = completed > 0 && c->n_done == completed;
   c->last_n = n;
   c->last_valid = c->test_mode != 0;
-  return MCX_OK;
+  return rc;
 }
 
 int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int on_device, void* stream) {
   if (!c) return MCX_E_INVALID;
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
-  if (!c->run_known)
+  if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
@@ -879,6 +988,7 @@ int mcx_get_stats(mcx_ctx* c, mcx_stats* out) {
   out->ms_estep = c->ms_kernel[3];
   out->timed_iterations = c->timed_iterations;
   out->ms_backward = c->ms_backward;
+  out->next_history = c->next_history;
   if (!c->d_cnt.p) return MCX_OK;
   (void)hipSetDevice(c->device);
   Counters h;
@@ -918,6 +1028,166 @@ int mcx_get_history_results(mcx_ctx* c, uint64_t* hashes, double* ledger) {
   if (e == hipSuccess && ledger) e = hipMemcpy(ledger, c->d_hled.p, 3 * c->last_n * sizeof(double), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(c, e, "read history results");
   return MCX_OK;
+}
+
+int mcx_checkpoint(mcx_ctx* c, void* buf, size_t* size) {
+  if (!c || !size) return MCX_E_INVALID;
+  if (!c->have_phantom) return fail(c, MCX_E_STATE, "no phantom");
+  const size_t need = ckpt_bytes(c);
+  if (!buf) {
+    *size = need;
+    return MCX_OK;
+  }
+  if (*size < need) {
+    *size = need;
+    return fail(c, MCX_E_RANGE, "checkpoint needs %zu bytes", need);
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronize");
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kCkptMagic, sizeof(h.magic));
+  h.version = kCkptVersion;
+  h.precision = c->precision;
+  h.nx = c->nx; h.ny = c->ny; h.nz = c->nz;
+  h.nstat = S_NSTAT;
+  h.run_seed = c->run_seed;
+  h.run_known = c->run_known ? 1u : 0u;
+  for (int k = 0; k < 3; ++k) h.voxel[k] = c->vox[k];
+  h.n_done = c->n_done;
+  h.next_history = c->next_history;
+  h.run_first = c->run_first;
+  h.run_n = c->run_n;
+  h.iterations = c->iterations;
+  h.chunks = c->chunks;
+  h.tally_pairs = c->tally_pairs;
+  h.ms_transport = c->ms_transport;
+  h.ms_flush = c->ms_flush;
+  if (c->d_cnt.p) {
+    Counters k;
+    e = hipMemcpy(&k, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "read statistics");
+    std::memcpy(h.stat, k.stat, sizeof(h.stat));
+    h.e_dep = k.e_dep;
+    h.e_esc = k.e_esc;
+  }
+  char* out = static_cast<char*>(buf);
+  std::memcpy(out, &h, sizeof(h));
+  const size_t vb = nvox(c) * sizeof(double);
+  e = hipMemcpy(out + sizeof(h), c->d_sumq.p, vb, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(out + sizeof(h) + vb, c->d_sumq2.p, vb, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "read tallies");
+  const uint64_t sum = fnv(1469598103934665603ull, out, need - sizeof(uint64_t));
+  std::memcpy(out + need - sizeof(uint64_t), &sum, sizeof(sum));
+  *size = need;
+  return MCX_OK;
+}
+
+int mcx_restore(mcx_ctx* c, const void* buf, size_t size) {
+  if (!c) return MCX_E_INVALID;
+  if (!buf) return fail(c, MCX_E_INVALID, "null checkpoint");
+  if (!c->have_phantom) return fail(c, MCX_E_STATE, "load the phantom first");
+  const size_t need = ckpt_bytes(c);
+  if (size != need) return fail(c, MCX_E_INVALID, "checkpoint of %zu bytes, this phantom needs %zu", size, need);
+  const char* in = static_cast<const char*>(buf);
+  CkptHeader h;
+  std::memcpy(&h, in, sizeof(h));
+  uint64_t sum;
+  std::memcpy(&sum, in + need - sizeof(uint64_t), sizeof(sum));
+  if (std::memcmp(h.magic, kCkptMagic, sizeof(h.magic)) != 0 || h.version != kCkptVersion || h.nstat != S_NSTAT)
+    return fail(c, MCX_E_INVALID, "not a checkpoint of this library version");
+  if (sum != fnv(1469598103934665603ull, in, need - sizeof(uint64_t)))
+    return fail(c, MCX_E_INVALID, "checkpoint checksum mismatch");
+  if (h.precision != c->precision) return fail(c, MCX_E_INVALID, "checkpoint precision differs from the context's");
+  if (h.nx != c->nx || h.ny != c->ny || h.nz != c->nz || h.voxel[0] != c->vox[0] || h.voxel[1] != c->vox[1] ||
+      h.voxel[2] != c->vox[2])
+    return fail(c, MCX_E_INVALID, "checkpoint phantom grid differs from the context's");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  int rc;
+  if (!c->d_cnt.p) {
+    if ((rc = dalloc(c, c->d_cnt, sizeof(Counters), "counters"))) return rc;
+  }
+  Counters k;
+  std::memset(&k, 0, sizeof(k));
+  std::memcpy(k.stat, h.stat, sizeof(k.stat));
+  k.e_dep = h.e_dep;
+  k.e_esc = h.e_esc;
+  const size_t vb = nvox(c) * sizeof(double);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(c->d_cnt.p, &k, sizeof(Counters), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_sumq.p, in + sizeof(h), vb, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_sumq2.p, in + sizeof(h) + vb, vb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "write tallies");
+  c->n_done = h.n_done;
+  c->next_history = h.next_history;
+  c->run_seed = h.run_seed;
+  c->run_first = h.run_first;
+  c->run_n = h.run_n;
+  c->run_known = false;  // the replays need the run's own context
+  c->iterations = h.iterations;
+  c->chunks = h.chunks;
+  c->tally_pairs = h.tally_pairs;
+  c->ms_transport = h.ms_transport;
+  c->ms_flush = h.ms_flush;
+  c->last_valid = false;
+  return MCX_OK;
+}
+
+int mcx_synchronize(mcx_ctx* c) {
+  if (!c) return MCX_E_INVALID;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "synchronize");
+  return MCX_OK;
+}
+
+int mcx_cancel(mcx_ctx* c) {
+  if (!c) return MCX_E_INVALID;
+  c->cancel.store(1);
+  return MCX_OK;
+}
+
+int mcx_workspace_size(mcx_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return MCX_E_INVALID;
+  *bytes = ws_fixed_bytes(c) + size_t(kTableSlots * kSlotBytes);
+  return MCX_OK;
+}
+
+int mcx_set_workspace(mcx_ctx* c, void* dev, size_t bytes) {
+  if (!c) return MCX_E_INVALID;
+  if (dev && (reinterpret_cast<uintptr_t>(dev) & 255u)) return fail(c, MCX_E_INVALID, "workspace must be 256-byte aligned");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  // the memory may have been written by other streams until now
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "synchronize before the workspace change");
+  // the statistics counters live in the workspace: carry them over
+  Counters saved;
+  const bool have_cnt = c->d_cnt.p != nullptr;
+  if (have_cnt && hipMemcpy(&saved, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, MCX_E_DEVICE, "read statistics");
+  for (DevBuf* b : {&c->d_queues, &c->d_cnt, &c->d_hkeys, &c->d_hvals}) dfree(*b);
+  c->queue_cap_built = 0;
+  c->ws = dev;
+  c->ws_bytes = dev ? bytes : 0;
+  c->ws_cap = 0;
+  c->hslots = kTableSlots;
+  int rc = dev ? carve_workspace(c) : MCX_OK;
+  if (rc) {  // too small: back to library-owned memory
+    for (DevBuf* b : {&c->d_queues, &c->d_cnt, &c->d_hkeys, &c->d_hvals}) dfree(*b);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  if (have_cnt) {
+    if (!c->d_cnt.p) {
+      const int r2 = dalloc(c, c->d_cnt, sizeof(Counters), "counters");
+      if (r2) return rc ? rc : r2;
+    }
+    if (hipMemcpy(c->d_cnt.p, &saved, sizeof(Counters), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, MCX_E_DEVICE, "restore statistics");
+  }
+  return rc;
 }
 
 }  // extern "C"
