@@ -182,12 +182,16 @@ int mcx_set_launch(mcx_ctx* ctx, uint32_t bank, uint32_t block, uint32_t steps);
  * (1, default) or launch its kernels one by one (0).  Graphs are used only
  * while per-kernel timing is off. */
 int mcx_set_graph(mcx_ctx* ctx, int on);
-/* Pick bank size, block size and steps per visit by timing a sample of
- * n_sample histories (0: min(total, 2e5)) for each candidate, apply the
- * fastest and reset the tallies.  With cache_path, a previous result for the
- * same device and workload (a hash of architecture, precision, grid, transport
- * parameters and sources) is reused, and a new one is appended as a JSON line.
- * chosen (3 values: bank, block, steps) may be NULL. */
+/* Pick the launch for the sources' histories.  The bank size follows a
+ * rule: the smallest power of two whose population target (a quarter of it)
+ * holds all the histories, up to 2^24, with the queues in at most a quarter
+ * of the device memory.  Block size {128, 256} and steps per visit
+ * {32, 128, 512} are chosen by timing a sample of n_sample histories
+ * (0: min(total, 2e5)) for each pair.  The choice is applied and the tallies
+ * are reset.  With cache_path, a previous result for the same device and
+ * workload (a hash of architecture, precision, grid, transport parameters and
+ * sources) is reused, and a new one is appended as a JSON line.  chosen (3
+ * values: bank, block, steps) may be NULL. */
 int mcx_autotune(mcx_ctx* ctx, uint64_t n_sample, const char* cache_path, uint32_t* chosen);
 /* Enable (1) or disable (0) per-kernel timing with HIP events recorded on
  * the run's stream around each transport kernel (small overhead). */

@@ -348,7 +348,21 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   int grid = int((std::min<uint64_t>(c->cap, 2ull * target) + c->block - 1) / c->block);
   grid = std::min(grid, int(uint64_t(kGridWaves) * 64 / c->block));
   grid = std::max(grid, 1);
-  const uint64_t table_budget = c->hslots / MCX_TALLY_LOAD_DIV;  // bounded load factor: few second probes
+  // The run's tally slots: a power-of-two prefix of the table that holds the
+  // whole run at a quarter of the bounded load factor (the full table until
+  // the pairs per history are known; the margin covers runs whose sources
+  // leave more pairs per history than the estimate).  The flush scans only
+  // these slots, so a small run does not pay for the full table; every slot
+  // a run used is empty again after its flush.
+  uint64_t slots = c->hslots;
+  if (mode == 0 && c->pairs_per_hist > 0.0) {
+    const double need = 4.0 * double(n) * 1.25 * c->pairs_per_hist * MCX_TALLY_LOAD_DIV;
+    uint64_t sl = std::min<uint64_t>(1ull << 16, c->hslots);
+    while (sl < c->hslots && double(sl) < need) sl <<= 1;
+    slots = sl;
+  }
+  a.hmask = slots - 1;
+  const uint64_t table_budget = slots / MCX_TALLY_LOAD_DIV;  // bounded load factor: few second probes
   uint64_t done = 0;
   auto t0 = std::chrono::steady_clock::now();
   double flush_ms = 0.0;
@@ -416,7 +430,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       if (c->h_cnt->overflow & OVF_QUEUE)
         return fail(c, MCX_E_RANGE, "event queue overflow (capacity %u records); raise the bank size", c->cap);
       if (c->h_cnt->overflow & OVF_TALLY)
-        return fail(c, MCX_E_RANGE, "tally table overflow (%llu slots)", (unsigned long long)c->hslots);
+        return fail(c, MCX_E_RANGE, "tally table overflow (%llu slots)", (unsigned long long)slots);
       if (c->h_cnt->overflow & OVF_SOURCE) return fail(c, MCX_E_INVALID, "a source point lies outside the phantom");
       if (c->h_cnt->overflow & OVF_LOST) return fail(c, MCX_E_DEVICE, "a particle lost its direction (no exit face)");
       if (c->h_cnt->done) break;
@@ -440,7 +454,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       continue;
     }
     auto tf = std::chrono::steady_clock::now();
-    e = launch_flush(a.hkeys, a.hvals, c->hslots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+    e = launch_flush(a.hkeys, a.hvals, slots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "tally flush");
@@ -750,6 +764,7 @@ int mcx_autotune(mcx_ctx* c, uint64_t n_sample, const char* cache_path, uint32_t
   for (const SourceDev& sd : c->src) {
     h = fnv(h, &sd.particle, sizeof(sd.particle));
     h = fnv(h, &sd.energy, sizeof(sd.energy));
+    h = fnv(h, &sd.end, sizeof(sd.end));
   }
   char key[32];
   std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)h);
@@ -771,7 +786,23 @@ int mcx_autotune(mcx_ctx* c, uint64_t n_sample, const char* cache_path, uint32_t
       std::fclose(f);
     }
   }
-  const uint32_t banks[] = {1u << 22, 1u << 23, 1u << 24};
+  // Bank size by rule, not by timing: its population target (a quarter of
+  // it) should hold every history of the run at once, up to 2^24, within a
+  // quarter of the device memory.  A sample small enough to time cannot show
+  // the bank's effect (every candidate admits the whole sample at once).
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(c, MCX_E_DEVICE, "device memory size");
+  const uint32_t saved_cap = c->cap;
+  uint32_t bank = 1u << 20;
+  while (bank < (1u << 26) && uint64_t(bank / 4) < std::min<uint64_t>(c->total_hist, 1ull << 24)) bank <<= 1;
+  for (;;) {
+    c->cap = bank;
+    const size_t qb = queue_bytes(c);
+    if (bank <= (1u << 20) || qb <= total_b / 4) break;
+    bank >>= 1;
+  }
+  c->cap = saved_cap;
+  const uint32_t banks[] = {bank};
   const uint32_t blocks[] = {128u, 256u};
   const uint32_t steps[] = {32u, 128u, 512u};
   double best = 0.0;

@@ -253,7 +253,9 @@ def test_autotune_picks_and_caches(tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     sim = mcx.Simulator(1, 0).setup(wl)
     chosen = sim.autotune(20000, cache)
-    assert chosen[0] in (1 << 22, 1 << 23, 1 << 24) and chosen[1] in (128, 256) and chosen[2] in (32, 128, 512)
+    # bank by rule: the smallest power of two from 2^20 whose population
+    # target (a quarter) holds the 20000 histories
+    assert chosen[0] == 1 << 20 and chosen[1] in (128, 256) and chosen[2] in (32, 128, 512)
     lines = open(cache).read().strip().splitlines()
     assert len(lines) == 1 and '"key"' in lines[0]
     again = sim.autotune(20000, cache)
