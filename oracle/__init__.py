@@ -23,6 +23,7 @@ SRC_PENCIL, SRC_RECT = 0, 1
 
 NO_COMPTON, NO_PHOTO, NO_RAYLEIGH, NO_PAIR = 1, 2, 4, 8
 NO_HARD_ELASTIC, NO_HARD_INELASTIC, NO_HARD_BREMS = 16, 32, 64
+STRAGGLING = 128
 
 # orc_eval channels
 MU_COMPTON, MU_PHOTO, MU_RAYLEIGH, MU_PAIR = 0, 1, 2, 3
@@ -115,6 +116,9 @@ def lib():
         L.orc_mu_cut.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_soft_a.restype = C.c_double
         L.orc_soft_a.argtypes = [C.c_double]
+        L.orc_soft_omega2.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.orc_soft_omega2.restype = C.c_double
+        L.orc_sample_straggle.argtypes = [C.c_double, C.c_double, C.c_uint32, C.c_int, dp]
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_splitmix64.argtypes = [C.c_uint64]
@@ -211,6 +215,11 @@ class Tables:
     def mu_cut(self, ptype, e):
         return lib().orc_mu_cut(self.h, ptype, e)
 
+    def soft_omega2(self, ptype: int, e: float) -> float:
+        """Second moment of the soft energy-loss DCS per g/cm^2 (MeV^2 cm^2/g)
+        of an electron (0) or positron (1)."""
+        return lib().orc_soft_omega2(self.h, ptype, e)
+
     def sample(self, which: str, e: float, n: int, seed: int = 7):
         a = np.zeros(n)
         b = np.zeros(n)
@@ -218,6 +227,14 @@ class Tables:
         if rc:
             raise ValueError(which)
         return a, b
+
+
+def sample_straggle(m: float, omega2: float, n: int, seed: int = 7) -> np.ndarray:
+    """n soft energy losses of mean m and variance omega2 from the Class II
+    step's straggling sampler."""
+    out = np.zeros(n)
+    assert lib().orc_sample_straggle(m, omega2, seed, n, _dp(out)) == 0
+    return out
 
 
 def soft_a(mbar: float) -> float:

@@ -17,8 +17,9 @@
  *     b/W with hard emission above Wcr, screened-Rutherford elastic DCS with
  *     Moliere screening, PENELOPE-style hard elastic mean free path
  *     lambda_h = max(lambda_el, min(C1 lambda_1, C2 E / S_s));
- *  R4 Class II step: soft energy loss is deterministic (range inversion, no
- *     straggling), one hinge per step at a uniform fraction of the step, soft
+ *  R4 Class II step: soft energy loss is deterministic (range inversion), or,
+ *     with ORC_STRAGGLING, straggled about that value (R8); one hinge per
+ *     step at a uniform fraction of the step, soft
  *     angular deflection from a one-parameter (mu + A)^-2 law whose mean
  *     matches the soft transport cross section, hard events by the delta
  *     method with a majorant over the step's energy interval (the log-log
@@ -29,6 +30,15 @@
  *     al. SC'11) keyed by (seed, history) with counter (draw pair, uid), so
  *     the numbers a particle draws do not depend on processing order;
  *  R7 Eq. (2) of the paper lacks the square root: sigma = sqrt((Q2 - Q^2)/N).
+ *  R8 straggling of the soft energy loss (optional): mean = the CSDA loss over
+ *     the step's mass path s, variance = s times the second moment of the
+ *     soft part of the energy-loss DCS (Bohr's variance from the leading
+ *     free-electron term of the Moller/Bhabha DCS below the collision
+ *     cutoff, plus b W^2/2 from the b/W bremsstrahlung DCS below the
+ *     radiative cutoff); the distribution is a Gaussian truncated
+ *     symmetrically to (0, 2 x mean) when mean > 3 sd, a uniform of the same
+ *     mean and variance when sqrt(3) sd < mean <= 3 sd, else a point mass at
+ *     0 plus a uniform on (0, w) with the same two moments.
  */
 #include "oracle.h"
 
@@ -510,6 +520,52 @@ double orc_soft_a(double mbar) {
   return exp(0.5 * (lo + hi));
 }
 
+/* Soft energy-loss straggling (R8).  Second moment of the soft DCS per unit
+ * mass path: the leading term 2 pi r_e^2 mc^2 n_e / (beta^2 W^2) of the
+ * binary-collision DCS times W^2, integrated over (0, Wc], gives
+ * 2 pi r_e^2 mc^2 n_e Wc / beta^2 (Bohr); b/W times W^2 over (0, Wr] gives
+ * b Wr^2 / 2.  Wc = min(Wcc, W_max), W_max = E/2 (e-) or E (e+), and W_max
+ * itself when hard inelastic events are off; Wr = min(Wcr, E), or E when
+ * hard bremsstrahlung is off. */
+double orc_soft_omega2(const orc_tables* tb, int type, double e) {
+  const orc_transport* t = &tb->t;
+  double p2 = e * (e + 2.0 * MC2);
+  double et = e + MC2;
+  double beta2 = p2 / (et * et);
+  double wmax = type == 1 ? e : 0.5 * e;
+  double wc = wmax;
+  if (!(t->flags & ORC_NO_HARD_INELASTIC) && t->wcc < wmax) wc = t->wcc;
+  double wr = e;
+  if (!(t->flags & ORC_NO_HARD_BREMS) && t->wcr < e) wr = t->wcr;
+  double k = 2.0 * PI * R_E * R_E * MC2 * tb->mc.ne;
+  return k * wc / beta2 + 0.5 * tb->mc.m.brems_b * wr * wr;
+}
+
+/* one soft energy loss of mean m and variance om2 (R8); no draw when m <= 0 */
+static double straggle(stream* s, double m, double om2) {
+  if (!(m > 0.0)) return m;
+  double m2 = m * m;
+  if (m2 > 9.0 * om2) {
+    /* Gaussian (Box-Muller, the cosine branch), truncated symmetrically
+     * about m to (0, 2m) by rejection: the mean stays m */
+    double om = sqrt(om2);
+    for (;;) {
+      double r = sqrt(-2.0 * log(draw(s)));
+      double w = m + om * r * cos(2.0 * PI * draw(s));
+      if (w > 0.0 && w < 2.0 * m) return w;
+    }
+  }
+  /* uniform on m -/+ sqrt(3) sd: mean m, variance om2 */
+  if (m2 > 3.0 * om2) return m + sqrt(3.0 * om2) * (2.0 * draw(s) - 1.0);
+  /* 0 with probability a, else uniform on (0, w): a and w from the mean m
+   * and the second moment s2 = om2 + m^2 (mean (1-a) w/2, second moment
+   * (1-a) w^2/3) */
+  double s2 = om2 + m2;
+  double a = 1.0 - 4.0 * m2 / (3.0 * s2);
+  double u = draw(s);
+  return u < a ? 0.0 : 1.5 * s2 / m * (u - a) / (1.0 - a);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry: constant LOCATE and STEP on the voxel grid (Sec. 4.2.2)         */
 /* ------------------------------------------------------------------------ */
@@ -979,6 +1035,10 @@ static void electron_track(ctx* c, part* p) {
       /* the face comes before the hinge: soft loss over db, cross, new step */
       double e1 = orc_range_inverse(tb, ti, r0 - rho * db);
       if (!(e1 < e)) e1 = e;
+      if (t->flags & ORC_STRAGGLING) {
+        e1 = e - straggle(&p->rng, e - e1, rho * db * orc_soft_omega2(tb, ti, e));
+        if (!(e1 > 0.0)) e1 = 0.0;
+      }
       deposit(c, p, e - e1);
       c->led[ORC_LED_PATH] += rho * db;
       /* loss over the geometric length db: d(E - E')/d rho = db S_soft(E') */
@@ -992,6 +1052,10 @@ static void electron_track(ctx* c, part* p) {
     move(p, th);
     double e1 = orc_range_inverse(tb, ti, r0 - rho * len);
     if (!(e1 < e)) e1 = e;
+    if (t->flags & ORC_STRAGGLING) {
+      e1 = e - straggle(&p->rng, e - e1, rho * len * orc_soft_omega2(tb, ti, e));
+      if (!(e1 > 0.0)) e1 = 0.0;
+    }
     deposit(c, p, e - e1);
     c->led[ORC_LED_PATH] += rho * len;
     p->e = e1;
@@ -1154,6 +1218,8 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
                      uint64_t n, const double* w, double* a_acc, double* b_acc,
                      double* p_acc, double* sum_q_h) {
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
+  /* the estimator has no term for the score of a straggled soft loss */
+  if (t->flags & ORC_STRAGGLING) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));
@@ -1184,6 +1250,14 @@ void orc_dose(const orc_phantom* ph, uint64_t n_hist, const double* sum_q,
 /* ------------------------------------------------------------------------ */
 /* Sampler access for the distribution tests                                */
 /* ------------------------------------------------------------------------ */
+
+int orc_sample_straggle(double m, double omega2, uint32_t seed, int n, double* out) {
+  for (int i = 0; i < n; ++i) {
+    stream s = {seed, (uint32_t)i, 1ull, 0u};
+    out[i] = straggle(&s, m, omega2);
+  }
+  return 0;
+}
 
 int orc_sample(const orc_tables* tb, int which, double e, uint32_t seed, int n,
                double* out0, double* out1) {

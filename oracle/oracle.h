@@ -41,7 +41,8 @@ enum { ORC_PHOTON = 0, ORC_ELECTRON = 1, ORC_POSITRON = 2 };
 enum { ORC_SRC_PENCIL = 0, ORC_SRC_RECT = 1 };
 
 /* flags: switch model channels off (a switched-off hard channel behaves as if
- * its cutoff were infinite: its stopping contribution becomes soft). */
+ * its cutoff were infinite: its stopping contribution becomes soft), or
+ * switch the straggling of the soft energy loss on (ORC_STRAGGLING). */
 enum {
   ORC_NO_COMPTON = 1u << 0,
   ORC_NO_PHOTO = 1u << 1,
@@ -49,7 +50,8 @@ enum {
   ORC_NO_PAIR = 1u << 3,
   ORC_NO_HARD_ELASTIC = 1u << 4,
   ORC_NO_HARD_INELASTIC = 1u << 5,
-  ORC_NO_HARD_BREMS = 1u << 6
+  ORC_NO_HARD_BREMS = 1u << 6,
+  ORC_STRAGGLING = 1u << 7
 };
 
 typedef struct {
@@ -125,6 +127,13 @@ double orc_screening(const orc_tables* tb, double e);
 double orc_elastic_k(const orc_tables* tb, double e);
 double orc_mu_cut(const orc_tables* tb, int type, double e);
 double orc_soft_a(double mean_mu);
+/* Second moment of the soft energy-loss DCS per unit mass path, MeV^2 cm^2/g,
+ * of an electron (type 0) or positron (1) of kinetic energy e: the variance
+ * of the soft loss over a path of s g/cm^2 is s times this. */
+double orc_soft_omega2(const orc_tables* tb, int type, double e);
+/* n soft energy losses of mean m and variance omega2 drawn by the straggling
+ * sampler of the Class II step, draw streams (seed, i, uid 1) for i < n. */
+int orc_sample_straggle(double m, double omega2, uint32_t seed, int n, double* out);
 
 /* Raw generators (pinned against published known-answer values). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
