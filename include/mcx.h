@@ -66,6 +66,18 @@ extern "C" {
 #define MCX_NO_HARD_ELASTIC (1u << 4)
 #define MCX_NO_HARD_INELASTIC (1u << 5)
 #define MCX_NO_HARD_BREMS (1u << 6)
+/* Straggling of the soft energy loss of a Class II step: the loss over a
+ * path of s g/cm^2 keeps the CSDA value as its mean and gets the variance
+ * s * Omega^2(E), the second moment of the soft part of the energy-loss DCS
+ * per unit mass path (Bohr's variance from the leading free-electron term of
+ * the Moller/Bhabha DCS below Wcc, plus b Wcr^2 / 2 from the b/W
+ * bremsstrahlung DCS below Wcr): a Gaussian truncated to (0, 2 x mean) when
+ * the mean exceeds 3 standard deviations, a uniform law of the same mean and
+ * variance down to sqrt(3) standard deviations, below that a point mass at
+ * zero plus a uniform law with the same two moments.  Off by default (the
+ * soft loss is then the deterministic CSDA value); not supported by
+ * mcx_dose_backward. */
+#define MCX_STRAGGLING (1u << 7)
 
 typedef struct mcx_ctx mcx_ctx;
 

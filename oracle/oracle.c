@@ -541,9 +541,13 @@ double orc_soft_omega2(const orc_tables* tb, int type, double e) {
   return k * wc / beta2 + 0.5 * tb->mc.m.brems_b * wr * wr;
 }
 
-/* one soft energy loss of mean m and variance om2 (R8); no draw when m <= 0 */
+/* one soft energy loss of mean m and variance om2 (R8).  Whether and how
+ * many numbers are drawn must not hinge on m alone: a zero path can give a
+ * CSDA loss of 0 or of a rounding residue, depending on how the range is
+ * inverted.  So a zero variance (zero path) draws nothing, and m = 0 with a
+ * positive variance falls in the two-mode branch, which returns 0. */
 static double straggle(stream* s, double m, double om2) {
-  if (!(m > 0.0)) return m;
+  if (!(om2 > 0.0)) return m;
   double m2 = m * m;
   if (m2 > 9.0 * om2) {
     /* Gaussian (Box-Muller, the cosine branch), truncated symmetrically

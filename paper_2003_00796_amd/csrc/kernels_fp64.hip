@@ -13,11 +13,12 @@ static hipError_t launch_flavor(const KArgs<double>& a, int par, uint32_t target
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(double);
   const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(double);
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL((k_source<double, F>), dim3(grid), dim3(block), 0, s, a, par);
+  constexpr int B = base_flavor(F);  // straggling changes the e+- step only
+  hipLaunchKernelGGL((k_source<double, B>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL((k_flight<double, F>), dim3(grid), dim3(block), sm_f, s, a, par);
+  hipLaunchKernelGGL((k_flight<double, B>), dim3(grid), dim3(block), sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL((k_knock<double, F>), dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_knock<double, B>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[3], s);
   hipLaunchKernelGGL((k_estep<double, F>), dim3(grid), dim3(block), sm_e, s, a, par);
   if (ev) (void)hipEventRecord(ev[4], s);
@@ -30,6 +31,9 @@ hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, in
   // replays never write the test outputs
   if (a.mode == 1) return launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev);
   if (a.mode == 2) return launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev);
+  if (a.straggle)
+    return a.test_mode ? launch_flavor<FL_STRAG_TEST>(a, par, target, grid, block, s, ev)
+                       : launch_flavor<FL_STRAG>(a, par, target, grid, block, s, ev);
   if (a.test_mode) return launch_flavor<FL_TEST>(a, par, target, grid, block, s, ev);
   return launch_flavor<FL_FWD>(a, par, target, grid, block, s, ev);
 }
@@ -66,7 +70,9 @@ hipError_t configure_fp64(int n_grid) {
   const void* k[kFlavors] = {reinterpret_cast<const void*>(&k_estep<double, FL_FWD>),
                              reinterpret_cast<const void*>(&k_estep<double, FL_TEST>),
                              reinterpret_cast<const void*>(&k_estep<double, FL_ADJ_A>),
-                             reinterpret_cast<const void*>(&k_estep<double, FL_ADJ_B>)};
+                             reinterpret_cast<const void*>(&k_estep<double, FL_ADJ_B>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_STRAG>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_STRAG_TEST>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

@@ -149,6 +149,13 @@ struct Tab {
   T k_coef;          // n_mol pi r_e^2 sum Z(Z+1): K(E) = k_coef (mc^2 / pv)^2
   T eta_a, eta_b;    // eta(E) = eta_a (mc^2)^2 / p^2c^2 * (1.13 + eta_b / beta^2)
   T ray_a;
+  // soft energy-loss straggling: second moment of the soft DCS per unit mass
+  // path, strag_k Wc / beta^2 + strag_b Wr^2 / 2, with Wc = min(wcc_soft,
+  // W_max) and Wr = min(wcr_soft, E) (the cutoffs are infinite for a
+  // switched-off hard channel)
+  T strag_k;         // 2 pi r_e^2 mc^2 n_e, MeV cm^2/g
+  T strag_b;         // bremsstrahlung DCS constant b, cm^2/g
+  T wcc_soft, wcr_soft;
 };
 
 template <typename T>
@@ -183,6 +190,7 @@ struct KArgs {
   // each history's weighted score Q_h and the local soft-loss derivative;
   // 2: replay B scatters (Q_h - Qbar) times the photon free-flight scores)
   int mode;
+  int straggle;          // soft energy-loss straggling on (selects the kernel flavour)
   const double* adj_w;   // per voxel: dL/dD_v * 1e6 / (rho_v V)
   double* adj_q;         // per history of the run: Q_h
   double* adj_grad;      // per voxel accumulator

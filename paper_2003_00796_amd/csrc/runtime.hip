@@ -277,6 +277,10 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.tb.eta_a = T(b.eta_a);
   a.tb.eta_b = T(b.eta_b);
   a.tb.ray_a = T(b.ray_a);
+  a.tb.strag_k = T(b.strag_k);
+  a.tb.strag_b = T(b.strag_b);
+  a.tb.wcc_soft = T(b.wcc_soft);
+  a.tb.wcr_soft = T(b.wcr_soft);
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
   a.dx = c->vox[0]; a.dy = c->vox[1]; a.dz = c->vox[2];
   a.ox = c->org[0]; a.oy = c->org[1]; a.oz = c->org[2];
@@ -303,6 +307,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.cap = c->cap;
   a.steps = c->steps;
   a.mode = mode;
+  a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
   if (mode) {
     a.test_mode = 0;
     a.adj_w = static_cast<const double*>(c->d_adj_w.p);
@@ -889,6 +894,8 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
+  if (c->tr.flags & MCX_STRAGGLING)
+    return fail(c, MCX_E_UNSUPPORTED, "the gradient estimator has no term for straggled soft losses");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

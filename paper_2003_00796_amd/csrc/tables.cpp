@@ -156,6 +156,10 @@ class Model {
     return 3.76 * az * az;
   }
   double k_coef() const { return nmol_ * kPi * kRe * kRe * m_.zz1_mol; }
+  // leading term of the binary-collision DCS, 2 pi r_e^2 mc^2 n_e / (beta^2
+  // W^2): times W^2 and integrated over (0, Wc] it gives strag_k Wc / beta^2
+  // (Bohr's variance of the soft collision loss per unit mass path)
+  double strag_k() const { return 2.0 * kPi * kRe * kRe * kMc2 * ne_; }
 
  private:
   mcx_material_desc m_;
@@ -275,6 +279,11 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
   b.eta_a = md.eta_a();
   b.eta_b = md.eta_b();
   b.ray_a = m.ray_a;
+  b.strag_k = md.strag_k();
+  b.strag_b = m.brems_b;
+  const double inf = std::numeric_limits<double>::infinity();
+  b.wcc_soft = (t.flags & MCX_NO_HARD_INELASTIC) ? inf : t.wcc;
+  b.wcr_soft = (t.flags & MCX_NO_HARD_BREMS) ? inf : t.wcr;
   return true;
 }
 

@@ -42,6 +42,7 @@ struct M<double> {
   static __device__ __forceinline__ double expm1(double x) { return ::expm1(x); }
   static __device__ __forceinline__ double floor(double x) { return ::floor(x); }
   static __device__ __forceinline__ void sincos(double x, double* s, double* c) { ::sincos(x, s, c); }
+  static __device__ __forceinline__ double cos(double x) { return ::cos(x); }
   static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
 };
 
@@ -64,6 +65,7 @@ struct M<float> {
   }
   static __device__ __forceinline__ float floor(float x) { return ::floorf(x); }
   static __device__ __forceinline__ void sincos(float x, float* s, float* c) { __sincosf(x, s, c); }
+  static __device__ __forceinline__ float cos(float x) { return __cosf(x); }
   static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
 };
 

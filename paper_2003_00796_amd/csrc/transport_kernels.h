@@ -36,17 +36,25 @@ __device__ __forceinline__ int q_eout(int par) { return Q_E0 + 1 - par; }
 // argument block (the host launches the flavour that matches them), so the
 // forward kernels carry no test-output or replay code (nor its registers).
 enum Flavor : int {
-  FL_FWD = 0,    // forward transport
-  FL_TEST = 1,   // forward transport with the per-history test outputs
-  FL_ADJ_A = 2,  // first density-gradient replay (per-history weighted score)
-  FL_ADJ_B = 3   // second replay (likelihood-ratio scores of photon flights)
+  FL_FWD = 0,         // forward transport
+  FL_TEST = 1,        // forward transport with the per-history test outputs
+  FL_ADJ_A = 2,       // first density-gradient replay (per-history weighted score)
+  FL_ADJ_B = 3,       // second replay (likelihood-ratio scores of photon flights)
+  FL_STRAG = 4,       // forward transport, soft energy-loss straggling
+  FL_STRAG_TEST = 5   // the same with the per-history test outputs
 };
-constexpr int kFlavors = 4;
+constexpr int kFlavors = 6;
+
+// straggling changes the e+- step only: the other kernels of a straggling
+// flavour are those of the flavour without it
+constexpr int base_flavor(int f) { return f == FL_STRAG ? FL_FWD : (f == FL_STRAG_TEST ? FL_TEST : f); }
+constexpr bool straggles(int f) { return f == FL_STRAG || f == FL_STRAG_TEST; }
 
 template <int F, typename T>
 __device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
-  __builtin_assume(a.test_mode == (F == FL_TEST ? 1 : 0));
-  __builtin_assume(a.mode == (F == FL_ADJ_A ? 1 : (F == FL_ADJ_B ? 2 : 0)));
+  constexpr int B = base_flavor(F);
+  __builtin_assume(a.test_mode == (B == FL_TEST ? 1 : 0));
+  __builtin_assume(a.mode == (B == FL_ADJ_A ? 1 : (B == FL_ADJ_B ? 2 : 0)));
 }
 
 // striped queues: this block's stripe, the records of a stripe, the prefix
@@ -653,8 +661,45 @@ __device__ __forceinline__ T binary_cos(T e, T w, bool primary) {
   return M<T>::sqrt(c2);
 }
 
-// one Class II step; returns false when the particle is gone
+// Straggling of the soft energy loss over a step: a loss of mean m (the CSDA
+// loss over the step's mass path) and variance om2 = mass path x the soft
+// second moment at the step's initial energy.  Gaussian (Box-Muller, cosine
+// branch) truncated symmetrically to (0, 2m) when m > 3 sd; uniform on
+// m -/+ sqrt(3) sd when sqrt(3) sd < m <= 3 sd; else 0 with probability
+// a = 1 - 4 m^2 / (3 s2) and uniform on (0, 3 s2 / (2m)) otherwise, with
+// s2 = om2 + m^2 (the same mean and second moment).  The draws depend on
+// the mass path, not on m: a zero path (a particle on a face) draws nothing,
+// although its CSDA loss may be a rounding residue rather than 0; m = 0 on a
+// positive path takes the two-mode branch, which returns 0.
 template <typename T>
+__device__ __forceinline__ T soft_straggle(const Tab<T>& tb, int lep, T e, T m, double mass_path, Rng<T>& rng) {
+  if (!(mass_path > 0.0)) return m;
+  const T p2 = e * (e + T(2.0 * kMc2));
+  const T et = e + T(kMc2);
+  const T beta2 = p2 / (et * et);
+  const T wmax = lep ? e : T(0.5) * e;
+  const T wc = tb.wcc_soft < wmax ? tb.wcc_soft : wmax;
+  const T wr = tb.wcr_soft < e ? tb.wcr_soft : e;
+  const T om2 = T(mass_path) * (tb.strag_k * wc / beta2 + T(0.5) * tb.strag_b * wr * wr);
+  const T m2 = m * m;
+  if (m2 > T(9) * om2) {
+    const T om = M<T>::sqrt(om2);
+    for (int tries = 0; tries < kMaxTries; ++tries) {
+      const T r = M<T>::sqrt(T(-2) * M<T>::log(uni<T>(rng)));
+      const T w = m + om * r * M<T>::cos(T(2.0 * kPi) * uni<T>(rng));
+      if (w > T(0) && w < T(2) * m) return w;
+    }
+    return m;
+  }
+  if (m2 > T(3) * om2) return m + M<T>::sqrt(T(3) * om2) * (T(2) * uni<T>(rng) - T(1));
+  const T s2 = om2 + m2;
+  const T aa = T(1) - T(4) * m2 / (T(3) * s2);
+  const T u = uni<T>(rng);
+  return u < aa ? T(0) : T(1.5) * s2 / m * (u - aa) / (T(1) - aa);
+}
+
+// one Class II step; returns false when the particle is gone
+template <typename T, bool STRAG>
 __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1, Child<T>& c2, DepAcc& acc,
                        LaneStats& ls, BlockStats* bs) {
   const Tab<T>& tb = a.tb;
@@ -696,8 +741,15 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   // before the hinge (then the step ends at the face), else the whole step
   // charged at the hinge; one range inversion serves both cases
   const bool face_first = db <= th;
-  T e1 = range_inv(tab, nt, base, T(r0 - T(double(rho) * (face_first ? db : len))), g.i);
+  const double mass_path = double(rho) * (face_first ? db : len);
+  T e1 = range_inv(tab, nt, base, T(r0 - T(mass_path)), g.i);
   if (!(e1 < e)) e1 = e;
+  if constexpr (STRAG) {
+    // the loss keeps its CSDA mean and fluctuates about it (drawn after the
+    // hinge position, before the soft deflection)
+    e1 = e - soft_straggle(tb, lep, e, e - e1, mass_path, p.rng);
+    if (!(e1 > T(0))) e1 = T(0);
+  }
   deposit(a, acc, ls, p, e - e1);
   p.e = e1;
   if (face_first) {
@@ -900,7 +952,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     c1.on = false;
     c2.on = false;
     if (alive) {
-      alive = e_step(a, tab, p, c1, c2, acc, ls, &bs);
+      alive = e_step<T, straggles(F)>(a, tab, p, c1, c2, acc, ls, &bs);
       ++used;
     }
     dep_flush_pending(a, acc, ls);

@@ -113,8 +113,10 @@ def test_straggling_two_mode_regime():
     assert stats.kstest(x[~zero], stats.uniform(0.0, w).cdf).pvalue > 1e-3
     assert abs(x.mean() - m) < 5 * x.std() / math.sqrt(n)
     assert abs((x ** 2).mean() - s2) < 5 * (x ** 2).std() / math.sqrt(n)
-    # no loss, no draw
+    # no mean loss on a positive path: the two-mode branch gives 0
     assert not O.sample_straggle(0.0, 1.0, 10).any()
+    # zero variance (a zero path): the loss is the CSDA value, nothing drawn
+    assert np.all(O.sample_straggle(0.3, 0.0, 10) == 0.3)
 
 
 @pytest.mark.parametrize("straggle", [False, True])
