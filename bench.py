@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6_000, help="oracle histories per host process")
     ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes (host cores used)")
     ap.add_argument("--electron", action="store_true", help="also time the 20 MeV electron workload")
+    ap.add_argument("--straggling", action="store_true",
+                    help="also time the mixed step with soft energy-loss straggling on")
     ap.add_argument("--no-fp64", action="store_true")
     # records per event queue: 2^26 puts a quarter of it, 16.8 M particles,
     # in flight at once (all histories of a 1e7 step are admitted together)
@@ -317,11 +319,28 @@ def main():
         "fp64": result_64,
         "mixed_over_fp64": (value / result_64["value"]) if result_64 else None,
         "high_dose_deviation": dev if result_64 else None,
-        "kernel_ms_per_step": {k: v / len(t_mix) for k, v in ms.items()},
-        "events_per_history": {k: st[k] / (n * len(t_mix)) for k in ("flights", "esteps", "crossings", "deposits",
-                                                                     "inserts", "evisits")},
+        # the statistics are those of the last timed step (each step starts
+        # from a reset of the tallies and statistics)
+        "kernel_ms_per_step": ms,
+        "events_per_history": {k: st[k] / n for k in ("flights", "esteps", "crossings", "deposits", "inserts",
+                                                      "evisits")},
         "roofline": roofline(st),
     }
+    if args.straggling:
+        t = dict(wl["transport"], flags=wl["transport"].get("flags", 0) | mcx.STRAGGLING)
+        sg = mcx.Simulator(mcx.MIXED, 0).setup(dict(wl, transport=t))
+        sg.set_launch(args.bank, 256, 128)
+        run_steps(sg, n, warm_seeds, sync)
+        t_sg = run_steps(sg, n, seeds, sync)
+        d_sg, s_sg = sg.dose()
+        st_sg = sg.stats()  # the last step's (each step starts from a reset)
+        sg.close()
+        hi = d_mix >= 0.5 * d_mix.max()
+        z = (d_sg[hi] - d_mix[hi]) / np.sqrt(s_sg[hi] ** 2 + s_mix[hi] ** 2)
+        out["straggling"] = dict(value=n * len(t_sg) / sum(t_sg), ms_per_step=1e3 * sum(t_sg) / len(t_sg),
+                                 esteps_per_history=st_sg["esteps"] / n,
+                                 dose_vs_csda=dict(high_dose_deviation(d_sg, d_mix), z_rms=float(np.sqrt(np.mean(z ** 2))),
+                                                   z_mean=float(np.mean(z))))
     if not args.no_gradient:
         out["gradient"] = gradient_timing(mcx, W, sync)
     if args.beamlets:
