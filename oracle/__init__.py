@@ -72,7 +72,7 @@ _STAT_FIELDS = ("histories", "flights", "compton", "photo", "rayleigh", "pair",
 
 class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in _STAT_FIELDS] + [
-        ("e_dep", C.c_double), ("e_esc", C.c_double), ("pos_esc", C.c_uint64)]
+        ("e_dep", C.c_double), ("e_esc", C.c_double), ("pos_esc", C.c_uint64), ("maj_excess", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

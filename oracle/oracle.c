@@ -1026,6 +1026,17 @@ static void electron_track(ctx* c, part* p) {
     double r0 = range_of(tb, ti, e);
     double elo = r0 - tau_max > 0.0 ? orc_range_inverse(tb, ti, r0 - tau_max) : tb->e[0];
     if (elo > e) elo = e;
+    if (t->flags & ORC_STRAGGLING) {
+      /* R14: a straggled loss can exceed the step's CSDA loss: by at most
+       * twice the CSDA mean under the Gaussian and uniform laws, and by at
+       * most 6 Omega^2(E)/S under the two-mode law (8 here, for the
+       * stopping power's change over the step); the hard-event majorant
+       * covers every energy the step can end at */
+      double dmax = 2.0 * (e - elo);
+      double dw = 8.0 * orc_soft_omega2(tb, ti, e) / ss;
+      if (dw > dmax) dmax = dw;
+      elo = e - dmax > tb->e[0] ? e - dmax : tb->e[0];
+    }
     double smaj = orc_sigma_majorant(tb, ti, elo, e);
     double u1 = draw(&p->rng);
     double tau_h = smaj > 0.0 ? -log(u1) / smaj : INF_D;
@@ -1088,6 +1099,7 @@ static void electron_track(ctx* c, part* p) {
     double s_el = interp(tb, tb->el[ti][CH_EL], 0.0, e1);
     double s_in = interp(tb, tb->el[ti][CH_IN], tb->thr_el[ti][CH_IN], e1);
     double s_br = interp(tb, tb->el[ti][CH_BR], tb->thr_el[ti][CH_BR], e1);
+    if (s_el + s_in + s_br > smaj) c->st->maj_excess++;
     if (u < s_el) e_hard(c, p, 0);
     else if (u < s_el + s_in) e_hard(c, p, 1);
     else if (u < s_el + s_in + s_br) e_hard(c, p, 2);

@@ -103,6 +103,7 @@ typedef struct {
   uint64_t absorbed, escaped;
   double e_dep, e_esc;
   uint64_t pos_esc;
+  uint64_t maj_excess;  /* hard selections whose cross sections exceeded the majorant (must stay 0) */
 } orc_stats;
 
 /* ledger entries written per history when ledger != NULL */

@@ -672,15 +672,20 @@ __device__ __forceinline__ T binary_cos(T e, T w, bool primary) {
 // although its CSDA loss may be a rounding residue rather than 0; m = 0 on a
 // positive path takes the two-mode branch, which returns 0.
 template <typename T>
-__device__ __forceinline__ T soft_straggle(const Tab<T>& tb, int lep, T e, T m, double mass_path, Rng<T>& rng) {
-  if (!(mass_path > 0.0)) return m;
+__device__ __forceinline__ T soft_omega2(const Tab<T>& tb, int lep, T e) {
   const T p2 = e * (e + T(2.0 * kMc2));
   const T et = e + T(kMc2);
   const T beta2 = p2 / (et * et);
   const T wmax = lep ? e : T(0.5) * e;
   const T wc = tb.wcc_soft < wmax ? tb.wcc_soft : wmax;
   const T wr = tb.wcr_soft < e ? tb.wcr_soft : e;
-  const T om2 = T(mass_path) * (tb.strag_k * wc / beta2 + T(0.5) * tb.strag_b * wr * wr);
+  return tb.strag_k * wc / beta2 + T(0.5) * tb.strag_b * wr * wr;
+}
+
+template <typename T>
+__device__ __forceinline__ T soft_straggle(const Tab<T>& tb, int lep, T e, T m, double mass_path, Rng<T>& rng) {
+  if (!(mass_path > 0.0)) return m;
+  const T om2 = T(mass_path) * soft_omega2(tb, lep, e);
   const T m2 = m * m;
   if (m2 > T(9) * om2) {
     const T om = M<T>::sqrt(om2);
@@ -724,6 +729,16 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const T r0 = range_at(tab, nt, base, g, e, le, tb.lemin, tb.dl);
   T elo = r0 - tau_max > T(0) ? range_inv(tab, nt, base, r0 - tau_max, g.i) : tb.emin;
   if (elo > e) elo = e;
+  if constexpr (STRAG) {
+    // a straggled loss can exceed the step's CSDA loss: by at most twice the
+    // CSDA mean (Gaussian and uniform laws) and by at most 6 Omega^2(E)/S
+    // (two-mode law; 8 here, for the stopping power's change over the step):
+    // the hard-event majorant covers every energy the step can end at
+    const T d2 = T(2) * (e - elo);
+    const T dw = T(8) * soft_omega2(tb, lep, e) / ss;
+    const T dmax = dw > d2 ? dw : d2;
+    elo = e - dmax > tb.emin ? e - dmax : tb.emin;
+  }
   const T smaj = majorant(tb, tab, base, lep, elo, g, e);
   const T u1 = uni<T>(p.rng);
   const T tau_h = smaj > T(0) ? -M<T>::log(u1) / smaj : M<T>::inf();

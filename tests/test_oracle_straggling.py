@@ -189,3 +189,24 @@ def test_gradient_refuses_straggling():
     ph = W.water_cube(8, 8.0)
     with pytest.raises(Exception):
         O.gradient(tb, ph, [W.pencil(0, 1.0, (4, 4, 0), 10)], 1, 0, 10, np.ones((8, 8, 8)))
+
+
+@pytest.mark.parametrize("straggle", [False, True])
+def test_hard_event_majorant_covers_every_step_end(straggle):
+    """The delta method needs the majorant to bound the hard cross sections at
+    the energy a step ends at.  A straggled loss can exceed the step's CSDA
+    loss, so with straggling the majorant interval is widened (R14): no hard
+    selection of a 20 MeV electron or 1 MeV photon run may see cross sections
+    above the majorant (without the widening about 3% of the 20 MeV
+    electron's selections did)."""
+    for wl, n in ((dict(W.workload("electron_200"), phantom=W.water_cube(50, 10.0),
+                        sources=[W.pencil(1, 20.0, (5.0, 5.0, 0.0), 200)]), 200),
+                  (dict(W.workload("water_pencil_32"), sources=[W.pencil(0, 1.0, (10.0, 10.0, 0.0), 3000)]), 3000),
+                  (dict(W.workload("water_pencil_32"), phantom=W.water_cube(20, 4.0),
+                        sources=[W.pencil(2, 5.0, (2.0, 2.0, 0.0), 300)]), 300)):
+        t = dict(wl["transport"], flags=O.STRAGGLING if straggle else 0)
+        tb = O.Tables(wl["material"], t)
+        r = O.run(tb, wl["phantom"], wl["sources"], 1, 0, n)
+        st = r.stats.as_dict()
+        assert st["hard_el"] + st["hard_in"] + st["delta"] > 0
+        assert st["maj_excess"] == 0
