@@ -24,6 +24,7 @@ SRC_PENCIL, SRC_RECT = 0, 1
 NO_COMPTON, NO_PHOTO, NO_RAYLEIGH, NO_PAIR = 1, 2, 4, 8
 NO_HARD_ELASTIC, NO_HARD_INELASTIC, NO_HARD_BREMS = 16, 32, 64
 STRAGGLING = 128
+ANNIH_FLIGHT = 256
 
 # orc_eval channels
 MU_COMPTON, MU_PHOTO, MU_RAYLEIGH, MU_PAIR = 0, 1, 2, 3
@@ -36,7 +37,7 @@ def ech(ptype: int, c: int) -> int:
 
 
 SMP = dict(compton=0, rayleigh=1, moller=2, bhabha=3, brems=4, hard_elastic=5,
-           soft=6, pair=7, free_path=8, annih=9)
+           soft=6, pair=7, free_path=8, annih=9, annih_flight=10)
 LED_DEP, LED_ESC, LED_POSESC, LED_PATH, LED_EABS, LED_N = range(6)
 
 
@@ -119,6 +120,8 @@ def lib():
         L.orc_soft_omega2.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_soft_omega2.restype = C.c_double
         L.orc_sample_straggle.argtypes = [C.c_double, C.c_double, C.c_uint32, C.c_int, dp]
+        L.orc_sigma_annih.argtypes = [C.c_void_p, C.c_double]
+        L.orc_sigma_annih.restype = C.c_double
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_splitmix64.argtypes = [C.c_uint64]
@@ -219,6 +222,11 @@ class Tables:
         """Second moment of the soft energy-loss DCS per g/cm^2 (MeV^2 cm^2/g)
         of an electron (0) or positron (1)."""
         return lib().orc_soft_omega2(self.h, ptype, e)
+
+    def sigma_annih(self, e: float) -> float:
+        """Heitler two-photon annihilation cross section per gram (cm^2/g) of a
+        positron of kinetic energy e."""
+        return lib().orc_sigma_annih(self.h, e)
 
     def sample(self, which: str, e: float, n: int, seed: int = 7):
         a = np.zeros(n)

@@ -30,6 +30,10 @@
  *     al. SC'11) keyed by (seed, history) with counter (draw pair, uid), so
  *     the numbers a particle draws do not depend on processing order;
  *  R7 Eq. (2) of the paper lacks the square root: sigma = sqrt((Q2 - Q^2)/N).
+ *  R9 two-photon annihilation of positrons in flight (optional): a fourth
+ *     hard channel with Heitler's cross section for electrons at rest; the
+ *     softer photon's energy fraction drawn from Heitler's DCS, the photon
+ *     directions from energy and momentum conservation.
  *  R8 straggling of the soft energy loss (optional): mean = the CSDA loss over
  *     the step's mass path s, variance = s times the second moment of the
  *     soft part of the energy-loss DCS (Bohr's variance from the leading
@@ -701,7 +705,7 @@ static void score(ctx* c, int64_t v, double s) {
 enum {
   EV_COMPTON = 1, EV_PHOTO = 2, EV_RAYLEIGH = 3, EV_PAIR = 4, EV_PH_ESCAPE = 5,
   EV_CROSS = 6, EV_STEP = 7, EV_HARD_EL = 8, EV_HARD_IN = 9, EV_HARD_BR = 10,
-  EV_ABSORB = 11, EV_E_ESCAPE = 12
+  EV_ABSORB = 11, EV_E_ESCAPE = 12, EV_ANNIH_FLIGHT = 13
 };
 
 static void event(const ctx* c, part* p, int code, int64_t v) {
@@ -967,6 +971,46 @@ static double binary_cos(double e, double w, int primary) {
   return sqrt(c2);
 }
 
+/* R9: Heitler's two-photon annihilation of a positron (kinetic energy e,
+ * g = 1 + e/mc^2, p = sqrt(g^2 - 1)) with a free electron at rest.  The
+ * softer photon takes the fraction z of the total energy e + 2mc^2, with
+ * z in [zmin, 1/2], zmin = 1/(g + 1 + p), and DCS per electron
+ *   K [S(z) + S(1-z)],  S(x) = -(g+1)^2 + (g^2 + 4g + 1)/x - 1/x^2,
+ *   K = pi r_e^2 / ((g+1)(g^2-1));
+ * its integral is the total cross section
+ *   K [(g^2 + 4g + 1) ln(g + p) - (g + 3) p]. */
+double orc_sigma_annih(const orc_tables* tb, double e) {
+  double g = 1.0 + e / MC2;
+  double p = sqrt(g * g - 1.0);
+  double k = PI * R_E * R_E * tb->mc.ne;
+  return k * ((g * g + 4.0 * g + 1.0) * log(g + p) - (g + 3.0) * p) / ((g + 1.0) * (g * g - 1.0));
+}
+
+/* z from the DCS: proposal 1/z on [zmin, 1/2] (log-uniform), accepted with
+ * probability z [S(z) + S(1-z)] / (2 (g^2 + 4g + 1)); z [S(z) + S(1-z)] is
+ * at most (g^2 + 4g + 1)(1 + z/(1-z)) <= 2 (g^2 + 4g + 1) for z <= 1/2 */
+static double sample_annih(stream* s, double e) {
+  double g = 1.0 + e / MC2;
+  double p = sqrt(g * g - 1.0);
+  double zmin = 1.0 / (g + 1.0 + p);
+  double c = g * g + 4.0 * g + 1.0;
+  double g1 = (g + 1.0) * (g + 1.0);
+  for (;;) {
+    double z = zmin * pow(0.5 / zmin, draw(s));
+    double y = 1.0 - z;
+    double f = -g1 + c / z - 1.0 / (z * z) - g1 + c / y - 1.0 / (y * y);
+    if (draw(s) * 2.0 * c <= z * f) return z;
+  }
+}
+
+/* polar cosine of the photon taking the fraction z (energy-momentum
+ * conservation): cos = (g + 1 - 1/z) / p */
+static double annih_cos(double e, double z) {
+  double g = 1.0 + e / MC2;
+  double c = (g + 1.0 - 1.0 / z) / sqrt(g * g - 1.0);
+  return c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+}
+
 static void e_hard(ctx* c, part* p, int which) {
   const orc_tables* tb = c->tb;
   int ti = p->type == ORC_POSITRON ? 1 : 0;
@@ -994,6 +1038,22 @@ static void e_hard(ctx* c, part* p, int which) {
     p->e = e - w;
     secondary(c, p, ORC_ELECTRON, w, ds);
     event(c, p, EV_HARD_IN, v);
+  } else if (which == 3) {
+    /* R9: the positron annihilates with an electron at rest */
+    c->st->annih++;
+    double e = p->e;
+    double z = sample_annih(&p->rng, e);
+    double phi = 2.0 * PI * draw(&p->rng);
+    double etot = e + 2.0 * MC2;
+    double ka = z * etot, kb = etot - ka;
+    double da[3] = {p->d[0], p->d[1], p->d[2]}, dbv[3] = {p->d[0], p->d[1], p->d[2]};
+    rotate(da, annih_cos(e, z), phi);
+    rotate(dbv, annih_cos(e, 1.0 - z), phi + PI);
+    secondary(c, p, ORC_PHOTON, ka, da);
+    secondary(c, p, ORC_PHOTON, kb, dbv);
+    p->e = 0.0;
+    event(c, p, EV_ANNIH_FLIGHT, v);
+    finish(c, p);
   } else {
     c->st->hard_br++;
     double wcr = c->t->wcr, e = p->e;
@@ -1038,6 +1098,10 @@ static void electron_track(ctx* c, part* p) {
       elo = e - dmax > tb->e[0] ? e - dmax : tb->e[0];
     }
     double smaj = orc_sigma_majorant(tb, ti, elo, e);
+    /* R9: Heitler's cross section falls with energy: its value at the low
+     * end of the step's energy interval bounds it over the step */
+    int annih = ti == 1 && (t->flags & ORC_ANNIH_FLIGHT);
+    if (annih) smaj += orc_sigma_annih(tb, elo);
     double u1 = draw(&p->rng);
     double tau_h = smaj > 0.0 ? -log(u1) / smaj : INF_D;
     int capped = !(tau_h <= tau_max);
@@ -1099,11 +1163,15 @@ static void electron_track(ctx* c, part* p) {
     double s_el = interp(tb, tb->el[ti][CH_EL], 0.0, e1);
     double s_in = interp(tb, tb->el[ti][CH_IN], tb->thr_el[ti][CH_IN], e1);
     double s_br = interp(tb, tb->el[ti][CH_BR], tb->thr_el[ti][CH_BR], e1);
-    if (s_el + s_in + s_br > smaj) c->st->maj_excess++;
+    double s_an = annih ? orc_sigma_annih(tb, e1) : 0.0;
+    if (s_el + s_in + s_br + s_an > smaj) c->st->maj_excess++;
     if (u < s_el) e_hard(c, p, 0);
     else if (u < s_el + s_in) e_hard(c, p, 1);
     else if (u < s_el + s_in + s_br) e_hard(c, p, 2);
-    else {
+    else if (u < s_el + s_in + s_br + s_an) {
+      e_hard(c, p, 3);
+      return;
+    } else {
       c->st->delta++;
       event(c, p, EV_STEP, v);
     }
@@ -1234,8 +1302,9 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
                      uint64_t n, const double* w, double* a_acc, double* b_acc,
                      double* p_acc, double* sum_q_h) {
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
-  /* the estimator has no term for the score of a straggled soft loss */
-  if (t->flags & ORC_STRAGGLING) return -4;
+  /* the estimator has no term for the score of a straggled soft loss, and
+   * the replays of the device path run the main step only */
+  if (t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));
@@ -1315,6 +1384,7 @@ int orc_sample(const orc_tables* tb, int which, double e, uint32_t seed, int n,
         break;
       }
       case ORC_SMP_ANNIH: a = 2.0 * draw(&s) - 1.0; break;
+      case ORC_SMP_ANNIH_FLIGHT: a = sample_annih(&s, e); b = annih_cos(e, a); break;
       default: return -1;
     }
     out0[i] = a;

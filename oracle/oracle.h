@@ -51,7 +51,8 @@ enum {
   ORC_NO_HARD_ELASTIC = 1u << 4,
   ORC_NO_HARD_INELASTIC = 1u << 5,
   ORC_NO_HARD_BREMS = 1u << 6,
-  ORC_STRAGGLING = 1u << 7
+  ORC_STRAGGLING = 1u << 7,
+  ORC_ANNIH_FLIGHT = 1u << 8  /* two-photon annihilation of positrons in flight */
 };
 
 typedef struct {
@@ -135,6 +136,9 @@ double orc_soft_omega2(const orc_tables* tb, int type, double e);
 /* n soft energy losses of mean m and variance omega2 drawn by the straggling
  * sampler of the Class II step, draw streams (seed, i, uid 1) for i < n. */
 int orc_sample_straggle(double m, double omega2, uint32_t seed, int n, double* out);
+/* Heitler cross section per gram (cm^2/g) of two-photon annihilation of a
+ * positron of kinetic energy e with the material's electrons at rest. */
+double orc_sigma_annih(const orc_tables* tb, double e);
 
 /* Raw generators (pinned against published known-answer values). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -157,7 +161,9 @@ enum {
   ORC_SMP_SOFT,          /* e holds <mu>; out0 = mu */
   ORC_SMP_PAIR,          /* out0 = T-/(E - 2mc^2), out1 = cos theta of e- */
   ORC_SMP_FREE_PATH,     /* out0 = photon mass free path tau (g/cm^2) */
-  ORC_SMP_ANNIH          /* out0 = cos theta of the first photon */
+  ORC_SMP_ANNIH,         /* out0 = cos theta of the first photon */
+  ORC_SMP_ANNIH_FLIGHT   /* out0 = energy fraction zeta of the softer photon,
+                            out1 = its cos theta (the other's follows) */
 };
 
 /* Transport histories [first, first + n) of the concatenated sources.
