@@ -78,6 +78,14 @@ extern "C" {
  * soft loss is then the deterministic CSDA value); not supported by
  * mcx_dose_backward. */
 #define MCX_STRAGGLING (1u << 7)
+/* Two-photon annihilation of positrons in flight with the material's
+ * electrons at rest: a fourth hard channel with Heitler's cross section
+ * (bounded over a step by its value at the step's lowest energy, since it
+ * falls with energy); the softer photon's share of E + 2mc^2 is drawn from
+ * Heitler's DCS and both photon directions follow from energy and momentum
+ * conservation.  Off by default (positrons then annihilate at rest only);
+ * not supported by mcx_dose_backward. */
+#define MCX_ANNIH_FLIGHT (1u << 8)
 
 typedef struct mcx_ctx mcx_ctx;
 

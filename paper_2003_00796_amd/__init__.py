@@ -24,6 +24,7 @@ SRC_PENCIL, SRC_RECT = 0, 1
 NO_COMPTON, NO_PHOTO, NO_RAYLEIGH, NO_PAIR = 1, 2, 4, 8
 NO_HARD_ELASTIC, NO_HARD_INELASTIC, NO_HARD_BREMS = 16, 32, 64
 STRAGGLING = 128
+ANNIH_FLIGHT = 256
 
 ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM", -4: "MCX_E_DEVICE",
           -5: "MCX_E_RANGE", -6: "MCX_E_CANCELLED", -7: "MCX_E_UNSUPPORTED"}

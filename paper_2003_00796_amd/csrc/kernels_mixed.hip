@@ -21,7 +21,7 @@ static hipError_t launch_flavor(const KArgs<float>& a, int par, uint32_t target,
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(float);
   const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(float);
   if (ev) (void)hipEventRecord(ev[0], s);
-  constexpr int B = base_flavor(F);  // straggling changes the e+- step only
+  constexpr int B = base_flavor(F);  // the extended physics changes the e+- step only
   hipLaunchKernelGGL((k_source<float, B>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL((k_flight<float, B>), dim3(grid), dim3(block), sm_f, s, a, par);
@@ -39,9 +39,9 @@ hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int
   // replays never write the test outputs
   if (a.mode == 1) return launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev);
   if (a.mode == 2) return launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev);
-  if (a.straggle)
-    return a.test_mode ? launch_flavor<FL_STRAG_TEST>(a, par, target, grid, block, s, ev)
-                       : launch_flavor<FL_STRAG>(a, par, target, grid, block, s, ev);
+  if (a.straggle || a.annih)
+    return a.test_mode ? launch_flavor<FL_EXT_TEST>(a, par, target, grid, block, s, ev)
+                       : launch_flavor<FL_EXT>(a, par, target, grid, block, s, ev);
   if (a.test_mode) return launch_flavor<FL_TEST>(a, par, target, grid, block, s, ev);
   return launch_flavor<FL_FWD>(a, par, target, grid, block, s, ev);
 }
@@ -65,8 +65,8 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
                              reinterpret_cast<const void*>(&k_estep<float, FL_TEST>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_ADJ_A>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_ADJ_B>),
-                             reinterpret_cast<const void*>(&k_estep<float, FL_STRAG>),
-                             reinterpret_cast<const void*>(&k_estep<float, FL_STRAG_TEST>)};
+                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_TEST>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

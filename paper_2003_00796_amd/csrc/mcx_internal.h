@@ -156,6 +156,8 @@ struct Tab {
   T strag_k;         // 2 pi r_e^2 mc^2 n_e, MeV cm^2/g
   T strag_b;         // bremsstrahlung DCS constant b, cm^2/g
   T wcc_soft, wcr_soft;
+  // two-photon annihilation in flight: pi r_e^2 n_e, cm^2/g
+  T annih_k;
 };
 
 template <typename T>
@@ -191,6 +193,7 @@ struct KArgs {
   // 2: replay B scatters (Q_h - Qbar) times the photon free-flight scores)
   int mode;
   int straggle;          // soft energy-loss straggling on (selects the kernel flavour)
+  int annih;             // positron annihilation in flight on (selects the kernel flavour)
   const double* adj_w;   // per voxel: dL/dD_v * 1e6 / (rho_v V)
   double* adj_q;         // per history of the run: Q_h
   double* adj_grad;      // per voxel accumulator

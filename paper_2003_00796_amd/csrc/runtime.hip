@@ -281,6 +281,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.tb.strag_b = T(b.strag_b);
   a.tb.wcc_soft = T(b.wcc_soft);
   a.tb.wcr_soft = T(b.wcr_soft);
+  a.tb.annih_k = T(b.annih_k);
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
   a.dx = c->vox[0]; a.dy = c->vox[1]; a.dz = c->vox[2];
   a.ox = c->org[0]; a.oy = c->org[1]; a.oz = c->org[2];
@@ -308,6 +309,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.steps = c->steps;
   a.mode = mode;
   a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
+  a.annih = (mode == 0 && (c->tr.flags & MCX_ANNIH_FLIGHT)) ? 1 : 0;
   if (mode) {
     a.test_mode = 0;
     a.adj_w = static_cast<const double*>(c->d_adj_w.p);
@@ -894,8 +896,8 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
-  if (c->tr.flags & MCX_STRAGGLING)
-    return fail(c, MCX_E_UNSUPPORTED, "the gradient estimator has no term for straggled soft losses");
+  if (c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT))
+    return fail(c, MCX_E_UNSUPPORTED, "the gradient replays run the main step only (no straggling, no annihilation in flight)");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

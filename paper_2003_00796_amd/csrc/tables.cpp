@@ -160,6 +160,7 @@ class Model {
   // W^2): times W^2 and integrated over (0, Wc] it gives strag_k Wc / beta^2
   // (Bohr's variance of the soft collision loss per unit mass path)
   double strag_k() const { return 2.0 * kPi * kRe * kRe * kMc2 * ne_; }
+  double annih_k() const { return kPi * kRe * kRe * ne_; }
 
  private:
   mcx_material_desc m_;
@@ -284,6 +285,7 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
   const double inf = std::numeric_limits<double>::infinity();
   b.wcc_soft = (t.flags & MCX_NO_HARD_INELASTIC) ? inf : t.wcc;
   b.wcr_soft = (t.flags & MCX_NO_HARD_BREMS) ? inf : t.wcr;
+  b.annih_k = md.annih_k();
   return true;
 }
 

@@ -16,6 +16,7 @@ struct BuiltTables {
   double k_coef = 0, eta_a = 0, eta_b = 0, ray_a = 0;
   // soft energy-loss straggling (see Tab in mcx_internal.h)
   double strag_k = 0, strag_b = 0, wcc_soft = 0, wcr_soft = 0;
+  double annih_k = 0;  // pi r_e^2 n_e: Heitler's cross section per gram is annih_k times a function of E
 };
 
 bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTables* out, std::string* err);

@@ -566,7 +566,7 @@ __device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStat
 enum Ev : uint32_t {
   EV_COMPTON = 1, EV_PHOTO = 2, EV_RAYLEIGH = 3, EV_PAIR = 4, EV_PH_ESCAPE = 5,
   EV_CROSS = 6, EV_STEP = 7, EV_HARD_EL = 8, EV_HARD_IN = 9, EV_HARD_BR = 10,
-  EV_ABSORB = 11, EV_E_ESCAPE = 12
+  EV_ABSORB = 11, EV_E_ESCAPE = 12, EV_ANNIH_FLIGHT = 13
 };
 
 template <typename T>

@@ -40,15 +40,16 @@ enum Flavor : int {
   FL_TEST = 1,        // forward transport with the per-history test outputs
   FL_ADJ_A = 2,       // first density-gradient replay (per-history weighted score)
   FL_ADJ_B = 3,       // second replay (likelihood-ratio scores of photon flights)
-  FL_STRAG = 4,       // forward transport, soft energy-loss straggling
-  FL_STRAG_TEST = 5   // the same with the per-history test outputs
+  FL_EXT = 4,         // forward transport with the optional physics: soft energy-loss
+                      // straggling, positron annihilation in flight (run-time switches)
+  FL_EXT_TEST = 5     // the same with the per-history test outputs
 };
 constexpr int kFlavors = 6;
 
-// straggling changes the e+- step only: the other kernels of a straggling
-// flavour are those of the flavour without it
-constexpr int base_flavor(int f) { return f == FL_STRAG ? FL_FWD : (f == FL_STRAG_TEST ? FL_TEST : f); }
-constexpr bool straggles(int f) { return f == FL_STRAG || f == FL_STRAG_TEST; }
+// the optional physics changes the e+- step only: the other kernels of an
+// extended flavour are those of the flavour without it
+constexpr int base_flavor(int f) { return f == FL_EXT ? FL_FWD : (f == FL_EXT_TEST ? FL_TEST : f); }
+constexpr bool extended(int f) { return f == FL_EXT || f == FL_EXT_TEST; }
 
 template <int F, typename T>
 __device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
@@ -703,8 +704,21 @@ __device__ __forceinline__ T soft_straggle(const Tab<T>& tb, int lep, T e, T m, 
   return u < aa ? T(0) : T(1.5) * s2 / m * (u - aa) / (T(1) - aa);
 }
 
-// one Class II step; returns false when the particle is gone
-template <typename T, bool STRAG>
+// Heitler's cross section per gram of two-photon annihilation in flight of a
+// positron of kinetic energy e (g = 1 + e/mc^2, p = sqrt(g^2 - 1)):
+// pi r_e^2 n_e [(g^2 + 4g + 1) ln(g + p) - (g + 3) p] / ((g + 1)(g^2 - 1)).
+// It falls with energy.
+template <typename T>
+__device__ __forceinline__ T sigma_annih(const Tab<T>& tb, T e) {
+  const T g = T(1) + e / T(kMc2);
+  const T p = M<T>::sqrt(g * g - T(1));
+  return tb.annih_k * ((g * g + T(4) * g + T(1)) * M<T>::log(g + p) - (g + T(3)) * p) / ((g + T(1)) * (g * g - T(1)));
+}
+
+// one Class II step; returns false when the particle is gone.  EXT compiles
+// in the optional physics (straggling, annihilation in flight), each behind
+// its run-time switch.
+template <typename T, bool EXT>
 __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1, Child<T>& c2, DepAcc& acc,
                        LaneStats& ls, BlockStats* bs) {
   const Tab<T>& tb = a.tb;
@@ -729,7 +743,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const T r0 = range_at(tab, nt, base, g, e, le, tb.lemin, tb.dl);
   T elo = r0 - tau_max > T(0) ? range_inv(tab, nt, base, r0 - tau_max, g.i) : tb.emin;
   if (elo > e) elo = e;
-  if constexpr (STRAG) {
+  if (EXT && a.straggle) {
     // a straggled loss can exceed the step's CSDA loss: by at most twice the
     // CSDA mean (Gaussian and uniform laws) and by at most 6 Omega^2(E)/S
     // (two-mode law; 8 here, for the stopping power's change over the step):
@@ -739,7 +753,12 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
     const T dmax = dw > d2 ? dw : d2;
     elo = e - dmax > tb.emin ? e - dmax : tb.emin;
   }
-  const T smaj = majorant(tb, tab, base, lep, elo, g, e);
+  T smaj = majorant(tb, tab, base, lep, elo, g, e);
+  if constexpr (EXT) {
+    // annihilation in flight: its cross section falls with energy, so its
+    // value at the interval's low end bounds it over the step
+    if (a.annih && lep) smaj += sigma_annih(tb, elo);
+  }
   const T u1 = uni<T>(p.rng);
   const T tau_h = smaj > T(0) ? -M<T>::log(u1) / smaj : M<T>::inf();
   const bool capped = !(tau_h <= tau_max);
@@ -759,7 +778,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const double mass_path = double(rho) * (face_first ? db : len);
   T e1 = range_inv(tab, nt, base, T(r0 - T(mass_path)), g.i);
   if (!(e1 < e)) e1 = e;
-  if constexpr (STRAG) {
+  if (EXT && a.straggle) {
     // the loss keeps its CSDA mean and fluctuates about it (drawn after the
     // hinge position, before the soft deflection)
     e1 = e - soft_straggle(tb, lep, e, e - e1, mass_path, p.rng);
@@ -820,11 +839,52 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   const T s_el = interp(tab, nt, base + O_LEL, g1, e1, T(0));
   const T s_in = interp(tab, nt, base + O_LIN, g1, e1, tb.thr_in[lep]);
   const T s_br = interp(tab, nt, base + O_LBR, g1, e1, tb.thr_br);
-  const int kind = u < s_el ? 1 : (u < s_el + s_in ? 2 : (u < s_el + s_in + s_br ? 3 : 0));
+  int kind = u < s_el ? 1 : (u < s_el + s_in ? 2 : (u < s_el + s_in + s_br ? 3 : 0));
+  if constexpr (EXT) {
+    if (kind == 0 && a.annih && lep && u < s_el + s_in + s_br + sigma_annih(tb, e1)) kind = 4;
+  }
   if (kind == 0) {
     stat_add(bs, S_DELTA);
     event(a, p, EV_STEP, v);
     return true;
+  }
+  if constexpr (EXT) {
+    if (kind == 4) {
+      // two-photon annihilation with an electron at rest: the softer photon
+      // takes the share z of E + 2mc^2, z in [zmin, 1/2], from Heitler's DCS
+      // S(z) + S(1-z), S(x) = -(g+1)^2 + (g^2+4g+1)/x - 1/x^2: proposal 1/z
+      // (log-uniform), acceptance z (S(z) + S(1-z)) / (2 (g^2+4g+1)) <= 1;
+      // polar cosines (g + 1 - 1/z)/p from energy-momentum conservation, the
+      // photons on opposite azimuths
+      stat_add(bs, S_ANNIH);
+      const T gm = T(1) + e1 / T(kMc2);
+      const T pm = M<T>::sqrt(gm * gm - T(1));
+      const T zmin = T(1) / (gm + T(1) + pm);
+      const T cc = gm * gm + T(4) * gm + T(1);
+      const T g1 = (gm + T(1)) * (gm + T(1));
+      T z = T(0.5);
+      for (int tries = 0; tries < kMaxTries; ++tries) {
+        z = zmin * M<T>::pow(T(0.5) / zmin, uni<T>(p.rng));
+        const T y = T(1) - z;
+        const T f = -g1 + cc / z - T(1) / (z * z) - g1 + cc / y - T(1) / (y * y);
+        if (uni<T>(p.rng) * T(2) * cc <= z * f) break;
+      }
+      const T ph = T(2.0 * kPi) * uni<T>(p.rng);
+      const T etot = e1 + T(2.0 * kMc2);
+      const T ka = z * etot, kb = etot - ka;
+      T ca = (gm + T(1) - T(1) / z) / pm, cb = (gm + T(1) - T(1) / (T(1) - z)) / pm;
+      ca = ca > T(1) ? T(1) : (ca < T(-1) ? T(-1) : ca);
+      cb = cb > T(1) ? T(1) : (cb < T(-1) ? T(-1) : cb);
+      T da[3] = {p.d[0], p.d[1], p.d[2]}, dv[3] = {p.d[0], p.d[1], p.d[2]};
+      rotate(da, ca, ph);
+      rotate(dv, cb, ph + T(kPi));
+      make_child(a, p, c1, PHOTON, ka, da, acc, ls, bs);
+      make_child(a, p, c2, PHOTON, kb, dv, acc, ls, bs);
+      p.e = T(0);
+      event(a, p, EV_ANNIH_FLIGHT, v);
+      finish(a, p);
+      return false;
+    }
   }
   T cos_p = T(1), cos_c = T(1), w = T(0);  // primary and secondary polar cosines, energy lost
   if (kind == 1) {
@@ -967,7 +1027,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     c1.on = false;
     c2.on = false;
     if (alive) {
-      alive = e_step<T, straggles(F)>(a, tab, p, c1, c2, acc, ls, &bs);
+      alive = e_step<T, extended(F)>(a, tab, p, c1, c2, acc, ls, &bs);
       ++used;
     }
     dep_flush_pending(a, acc, ls);
