@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--electron", action="store_true", help="also time the 20 MeV electron workload")
     ap.add_argument("--straggling", action="store_true",
                     help="also time the mixed step with soft energy-loss straggling on")
+    ap.add_argument("--annih-flight", action="store_true",
+                    help="also time the mixed step with positron annihilation in flight on")
     ap.add_argument("--no-fp64", action="store_true")
     # records per event queue: 2^26 puts a quarter of it, 16.8 M particles,
     # in flight at once (all histories of a 1e7 step are admitted together)
@@ -326,8 +328,9 @@ def main():
                                                       "evisits")},
         "roofline": roofline(st),
     }
-    if args.straggling:
-        t = dict(wl["transport"], flags=wl["transport"].get("flags", 0) | mcx.STRAGGLING)
+    if args.straggling or args.annih_flight:
+        extra = (mcx.STRAGGLING if args.straggling else 0) | (mcx.ANNIH_FLIGHT if args.annih_flight else 0)
+        t = dict(wl["transport"], flags=wl["transport"].get("flags", 0) | extra)
         sg = mcx.Simulator(mcx.MIXED, 0).setup(dict(wl, transport=t))
         sg.set_launch(args.bank, 256, 128)
         run_steps(sg, n, warm_seeds, sync)
@@ -337,9 +340,10 @@ def main():
         sg.close()
         hi = d_mix >= 0.5 * d_mix.max()
         z = (d_sg[hi] - d_mix[hi]) / np.sqrt(s_sg[hi] ** 2 + s_mix[hi] ** 2)
-        out["straggling"] = dict(value=n * len(t_sg) / sum(t_sg), ms_per_step=1e3 * sum(t_sg) / len(t_sg),
-                                 esteps_per_history=st_sg["esteps"] / n,
-                                 dose_vs_csda=dict(high_dose_deviation(d_sg, d_mix), z_rms=float(np.sqrt(np.mean(z ** 2))),
+        out["extended_physics"] = dict(straggling=bool(args.straggling), annih_flight=bool(args.annih_flight),
+                                 value=n * len(t_sg) / sum(t_sg), ms_per_step=1e3 * sum(t_sg) / len(t_sg),
+                                 esteps_per_history=st_sg["esteps"] / n, annihilations_per_history=st_sg["annih"] / n,
+                                 dose_vs_main=dict(high_dose_deviation(d_sg, d_mix), z_rms=float(np.sqrt(np.mean(z ** 2))),
                                                    z_mean=float(np.mean(z))))
     if not args.no_gradient:
         out["gradient"] = gradient_timing(mcx, W, sync)
