@@ -152,6 +152,16 @@ def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
     sync()
     t_batched = time.perf_counter() - t0
     d_all, _ = sim.dose()
+    # the same run with the per-beamlet dose-influence output
+    sim.set_influence(True, 30)
+    sim.reset()
+    sync()
+    t0 = time.perf_counter()
+    sim.run(1, 0, sim.n_hist_total)
+    sync()
+    t_infl = time.perf_counter() - t0
+    n_entries = sim.influence()[0].size
+    sim.set_influence(False)
     sim.reset()
     sync()
     t0 = time.perf_counter()
@@ -167,6 +177,7 @@ def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
     return dict(workload="beamlets_256: 512 beamlets 4-15 MeV, lognormal counts, 256^3 x 2 mm noise phantom, mixed",
                 histories=int(sum(x["n_hist"] for x in wl["sources"])), autotuned=dict(zip(("bank", "block", "steps"), chosen)),
                 autotune_s=t_tune, batched_s=t_batched, per_beamlet_s=t_each,
+                batched_with_influence_s=t_infl, influence_entries=n_entries,
                 batched_hist_per_s=sum(x["n_hist"] for x in wl["sources"]) / t_batched,
                 speedup=t_each / t_batched,
                 same_dose_rel_max=float(np.max(np.abs(d_all[hi] - d_each[hi]) / d_all[hi])))

@@ -258,6 +258,25 @@ int mcx_reset_tallies(mcx_ctx* ctx);
 /* Statistics since the last reset. */
 int mcx_get_stats(mcx_ctx* ctx, mcx_stats* out);
 
+/* Per-source dose influence (one source = one beamlet): with on != 0, every
+ * later run also accumulates, per (source, voxel) pair that received
+ * energy, the per-history scores q of that source's histories: Sum q and
+ * Sum q^2 (MeV), formed at the chunk flush where each history's score is
+ * complete (Eq. (1)-(3)).  The pairs live in a device hash table of
+ * 2^log2_slots entries (24 B each; log2_slots in [10, 30]); a run that
+ * fills it fails with MCX_E_RANGE.  The dose of source b in voxel v per
+ * history of b is Sum q * 1e6 / (rho_v V n_b) eV/g, n_b its histories run.
+ * mcx_reset_tallies clears the table; on = 0 frees it.  The table is library
+ * memory, and checkpoints do not hold it. */
+int mcx_set_influence(mcx_ctx* ctx, int on, uint32_t log2_slots);
+/* Read the influence table as n entries (source index, voxel index, Sum q,
+ * Sum q^2) in no particular order, into host arrays of `capacity` entries.
+ * *n receives the number of entries; with all four arrays NULL only the
+ * count is returned; MCX_E_RANGE if capacity < *n.  MCX_E_STATE when the
+ * influence output is off. */
+int mcx_get_influence(mcx_ctx* ctx, uint32_t* source, uint32_t* voxel, double* sum_q, double* sum_q2,
+                      uint64_t capacity, uint64_t* n);
+
 /* Wait for the work queued on the context's own stream and report a device
  * fault or an earlier asynchronous HIP error as MCX_E_DEVICE.  (mcx_run and
  * the result calls already wait for their own work before returning.) */

@@ -35,7 +35,7 @@ ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
                "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune",
                "mcx_synchronize", "mcx_cancel", "mcx_checkpoint", "mcx_restore", "mcx_workspace_size",
-               "mcx_set_workspace")
+               "mcx_set_workspace", "mcx_set_influence", "mcx_get_influence")
 
 
 class MaterialDesc(C.Structure):
@@ -136,6 +136,8 @@ def lib():
         L.mcx_restore.argtypes = [vp, vp, C.c_size_t]
         L.mcx_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.mcx_set_workspace.argtypes = [vp, vp, C.c_size_t]
+        L.mcx_set_influence.argtypes = [vp, C.c_int, C.c_uint32]
+        L.mcx_get_influence.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, C.POINTER(C.c_uint64)]
         for f in ABI_SYMBOLS:
             if f not in ("mcx_destroy", "mcx_last_error"):
                 getattr(L, f).restype = C.c_int
@@ -286,6 +288,27 @@ class Simulator:
     def restore(self, data: bytes):
         buf = C.create_string_buffer(bytes(data), len(data))
         self._check(self._L.mcx_restore(self._h, buf, len(data)), "restore")
+
+    def set_influence(self, on: bool = True, log2_slots: int = 24):
+        """Per-source (beamlet) dose influence: (source, voxel) Sum q and
+        Sum q^2 accumulated by later runs (see mcx_set_influence)."""
+        self._check(self._L.mcx_set_influence(self._h, 1 if on else 0, log2_slots), "set_influence")
+
+    def influence(self):
+        """(source, voxel, sum_q, sum_q2) arrays of the influence table,
+        sorted by source, then voxel."""
+        n = C.c_uint64(0)
+        self._check(self._L.mcx_get_influence(self._h, None, None, None, None, 0, C.byref(n)), "get_influence")
+        k = n.value
+        src = np.zeros(k, dtype=np.uint32)
+        vox = np.zeros(k, dtype=np.uint32)
+        q = np.zeros(k)
+        q2 = np.zeros(k)
+        if k:
+            self._check(self._L.mcx_get_influence(self._h, _ptr(src), _ptr(vox), _ptr(q), _ptr(q2), k, C.byref(n)),
+                        "get_influence")
+        order = np.lexsort((vox, src))
+        return src[order], vox[order], q[order], q2[order]
 
     def workspace_size(self) -> int:
         n = C.c_size_t(0)

@@ -32,6 +32,7 @@ UNITS = [
     ("kernels_mixed.hip", ["-freciprocal-math", "-fno-signed-zeros", "-fno-trapping-math", "-fno-math-errno",
                            "-fgpu-flush-denormals-to-zero", "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("runtime.hip", []),
+    ("influence.hip", []),
 ]
 
 

@@ -35,6 +35,15 @@ hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddos
                                    const float* rho, uint64_t nvox, double vol, double nhist, double* out,
                                    hipStream_t s);
 hipError_t launch_sum(const double* q, uint64_t n, double* out, hipStream_t s);
+// per-source dose influence: the chunk flush that also adds every score to
+// the (source, voxel) table, and the table's compaction into arrays
+hipError_t launch_flush_influence(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q2, Counters* cnt,
+                                  int test_mode, double* hist_led, uint64_t n_run, const SourceDev* src, int nsrc,
+                                  uint64_t* ikeys, double* iq, double* iq2, uint64_t imask, uint32_t* iovf,
+                                  hipStream_t s);
+hipError_t launch_influence_compact(const uint64_t* ikeys, const double* iq, const double* iq2, uint64_t nslot,
+                                    uint32_t* osrc, uint32_t* ovox, double* oq, double* oq2, uint64_t cap,
+                                    unsigned long long* count, hipStream_t s);
 // same-density cube half-widths of every voxel into `out` (tmp: nvox bytes)
 hipError_t launch_cube_map(const double* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s);
 hipError_t launch_cube_map(const float* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s);

@@ -82,6 +82,11 @@ struct mcx_ctx {
   // cancellation request (mcx_cancel may be called from another host thread)
   std::atomic<int> cancel{0};
   uint64_t next_history = 0;  // first history id not completed by the last run
+  // per-source dose influence (mcx_set_influence): (source, voxel) keys,
+  // Sum q and Sum q^2, overflow flag
+  int influence = 0;
+  uint64_t islots = 0;
+  DevBuf d_ikeys, d_iq, d_iq2, d_iovf;
   // test mode
   int test_mode = 0;
   DevBuf d_hhash, d_hled;
@@ -461,10 +466,19 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
       continue;
     }
     auto tf = std::chrono::steady_clock::now();
-    e = launch_flush(a.hkeys, a.hvals, slots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+    uint32_t iovf = 0;
+    if (c->influence) {
+      e = launch_flush_influence(a.hkeys, a.hvals, slots, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, a.src, a.nsrc,
+                                 static_cast<uint64_t*>(c->d_ikeys.p), static_cast<double*>(c->d_iq.p),
+                                 static_cast<double*>(c->d_iq2.p), c->islots - 1, static_cast<uint32_t*>(c->d_iovf.p), s);
+      if (e == hipSuccess) e = hipMemcpyAsync(&iovf, c->d_iovf.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    } else {
+      e = launch_flush(a.hkeys, a.hvals, slots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "tally flush");
+    if (iovf) return fail(c, MCX_E_RANGE, "influence table overflow (%llu slots)", (unsigned long long)c->islots);
     flush_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
     const double pairs = double(c->h_cnt->occupied);
     c->tally_pairs += c->h_cnt->occupied;
@@ -520,7 +534,8 @@ void mcx_destroy(mcx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_cube, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
-                    &c->d_hvals, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad, &c->d_adj_dl, &c->d_adj_out,
+                    &c->d_hvals, &c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad,
+                    &c->d_adj_dl, &c->d_adj_out,
                     &c->d_adj_sum, &c->d_hhash, &c->d_hled})
     dfree(*b);
   if (c->h_cnt) (void)hipHostFree(c->h_cnt);
@@ -587,6 +602,12 @@ int mcx_reset_tallies(mcx_ctx* c) {
   hipError_t e = hipMemsetAsync(c->d_sumq.p, 0, bytes, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d_sumq2.p, 0, bytes, c->stream);
   if (e == hipSuccess && c->d_cnt.p) e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
+  if (e == hipSuccess && c->influence) {
+    e = hipMemsetAsync(c->d_ikeys.p, 0xFF, c->islots * sizeof(uint64_t), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_iq.p, 0, c->islots * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_iq2.p, 0, c->islots * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_iovf.p, 0, sizeof(uint32_t), c->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reset tallies");
   c->n_done = 0;
@@ -1171,6 +1192,99 @@ int mcx_restore(mcx_ctx* c, const void* buf, size_t size) {
   c->ms_transport = h.ms_transport;
   c->ms_flush = h.ms_flush;
   c->last_valid = false;
+  return MCX_OK;
+}
+
+int mcx_set_influence(mcx_ctx* c, int on, uint32_t log2_slots) {
+  if (!c) return MCX_E_INVALID;
+  if (!on) {
+    for (DevBuf* b : {&c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf}) dfree(*b);
+    c->influence = 0;
+    c->islots = 0;
+    return MCX_OK;
+  }
+  if (log2_slots < 10 || log2_slots > 30) return fail(c, MCX_E_INVALID, "log2_slots must lie in [10, 30]");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  const uint64_t slots = 1ull << log2_slots;
+  int rc;
+  if ((rc = dalloc(c, c->d_ikeys, slots * sizeof(uint64_t), "influence keys")) ||
+      (rc = dalloc(c, c->d_iq, slots * sizeof(double), "influence Sum q")) ||
+      (rc = dalloc(c, c->d_iq2, slots * sizeof(double), "influence Sum q^2")) ||
+      (rc = dalloc(c, c->d_iovf, sizeof(uint32_t), "influence overflow flag"))) {
+    for (DevBuf* b : {&c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf}) dfree(*b);
+    c->influence = 0;
+    return rc;
+  }
+  hipError_t e = hipMemsetAsync(c->d_ikeys.p, 0xFF, slots * sizeof(uint64_t), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_iq.p, 0, slots * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_iq2.p, 0, slots * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_iovf.p, 0, sizeof(uint32_t), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "clear influence table");
+  c->influence = 1;
+  c->islots = slots;
+  return MCX_OK;
+}
+
+int mcx_get_influence(mcx_ctx* c, uint32_t* source, uint32_t* voxel, double* sum_q, double* sum_q2, uint64_t capacity,
+                      uint64_t* n) {
+  if (!c || !n) return MCX_E_INVALID;
+  if (!c->influence) return fail(c, MCX_E_STATE, "influence output is off (mcx_set_influence)");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  hipStream_t s = c->stream;
+  DevBuf cnt;
+  int rc = dalloc(c, cnt, sizeof(unsigned long long), "influence count");
+  if (rc) return rc;
+  unsigned long long count = 0;
+  auto pass = [&](uint64_t cap, uint32_t* os, uint32_t* ov, double* oq, double* oq2) {
+    hipError_t e = hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess)
+      e = launch_influence_compact(static_cast<const uint64_t*>(c->d_ikeys.p), static_cast<const double*>(c->d_iq.p),
+                                   static_cast<const double*>(c->d_iq2.p), c->islots, os, ov, oq, oq2, cap,
+                                   static_cast<unsigned long long*>(cnt.p), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, cnt.p, sizeof(count), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  };
+  hipError_t e = pass(0, nullptr, nullptr, nullptr, nullptr);
+  if (e != hipSuccess) {
+    dfree(cnt);
+    return hip_fail(c, e, "count influence entries");
+  }
+  *n = count;
+  if (!source && !voxel && !sum_q && !sum_q2) {
+    dfree(cnt);
+    return MCX_OK;
+  }
+  if (!source || !voxel || !sum_q || !sum_q2) {
+    dfree(cnt);
+    return fail(c, MCX_E_INVALID, "pass all four output arrays, or none to count");
+  }
+  if (capacity < count) {
+    dfree(cnt);
+    return fail(c, MCX_E_RANGE, "influence output needs %llu entries", count);
+  }
+  DevBuf out;
+  if ((rc = dalloc(c, out, size_t(count) * (2 * sizeof(uint32_t) + 2 * sizeof(double)) + 64, "influence staging"))) {
+    dfree(cnt);
+    return rc;
+  }
+  double* oq = static_cast<double*>(out.p);
+  double* oq2 = oq + count;
+  uint32_t* os = reinterpret_cast<uint32_t*>(oq2 + count);
+  uint32_t* ov = os + count;
+  const unsigned long long expect = count;
+  e = pass(expect, os, ov, oq, oq2);
+  if (e == hipSuccess && count != expect) e = hipErrorUnknown;
+  if (e == hipSuccess && count) {
+    e = hipMemcpy(source, os, size_t(count) * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(voxel, ov, size_t(count) * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(sum_q, oq, size_t(count) * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(sum_q2, oq2, size_t(count) * sizeof(double), hipMemcpyDeviceToHost);
+  }
+  dfree(out);
+  dfree(cnt);
+  if (e != hipSuccess) return hip_fail(c, e, "read influence entries");
   return MCX_OK;
 }
 
