@@ -57,7 +57,7 @@ class Phantom(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("ox", C.c_double), ("oy", C.c_double), ("oz", C.c_double),
-                ("rho", C.POINTER(C.c_double))]
+                ("rho", C.POINTER(C.c_double)), ("mat", C.POINTER(C.c_uint8))]
 
 
 class Source(C.Structure):
@@ -134,6 +134,10 @@ def lib():
         L.orc_run.argtypes = [C.c_void_p, C.POINTER(Transport), C.POINTER(Phantom),
                               C.POINTER(Source), C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
                               dp, dp, C.POINTER(Stats), C.POINTER(C.c_uint64), dp]
+        L.orc_run_mm.argtypes = [C.c_void_p, C.c_int, C.POINTER(Transport), C.POINTER(Phantom),
+                                 C.POINTER(Source), C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
+                                 dp, dp, C.POINTER(Stats), C.POINTER(C.c_uint64), dp]
+        L.orc_run_mm.restype = C.c_int
         L.orc_dose.argtypes = [C.POINTER(Phantom), C.c_uint64, dp, dp, dp, dp]
         L.orc_run_gradient.restype = C.c_int
         L.orc_run_gradient.argtypes = [C.c_void_p, C.POINTER(Transport), C.POINTER(Phantom),
@@ -276,6 +280,11 @@ def phantom_struct(ph: dict):
     nz, ny, nx = ph["shape"]
     s = Phantom(nx=nx, ny=ny, nz=nz, dx=ph["voxel"][0], dy=ph["voxel"][1], dz=ph["voxel"][2],
                 ox=ph["origin"][0], oy=ph["origin"][1], oz=ph["origin"][2], rho=_dp(rho))
+    if ph.get("mat") is not None:
+        mat = np.ascontiguousarray(ph["mat"], dtype=np.uint8).ravel()
+        assert mat.size == rho.size
+        s.mat = mat.ctypes.data_as(C.POINTER(C.c_uint8))
+        s._keep_mat = mat  # the array must outlive the structure
     return s, rho
 
 
@@ -287,9 +296,12 @@ class RunResult:
         self.n = 0
 
 
-def run(tables: Tables, phantom: dict, sources, seed: int, first: int, n: int,
+def run(tables, phantom: dict, sources, seed: int, first: int, n: int,
         result: RunResult | None = None, hashes: bool = False, ledger: bool = False):
-    """Transport histories [first, first+n); accumulates into `result`."""
+    """Transport histories [first, first+n); accumulates into `result`.
+    `tables` is one Tables, or a list of Tables (one per material, all on the
+    same grid and transport parameters) used with the phantom's "mat"
+    array."""
     ph, rho = phantom_struct(phantom)
     nvox = rho.size
     if result is None:
@@ -297,10 +309,15 @@ def run(tables: Tables, phantom: dict, sources, seed: int, first: int, n: int,
     src = source_array(sources)
     hs = np.zeros(n, dtype=np.uint64) if hashes else None
     led = np.zeros((n, LED_N)) if ledger else None
-    rc = lib().orc_run(tables.h, C.byref(tables.t), C.byref(ph), src, len(sources), seed, first, n,
-                       _dp(result.sum_q), _dp(result.sum_q2), C.byref(result.stats),
-                       hs.ctypes.data_as(C.POINTER(C.c_uint64)) if hs is not None else None,
-                       _dp(led) if led is not None else None)
+    hp = hs.ctypes.data_as(C.POINTER(C.c_uint64)) if hs is not None else None
+    lp = _dp(led) if led is not None else None
+    if isinstance(tables, (list, tuple)):
+        arr = (C.c_void_p * len(tables))(*[tb.h for tb in tables])
+        rc = lib().orc_run_mm(arr, len(tables), C.byref(tables[0].t), C.byref(ph), src, len(sources), seed, first,
+                              n, _dp(result.sum_q), _dp(result.sum_q2), C.byref(result.stats), hp, lp)
+    else:
+        rc = lib().orc_run(tables.h, C.byref(tables.t), C.byref(ph), src, len(sources), seed, first, n,
+                           _dp(result.sum_q), _dp(result.sum_q2), C.byref(result.stats), hp, lp)
     if rc:
         raise RuntimeError(f"orc_run failed: {rc}")
     result.n += n

@@ -34,6 +34,11 @@
  *     hard channel with Heitler's cross section for electrons at rest; the
  *     softer photon's energy fraction drawn from Heitler's DCS, the photon
  *     directions from energy and momentum conservation.
+ *  R10 several materials (optional): per-voxel material index, tables per
+ *     material on one grid; a photon flight accumulates the optical depth
+ *     rho mu_m(E) l voxel by voxel and interacts by the tables of the voxel it
+ *     stops in; an e+- step uses the tables of its voxel (every face ends a
+ *     step, so a step stays in one material).
  *  R8 straggling of the soft energy loss (optional): mean = the CSDA loss over
  *     the step's mass path s, variance = s times the second moment of the
  *     soft part of the energy-loss DCS (Bohr's variance from the leading
@@ -589,6 +594,8 @@ typedef struct {
 
 typedef struct {
   const orc_tables* tb;
+  const orc_tables* tbm[ORC_MAX_MAT];  /* tables per material (R10) */
+  const uint8_t* mat;                  /* per-voxel material, NULL: tb everywhere */
   const orc_transport* t;
   const orc_phantom* ph;
   int n[3];
@@ -799,6 +806,9 @@ static double sample_rayleigh(const orc_tables* tb, stream* s, double e) {
   }
 }
 
+/* tables of voxel v's material */
+static const orc_tables* tables_at(const ctx* c, int64_t v) { return c->mat ? c->tbm[c->mat[v]] : c->tb; }
+
 static void photon_knock(ctx* c, part* p, int ch) {
   orc_stats* st = c->st;
   int64_t v = lin(c, p->ix);
@@ -833,7 +843,7 @@ static void photon_knock(ctx* c, part* p, int ch) {
     event(c, p, EV_PHOTO, v);
   } else if (ch == 2) {
     st->rayleigh++;
-    double ct = sample_rayleigh(c->tb, &p->rng, p->e);
+    double ct = sample_rayleigh(tables_at(c, v), &p->rng, p->e);
     double phi = 2.0 * PI * draw(&p->rng);
     rotate(p->d, ct, phi);
     event(c, p, EV_RAYLEIGH, v);
@@ -859,9 +869,63 @@ static void photon_knock(ctx* c, part* p, int ch) {
 
 /* photon: JUMP (free path in mass thickness), STEP (DDA through voxels) and
  * KNOCK until absorbed or escaped */
+/* R10: the flight through voxels of several materials in optical depth:
+ * tau = -ln u, each voxel takes rho mu_m(E) l of it; the interaction channel
+ * is chosen by the tables of the voxel the photon stops in */
+static int photon_flight_mm(ctx* c, part* p, double* mu, double* mt_out) {
+  orc_stats* st = c->st;
+  double mtm[ORC_MAX_MAT];
+  for (int m = 0; m < ORC_MAX_MAT; ++m) {
+    const orc_tables* tm = c->tbm[m];
+    mtm[m] = 0.0;
+    if (!tm) continue;
+    for (int k = 0; k < 4; ++k) mtm[m] += interp(tm, tm->ph[k], tm->thr_ph[k], p->e);
+  }
+  st->flights++;
+  double tau = -log(draw(&p->rng));
+  for (;;) {
+    int a;
+    double s = face(c, p, &a);
+    int64_t v = lin(c, p->ix);
+    double att = c->ph->rho[v] * mtm[c->mat[v]];
+    if (att * s >= tau) {
+      move(p, tau / att);
+      break;
+    }
+    tau -= att * s;
+    if (cross(c, p, s, a)) {
+      st->escaped++;
+      c->led[ORC_LED_ESC] += p->e;
+      event(c, p, EV_PH_ESCAPE, v);
+      finish(c, p);
+      return 1;
+    }
+  }
+  const orc_tables* tb = tables_at(c, lin(c, p->ix));
+  double mt = 0.0;
+  for (int k = 0; k < 4; ++k) { mu[k] = interp(tb, tb->ph[k], tb->thr_ph[k], p->e); mt += mu[k]; }
+  *mt_out = mt;
+  return 0;
+}
+
 static void photon_track(ctx* c, part* p) {
   const orc_tables* tb = c->tb;
   orc_stats* st = c->st;
+  while (p->e > 0.0 && c->mat) {
+    double mu[4], mt;
+    if (photon_flight_mm(c, p, mu, &mt)) return;
+    double u = draw(&p->rng) * mt;
+    int ch = -1;
+    double cum = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      cum += mu[k];
+      if (u < cum) { ch = k; break; }
+    }
+    if (ch < 0)
+      for (int k = 3; k >= 0; --k)
+        if (mu[k] > 0.0) { ch = k; break; }
+    photon_knock(c, p, ch);
+  }
   while (p->e > 0.0) {
     double mu[4], mt = 0.0;
     for (int k = 0; k < 4; ++k) { mu[k] = interp(tb, tb->ph[k], tb->thr_ph[k], p->e); mt += mu[k]; }
@@ -1012,7 +1076,7 @@ static double annih_cos(double e, double z) {
 }
 
 static void e_hard(ctx* c, part* p, int which) {
-  const orc_tables* tb = c->tb;
+  const orc_tables* tb = tables_at(c, lin(c, p->ix));
   int ti = p->type == ORC_POSITRON ? 1 : 0;
   int64_t v = lin(c, p->ix);
   if (which == 0) {
@@ -1070,7 +1134,6 @@ static void e_hard(ctx* c, part* p, int which) {
 
 /* Class II step loop of one electron or positron */
 static void electron_track(ctx* c, part* p) {
-  const orc_tables* tb = c->tb;
   const orc_transport* t = c->t;
   int ti = p->type == ORC_POSITRON ? 1 : 0;
   double eabs = t->eabs[p->type];
@@ -1079,6 +1142,7 @@ static void electron_track(ctx* c, part* p) {
     c->st->esteps++;
     double e = p->e;
     int64_t v = lin(c, p->ix);
+    const orc_tables* tb = tables_at(c, v);  /* the step stays in this voxel's material */
     double rho = c->ph->rho[v];
     /* step control: maximum mass step and the hard-event majorant */
     double ss = interp(tb, tb->el[ti][CH_S], 0.0, e);
@@ -1191,24 +1255,32 @@ static int locate(const ctx* c, part* p) {
   return 0;
 }
 
-static int run_body(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
+static int run_body(const orc_tables* const* tbs, int n_mat, const orc_transport* t, const orc_phantom* ph,
                     const orc_source* src, int n_src, uint32_t seed, uint64_t first,
                     uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
                     uint64_t* hashes, double* ledger, const double* w, double* a_acc,
                     double* b_acc, double* p_acc, double* sum_q_h) {
-  if (!tb || !t || !ph || !src || n_src <= 0 || !sum_q || !sum_q2 || !stats) return -1;
+  if (!tbs || n_mat < 1 || n_mat > ORC_MAX_MAT || !t || !ph || !src || n_src <= 0 || !sum_q || !sum_q2 || !stats)
+    return -1;
+  for (int m = 0; m < n_mat; ++m)
+    if (!tbs[m]) return -1;
   uint64_t total = 0;
   for (int s = 0; s < n_src; ++s) total += src[s].n_hist;
   if (first + n > total || first + n > 0xFFFFFFFFull) return -2;
+  int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
+  if (ph->mat)
+    for (int64_t v = 0; v < nv; ++v)
+      if (ph->mat[v] >= n_mat) return -5;
   ctx c;
   memset(&c, 0, sizeof(c));
-  c.tb = tb;
+  c.tb = tbs[0];
+  for (int m = 0; m < n_mat; ++m) c.tbm[m] = tbs[m];
+  c.mat = ph->mat;
   c.t = t;
   c.ph = ph;
   c.n[0] = ph->nx; c.n[1] = ph->ny; c.n[2] = ph->nz;
   c.dx[0] = ph->dx; c.dx[1] = ph->dy; c.dx[2] = ph->dz;
   c.o[0] = ph->ox; c.o[1] = ph->oy; c.o[2] = ph->oz;
-  int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   c.tmp = (double*)calloc((size_t)nv, sizeof(double));
   c.mark = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nv);
   c.touched = (int64_t*)malloc(sizeof(int64_t) * (size_t)nv);
@@ -1293,7 +1365,14 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
             const orc_source* src, int n_src, uint32_t seed, uint64_t first,
             uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
             uint64_t* hashes, double* ledger) {
-  return run_body(tb, t, ph, src, n_src, seed, first, n, sum_q, sum_q2, stats, hashes, ledger,
+  return run_body(&tb, 1, t, ph, src, n_src, seed, first, n, sum_q, sum_q2, stats, hashes, ledger,
+                  NULL, NULL, NULL, NULL, NULL);
+}
+
+int orc_run_mm(const orc_tables* const* tbs, int n_mat, const orc_transport* t, const orc_phantom* ph,
+               const orc_source* src, int n_src, uint32_t seed, uint64_t first, uint64_t n, double* sum_q,
+               double* sum_q2, orc_stats* stats, uint64_t* hashes, double* ledger) {
+  return run_body(tbs, n_mat, t, ph, src, n_src, seed, first, n, sum_q, sum_q2, stats, hashes, ledger,
                   NULL, NULL, NULL, NULL, NULL);
 }
 
@@ -1304,13 +1383,13 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
   /* the estimator has no term for the score of a straggled soft loss, and
    * the replays of the device path run the main step only */
-  if (t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) return -4;
+  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || ph->mat) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));
   orc_stats st;
   memset(&st, 0, sizeof(st));
-  int rc = run_body(tb, t, ph, src, n_src, seed, first, n, q, q2, &st, NULL, NULL, w, a_acc, b_acc,
+  int rc = run_body(&tb, 1, t, ph, src, n_src, seed, first, n, q, q2, &st, NULL, NULL, w, a_acc, b_acc,
                     p_acc, sum_q_h);
   free(q);
   free(q2);

@@ -84,7 +84,10 @@ typedef struct {
   double dx, dy, dz;   /* voxel size, cm */
   double ox, oy, oz;   /* corner of voxel (0,0,0), cm */
   const double* rho;   /* g/cm^3, x fastest, length nx*ny*nz */
+  const uint8_t* mat;  /* material index per voxel (< the number of tables), or NULL */
 } orc_phantom;
+
+#define ORC_MAX_MAT 4
 
 typedef struct {
   int particle;        /* ORC_PHOTON / ORC_ELECTRON / ORC_POSITRON */
@@ -170,6 +173,12 @@ enum {
  * sum_q / sum_q2 (length nx*ny*nz, MeV) are ACCUMULATED; stats is
  * accumulated; hashes (n) and ledger (n * ORC_LED_N) are written when non-NULL.
  * Returns 0 or a negative error code. */
+/* Several materials (R10): tbs[m] holds the tables of material m, all built
+ * on the same grid with the same transport parameters; ph->mat selects one
+ * per voxel.  Returns -5 for a material index >= n_mat. */
+int orc_run_mm(const orc_tables* const* tbs, int n_mat, const orc_transport* t, const orc_phantom* ph,
+               const orc_source* src, int n_src, uint32_t seed, uint64_t first, uint64_t n, double* sum_q,
+               double* sum_q2, orc_stats* stats, uint64_t* hashes, double* ledger);
 int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
             const orc_source* src, int n_src, uint32_t seed, uint64_t first,
             uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,

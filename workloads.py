@@ -37,6 +37,18 @@ WATER = dict(
     brems_b=0.016,
 )
 
+# Synthetic cortical-bone-like material (model parameters, not data): per
+# formula unit 50 electrons and 96.2 g/mol (Z/A = 0.52), Z(Z+1) sum for an
+# effective Z of 13.8, I = 106.4 eV; photoelectric, pair and bremsstrahlung
+# coefficients raised with Z; Rayleigh F(0) = Z of the unit.
+BONE = dict(
+    z_mol=50.0, a_mol=96.2, zz1_mol=740.0, z_screen=13.8, i_exc=106.4e-6,
+    pe_coef=28.5, pe_eref=0.01, pe_exp=3.0,
+    pp_coef=1.9e-3,
+    ray_f0=50.0, ray_a=4.6,
+    brems_b=0.028,
+)
+
 
 def transport(e_max: float = 10.0, n_grid: int = 200, flags: int = 0, **kw) -> dict:
     t = dict(n_grid=n_grid, e_min=1.0e-3, e_max=e_max, eabs=(0.01, 0.1, 0.1),
@@ -100,6 +112,14 @@ def hetero_phantom(n: int, size: float = 25.6, seed: int = 2) -> dict:
         inside = (xx - cx) ** 2 + (yy - cy) ** 2 + (zz - cz) ** 2 <= r * r
         rho[inside] = 1.85
     return dict(shape=(n, n, n), voxel=(d, d, d), origin=(0.0, 0.0, 0.0), rho=rho)
+
+
+def hetero_mm_phantom(n: int, size: float = 25.6, seed: int = 2) -> dict:
+    """The heterogeneous phantom with materials: water (0) for the
+    background and the lung slab, bone (1) for the spheres."""
+    ph = hetero_phantom(n, size, seed)
+    ph["mat"] = (ph["rho"] == 1.85).astype(np.uint8)
+    return ph
 
 
 def ct_noise_phantom(n: int = 256, d: float = 0.2, seed: int = 3, sigma: float = 4.0) -> dict:
@@ -181,4 +201,10 @@ def workload(name: str, n_hist: int | None = None) -> dict:
         return dict(name=name, phantom=hetero_phantom(64),
                     sources=[rect_field(0, 6.0, (12.8, 12.8, 0.0), (10.0, 10.0), n)],
                     transport=transport(10.0, 200), seed=1, material=WATER)
+    if name in ("hetero_mm_64", "hetero_mm_128"):
+        nn = 64 if name.endswith("64") else 128
+        n = n_hist or 10_000_000
+        return dict(name=name, phantom=hetero_mm_phantom(nn),
+                    sources=[rect_field(0, 6.0, (12.8, 12.8, 0.0), (10.0, 10.0), n)],
+                    transport=transport(10.0, 200), seed=1, material=WATER, materials=[WATER, BONE])
     raise KeyError(name)
