@@ -122,13 +122,18 @@ typedef struct {
 /* Voxel phantom.  nx, ny, nz <= 1024; voxel sizes > 0; rho > 0 everywhere
  * (MCX_E_INVALID otherwise).  rho is FP64, x-fastest; if rho_on_device is
  * nonzero it is a device pointer that is copied on the device (the caller
- * may free it after the call returns). */
+ * may free it after the call returns).  mat (host memory, same layout, may be
+ * NULL) gives each voxel a material index < 4 of mcx_load_material: with it
+ * the transport runs the several-material kernels (photon flights in
+ * optical depth, each interaction and step by its voxel's tables), which
+ * need every material up to the largest index loaded before mcx_run. */
 typedef struct {
   int nx, ny, nz;
   double voxel_cm[3];
   double origin_cm[3];
   const double* rho;
   int rho_on_device;
+  const uint8_t* mat;
 } mcx_phantom_desc;
 
 /* One source (a beamlet).  Histories are numbered by concatenating the
@@ -181,8 +186,10 @@ const char* mcx_last_error(mcx_ctx* ctx);
 
 /* Transport parameters; must precede mcx_load_material.  Copied. */
 int mcx_set_transport(mcx_ctx* ctx, const mcx_transport* t);
-/* Tabulate the material on the transport grid and copy the tables to the
- * device.  Only mat_id 0 is supported (MCX_E_UNSUPPORTED otherwise). */
+/* Tabulate material mat_id (0..3) on the transport grid and copy the tables
+ * to the device.  Material 0 serves every voxel of a phantom without a
+ * material array; the others are selected per voxel by the phantom's
+ * material array.  mcx_set_transport discards every loaded material. */
 int mcx_load_material(mcx_ctx* ctx, int mat_id, const mcx_material_desc* m);
 /* Copy the phantom densities to the device (converted to FP32 in MIXED
  * precision).  Resets the tallies. */

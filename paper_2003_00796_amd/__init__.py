@@ -52,7 +52,8 @@ class Transport(C.Structure):
 
 class PhantomDesc(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("voxel_cm", C.c_double * 3),
-                ("origin_cm", C.c_double * 3), ("rho", C.c_void_p), ("rho_on_device", C.c_int)]
+                ("origin_cm", C.c_double * 3), ("rho", C.c_void_p), ("rho_on_device", C.c_int),
+                ("mat", C.c_void_p)]
 
 
 class Source(C.Structure):
@@ -216,6 +217,11 @@ class Simulator:
             keep = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
             d.rho = C.c_void_p(keep.ctypes.data)
             d.rho_on_device = 0
+        mat = ph.get("mat")
+        if mat is not None:
+            mkeep = np.ascontiguousarray(np.asarray(mat, dtype=np.uint8))
+            assert mkeep.size == nx * ny * nz
+            d.mat = C.c_void_p(mkeep.ctypes.data)
         self._check(self._L.mcx_load_phantom(self._h, C.byref(d)), "load_phantom")
         self.shape = (nz, ny, nx)
 
@@ -256,7 +262,8 @@ class Simulator:
     def setup(self, workload: dict):
         """material + transport + phantom + sources from a workload dict."""
         self.set_transport(workload["transport"])
-        self.load_material(workload["material"])
+        for k, m in enumerate(workload.get("materials") or [workload["material"]]):
+            self.load_material(m, k)
         self.load_phantom(workload["phantom"])
         self.set_sources(workload["sources"])
         return self

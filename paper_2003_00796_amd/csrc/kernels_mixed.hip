@@ -24,11 +24,13 @@ static hipError_t launch_flavor(const KArgs<float>& a, int par, uint32_t target,
   constexpr int B = base_flavor(F);  // the extended physics changes the e+- step only
   hipLaunchKernelGGL((k_source<float, B>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL((k_flight<float, B>), dim3(grid), dim3(block), sm_f, s, a, par);
+  constexpr int PF = photon_flavor(F);
+  hipLaunchKernelGGL((k_flight<float, PF>), dim3(grid), dim3(block), several(F) ? sm_f * size_t(a.tb.nmat) : sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL((k_knock<float, B>), dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_knock<float, PF>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL((k_estep<float, F>), dim3(grid), dim3(block), sm_e, s, a, par);
+  hipLaunchKernelGGL((k_estep<float, F>), dim3(grid), dim3(block), several(F) ? size_t(kSoftN) * sizeof(float) : sm_e, s,
+                     a, par);
   if (ev) (void)hipEventRecord(ev[4], s);
   hipLaunchKernelGGL(k_advance<float>, dim3(1), dim3(64), 0, s, a.cnt, par, target, a.cap);
   return hipGetLastError();
@@ -39,6 +41,9 @@ hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int
   // replays never write the test outputs
   if (a.mode == 1) return launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev);
   if (a.mode == 2) return launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev);
+  if (a.mm)
+    return a.test_mode ? launch_flavor<FL_MM_TEST>(a, par, target, grid, block, s, ev)
+                       : launch_flavor<FL_MM>(a, par, target, grid, block, s, ev);
   if (a.straggle || a.annih)
     return a.test_mode ? launch_flavor<FL_EXT_TEST>(a, par, target, grid, block, s, ev)
                        : launch_flavor<FL_EXT>(a, par, target, grid, block, s, ev);
@@ -66,7 +71,9 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
                              reinterpret_cast<const void*>(&k_estep<float, FL_ADJ_A>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_ADJ_B>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_EXT>),
-                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_TEST>)};
+                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_TEST>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MM>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MM_TEST>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -74,11 +81,12 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
   return hipSuccess;
 }
 
-hipError_t launch_cube_map(const float* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s) {
+hipError_t launch_cube_map(const float* rho, const uint8_t* mat, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp,
+                           hipStream_t s) {
   const uint64_t nv = uint64_t(nx) * ny * nz;
   const unsigned g = unsigned(std::min<uint64_t>((nv + 255) / 256, 65536));
   // seed, then the x, y and z passes: tmp -> out -> tmp -> out
-  hipLaunchKernelGGL(k_cube_seed<float>, dim3(g), dim3(256), 0, s, rho, nx, ny, nz, tmp);
+  hipLaunchKernelGGL(k_cube_seed<float>, dim3(g), dim3(256), 0, s, rho, mat, nx, ny, nz, tmp);
   hipLaunchKernelGGL(k_cube_pass<float>, dim3(g), dim3(256), 0, s, tmp, out, nx, ny, nz, 0);
   hipLaunchKernelGGL(k_cube_pass<float>, dim3(g), dim3(256), 0, s, out, tmp, nx, ny, nz, 1);
   hipLaunchKernelGGL(k_cube_pass<float>, dim3(g), dim3(256), 0, s, tmp, out, nx, ny, nz, 2);

@@ -45,8 +45,11 @@ hipError_t launch_influence_compact(const uint64_t* ikeys, const double* iq, con
                                     uint32_t* osrc, uint32_t* ovox, double* oq, double* oq2, uint64_t cap,
                                     unsigned long long* count, hipStream_t s);
 // same-density cube half-widths of every voxel into `out` (tmp: nvox bytes)
-hipError_t launch_cube_map(const double* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s);
-hipError_t launch_cube_map(const float* rho, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp, hipStream_t s);
+// (mat, when not null: a cube also has one material throughout)
+hipError_t launch_cube_map(const double* rho, const uint8_t* mat, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp,
+                           hipStream_t s);
+hipError_t launch_cube_map(const float* rho, const uint8_t* mat, int nx, int ny, int nz, uint8_t* out, uint8_t* tmp,
+                           hipStream_t s);
 // LDS bytes the e+- kernel stages for a grid of n nodes
 size_t estep_lds_bytes(int n, bool fp64);
 hipError_t configure_kernels(int n_grid, bool fp64);

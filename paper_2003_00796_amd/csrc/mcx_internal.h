@@ -25,6 +25,8 @@ constexpr double kHc = 1.23984198e-2;        // MeV Angstrom
 constexpr double kPi = 3.14159265358979323846;
 
 constexpr int kMaxGrid = 512;
+// materials per phantom (per-voxel index, one table block each)
+constexpr int kMaxMat = 4;
 constexpr int kMaxBlock = 256;  // kernels are compiled for blocks of at most 256 threads
 constexpr uint64_t kEmptyKey = ~0ull;
 
@@ -138,6 +140,15 @@ struct SourceDev {
   uint64_t end;  // exclusive end of this source's history ids
 };
 
+// constants of one material that the kernels need besides its tables
+template <typename T>
+struct MatConst {
+  T k_coef, eta_a, eta_b;  // screened Rutherford elastic (see Tab)
+  T ray_a;                 // Rayleigh form factor
+  T strag_k, strag_b;      // straggling (see Tab)
+  T annih_k;               // annihilation in flight (see Tab)
+};
+
 template <typename T>
 struct Tab {
   const T* t;        // channel-major block, T_NCH * n
@@ -158,7 +169,17 @@ struct Tab {
   T wcc_soft, wcr_soft;
   // two-photon annihilation in flight: pi r_e^2 n_e, cm^2/g
   T annih_k;
+  // several materials: their number, their constants, and the offset of
+  // material m's channel block in t (material 0 at 0, the soft-law table
+  // after it, then materials 1, 2, ...)
+  int nmat;
+  MatConst<T> mc[kMaxMat];
 };
+
+// offset of material m's T_NCH x n channel block in the table block
+constexpr uint32_t mat_block(int m, int n) {
+  return m == 0 ? 0u : uint32_t(T_NCH * n + kSoftN + (m - 1) * T_NCH * n);
+}
 
 template <typename T>
 struct KArgs {
@@ -171,6 +192,8 @@ struct KArgs {
   // per voxel: half-width (in voxels) of the largest cube around it that lies
   // in the phantom and has its density throughout
   const uint8_t* cube;
+  // per-voxel material index (several-material phantoms), else null
+  const uint8_t* mat;
   // transport
   T eabs[3];
   T c2, wcc, wcr;
@@ -194,6 +217,7 @@ struct KArgs {
   int mode;
   int straggle;          // soft energy-loss straggling on (selects the kernel flavour)
   int annih;             // positron annihilation in flight on (selects the kernel flavour)
+  int mm;                // several materials (selects the kernel flavour)
   const double* adj_w;   // per voxel: dL/dD_v * 1e6 / (rho_v V)
   double* adj_q;         // per history of the run: Q_h
   double* adj_grad;      // per voxel accumulator

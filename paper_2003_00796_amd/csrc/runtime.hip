@@ -56,6 +56,11 @@ struct mcx_ctx {
   double vox[3] = {0, 0, 0}, org[3] = {0, 0, 0};
   DevBuf d_rho;
   DevBuf d_cube;  // same-density cube half-widths, one byte per voxel
+  // several materials: tables per material, and the per-voxel index
+  BuiltTables mtabs[kMaxMat];
+  bool have_mat[kMaxMat] = {false, false, false, false};
+  DevBuf d_vmat;
+  int vmat_max = -1;  // largest material index of the phantom (-1: no material array)
   // sources
   std::vector<SourceDev> src;
   DevBuf d_src;
@@ -287,6 +292,20 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.tb.wcc_soft = T(b.wcc_soft);
   a.tb.wcr_soft = T(b.wcr_soft);
   a.tb.annih_k = T(b.annih_k);
+  a.tb.nmat = 1;
+  for (int k = 0; k < kMaxMat; ++k) {
+    const BuiltTables& bk = c->have_mat[k] ? c->mtabs[k] : b;
+    if (c->have_mat[k]) a.tb.nmat = std::max(a.tb.nmat, k + 1);
+    MatConst<T>& mc = a.tb.mc[k];
+    mc.k_coef = T(bk.k_coef);
+    mc.eta_a = T(bk.eta_a);
+    mc.eta_b = T(bk.eta_b);
+    mc.ray_a = T(bk.ray_a);
+    mc.strag_k = T(bk.strag_k);
+    mc.strag_b = T(bk.strag_b);
+    mc.annih_k = T(bk.annih_k);
+  }
+  a.mat = static_cast<const uint8_t*>(c->d_vmat.p);
   a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
   a.dx = c->vox[0]; a.dy = c->vox[1]; a.dz = c->vox[2];
   a.ox = c->org[0]; a.oy = c->org[1]; a.oz = c->org[2];
@@ -315,6 +334,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.mode = mode;
   a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
   a.annih = (mode == 0 && (c->tr.flags & MCX_ANNIH_FLIGHT)) ? 1 : 0;
+  a.mm = (mode == 0 && c->d_vmat.p) ? 1 : 0;
   if (mode) {
     a.test_mode = 0;
     a.adj_w = static_cast<const double*>(c->d_adj_w.p);
@@ -534,7 +554,8 @@ void mcx_destroy(mcx_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_cube, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
-                    &c->d_hvals, &c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf, &c->d_adj_w, &c->d_adj_q, &c->d_adj_grad,
+                    &c->d_hvals, &c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf, &c->d_vmat, &c->d_adj_w, &c->d_adj_q,
+                    &c->d_adj_grad,
                     &c->d_adj_dl, &c->d_adj_out,
                     &c->d_adj_sum, &c->d_hhash, &c->d_hled})
     dfree(*b);
@@ -558,13 +579,14 @@ int mcx_set_transport(mcx_ctx* c, const mcx_transport* t) {
   c->tr = *t;
   c->have_transport = true;
   c->have_material = false;
+  for (bool& h : c->have_mat) h = false;
   return MCX_OK;
 }
 
 int mcx_load_material(mcx_ctx* c, int mat_id, const mcx_material_desc* m) {
   if (!c) return MCX_E_INVALID;
   if (!m) return fail(c, MCX_E_INVALID, "null material");
-  if (mat_id != 0) return fail(c, MCX_E_UNSUPPORTED, "only material 0 is supported");
+  if (mat_id < 0 || mat_id >= kMaxMat) return fail(c, MCX_E_UNSUPPORTED, "material ids are 0..%d", kMaxMat - 1);
   if (!c->have_transport) return fail(c, MCX_E_STATE, "set the transport parameters first");
   const double pos[] = {m->z_mol, m->a_mol, m->zz1_mol, m->z_screen, m->i_exc, m->pe_eref, m->ray_a};
   for (double v : pos)
@@ -575,22 +597,39 @@ int mcx_load_material(mcx_ctx* c, int mat_id, const mcx_material_desc* m) {
   BuiltTables b;
   if (!build_tables(*m, c->tr, &b, &err)) return fail(c, MCX_E_INVALID, "%s", err.c_str());
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  c->mtabs[mat_id] = std::move(b);
+  c->have_mat[mat_id] = true;
+  if (mat_id == 0) {
+    c->tabs = c->mtabs[0];
+    c->mat = *m;
+    c->have_material = true;
+  }
+  if (!c->have_material) return MCX_OK;  // uploaded once material 0 is there
+  // device block: material 0's channels, the soft-law table, then the
+  // channels of materials 1, 2, ... (missing ones hold material 0's)
+  const int n = c->tabs.n;
+  const size_t ch = size_t(T_NCH) * n;
+  int nm = 1;
+  for (int k = 1; k < kMaxMat; ++k)
+    if (c->have_mat[k]) nm = k + 1;
+  std::vector<double> blk(c->tabs.block.begin(), c->tabs.block.end());
+  for (int k = 1; k < nm; ++k) {
+    const BuiltTables& bk = c->have_mat[k] ? c->mtabs[k] : c->tabs;
+    blk.insert(blk.end(), bk.block.begin(), bk.block.begin() + ch);
+  }
   int rc;
-  const size_t bytes = b.block.size() * tsize(c);  // channels + soft-law guesses
+  const size_t bytes = blk.size() * tsize(c);
   if ((rc = dalloc(c, c->d_tab, bytes, "tables"))) return rc;
   hipError_t e;
   if (fp64(c)) {
-    e = hipMemcpy(c->d_tab.p, b.block.data(), bytes, hipMemcpyHostToDevice);
+    e = hipMemcpy(c->d_tab.p, blk.data(), bytes, hipMemcpyHostToDevice);
   } else {
-    std::vector<float> f(b.block.begin(), b.block.end());
+    std::vector<float> f(blk.begin(), blk.end());
     e = hipMemcpy(c->d_tab.p, f.data(), bytes, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(c, e, "copy tables");
-  e = configure_kernels(b.n, fp64(c));
+  e = configure_kernels(n, fp64(c));
   if (e != hipSuccess) return hip_fail(c, e, "configure kernels");
-  c->tabs = std::move(b);
-  c->mat = *m;
-  c->have_material = true;
   return MCX_OK;
 }
 
@@ -645,15 +684,31 @@ int mcx_load_phantom(mcx_ctx* c, const mcx_phantom_desc* p) {
     e = hipMemcpy(c->d_rho.p, f.data(), nv * sizeof(float), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(c, e, "copy densities");
-  // same-density cubes for the photon walk (a scratch byte per voxel while
-  // the map is built)
+  // per-voxel materials (several-material kernels), else none
+  c->vmat_max = -1;
+  dfree(c->d_vmat);
+  if (p->mat) {
+    int mx = 0;
+    for (uint64_t v = 0; v < nv; ++v) {
+      if (p->mat[v] >= kMaxMat) return fail(c, MCX_E_INVALID, "material index %d >= %d (voxel %llu)", int(p->mat[v]),
+                                            kMaxMat, (unsigned long long)v);
+      mx = std::max(mx, int(p->mat[v]));
+    }
+    if ((rc = dalloc(c, c->d_vmat, nv, "voxel materials"))) return rc;
+    e = hipMemcpy(c->d_vmat.p, p->mat, nv, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "copy voxel materials");
+    c->vmat_max = mx;
+  }
+  // same-density (and same-material) cubes for the photon walk (a scratch
+  // byte per voxel while the map is built)
   if ((rc = dalloc(c, c->d_cube, nv, "same-density cube map"))) return rc;
   {
     DevBuf tmp;
     if ((rc = dalloc(c, tmp, nv, "cube map scratch"))) return rc;
-    e = fp64(c) ? launch_cube_map(static_cast<const double*>(c->d_rho.p), p->nx, p->ny, p->nz,
+    const uint8_t* vm = static_cast<const uint8_t*>(c->d_vmat.p);
+    e = fp64(c) ? launch_cube_map(static_cast<const double*>(c->d_rho.p), vm, p->nx, p->ny, p->nz,
                                   static_cast<uint8_t*>(c->d_cube.p), static_cast<uint8_t*>(tmp.p), c->stream)
-                : launch_cube_map(static_cast<const float*>(c->d_rho.p), p->nx, p->ny, p->nz,
+                : launch_cube_map(static_cast<const float*>(c->d_rho.p), vm, p->nx, p->ny, p->nz,
                                   static_cast<uint8_t*>(c->d_cube.p), static_cast<uint8_t*>(tmp.p), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     dfree(tmp);
@@ -875,6 +930,8 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
   if (!c->have_sources || !c->have_material || !c->have_phantom)
     return fail(c, MCX_E_STATE, "set transport, material, phantom and sources first");
   if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
+  for (int k = 0; k <= c->vmat_max; ++k)
+    if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
   if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
@@ -917,8 +974,9 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
-  if (c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT))
-    return fail(c, MCX_E_UNSUPPORTED, "the gradient replays run the main step only (no straggling, no annihilation in flight)");
+  if ((c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT)) || c->d_vmat.p)
+    return fail(c, MCX_E_UNSUPPORTED,
+                "the gradient replays run the main path only (one material, no straggling, no annihilation in flight)");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

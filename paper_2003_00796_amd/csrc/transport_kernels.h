@@ -42,14 +42,28 @@ enum Flavor : int {
   FL_ADJ_B = 3,       // second replay (likelihood-ratio scores of photon flights)
   FL_EXT = 4,         // forward transport with the optional physics: soft energy-loss
                       // straggling, positron annihilation in flight (run-time switches)
-  FL_EXT_TEST = 5     // the same with the per-history test outputs
+  FL_EXT_TEST = 5,    // the same with the per-history test outputs
+  FL_MM = 6,          // several materials (per-voxel index), with the optional physics
+  FL_MM_TEST = 7      // the same with the per-history test outputs
 };
-constexpr int kFlavors = 6;
+constexpr int kFlavors = 8;
 
 // the optional physics changes the e+- step only: the other kernels of an
-// extended flavour are those of the flavour without it
-constexpr int base_flavor(int f) { return f == FL_EXT ? FL_FWD : (f == FL_EXT_TEST ? FL_TEST : f); }
-constexpr bool extended(int f) { return f == FL_EXT || f == FL_EXT_TEST; }
+// extended flavour are those of the flavour without it; several materials
+// change the photon flight and interactions too
+constexpr int base_flavor(int f) {
+  return (f == FL_EXT || f == FL_MM) ? FL_FWD : ((f == FL_EXT_TEST || f == FL_MM_TEST) ? FL_TEST : f);
+}
+constexpr bool extended(int f) { return f >= FL_EXT; }
+constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST; }
+constexpr int photon_flavor(int f) { return several(f) ? f : base_flavor(f); }
+
+// constants of material m (selects over the kMaxMat entries: no indexing of
+// the argument block by a run-time value)
+template <typename T>
+__device__ __forceinline__ MatConst<T> mat_const(const Tab<T>& tb, uint32_t m) {
+  return m == 0u ? tb.mc[0] : (m == 1u ? tb.mc[1] : (m == 2u ? tb.mc[2] : tb.mc[3]));
+}
 
 template <int F, typename T>
 __device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
@@ -198,7 +212,7 @@ static_assert(kCubeMax >= 1 && kCubeMax <= 255, "cube half-width must fit a byte
 constexpr uint32_t kCubeMin = MCX_CUBE_MIN;
 
 template <typename T>
-__global__ void k_cube_seed(const T* rho, int nx, int ny, int nz, uint8_t* out) {
+__global__ void k_cube_seed(const T* rho, const uint8_t* mat, int nx, int ny, int nz, uint8_t* out) {
   const uint64_t nv = uint64_t(nx) * ny * nz;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nv; v += stride) {
@@ -208,7 +222,8 @@ __global__ void k_cube_seed(const T* rho, int nx, int ny, int nz, uint8_t* out) 
     for (int dz = -1; dz <= 1 && !edge; ++dz)
       for (int dy = -1; dy <= 1 && !edge; ++dy)
         for (int dx = -1; dx <= 1 && !edge; ++dx)
-          edge = rho[(uint64_t(z + dz) * ny + uint64_t(y + dy)) * nx + uint64_t(x + dx)] != r0;
+          edge = rho[(uint64_t(z + dz) * ny + uint64_t(y + dy)) * nx + uint64_t(x + dx)] != r0 ||
+                 (mat && mat[(uint64_t(z + dz) * ny + uint64_t(y + dy)) * nx + uint64_t(x + dx)] != mat[v]);
     out[v] = edge ? uint8_t(0) : uint8_t(kCubeMax);
   }
 }
@@ -247,9 +262,19 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
   __shared__ BlockStats bs;
   LaneStats ls;
   stats_init(&bs, ls);
-  stage(a.tb, tab, T_PHOTON_END);
-  __syncthreads();
+  constexpr bool MMF = several(F);
   const int nt = a.tb.n;
+  if constexpr (MMF) {
+    // the photon channels of every material, T_PHOTON_END x n each
+    const int per = T_PHOTON_END * nt;
+    for (int k = threadIdx.x; k < per * a.tb.nmat; k += blockDim.x) {
+      const int m = k / per;
+      tab[k] = a.tb.t[mat_block(m, nt) + uint32_t(k - m * per)];
+    }
+  } else {
+    stage(a.tb, tab, T_PHOTON_END);
+  }
+  __syncthreads();
   const Bank<T>& in = a.q[q_gin(par)];
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -261,13 +286,37 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
       const T e = p.e;
       const Grid<T> g = grid_at(a.tb, M<T>::log(e));
       T mu[4];
-      mu[0] = interp(tab, nt, T_LMU_C, g, e, T(0));
-      mu[1] = interp(tab, nt, T_LMU_PE, g, e, T(0));
-      mu[2] = interp(tab, nt, T_LMU_R, g, e, T(0));
-      mu[3] = interp(tab, nt, T_LMU_PP, g, e, a.tb.thr_pp);
-      const T mt = mu[0] + mu[1] + mu[2] + mu[3];
+      T mt = T(0);
+      // several materials: the attenuation rho mu_m(E) of each voxel's
+      // material; the flight is measured in optical depth
+      T mtm[kMaxMat];
+      if constexpr (MMF) {
+#pragma unroll
+        for (int m = 0; m < kMaxMat; ++m) {
+          const T* tm = tab + m * T_PHOTON_END * nt;
+          mtm[m] = m < a.tb.nmat ? interp(tm, nt, T_LMU_C, g, e, T(0)) + interp(tm, nt, T_LMU_PE, g, e, T(0)) +
+                                       interp(tm, nt, T_LMU_R, g, e, T(0)) +
+                                       interp(tm, nt, T_LMU_PP, g, e, a.tb.thr_pp)
+                                 : T(0);
+        }
+      } else {
+        mu[0] = interp(tab, nt, T_LMU_C, g, e, T(0));
+        mu[1] = interp(tab, nt, T_LMU_PE, g, e, T(0));
+        mu[2] = interp(tab, nt, T_LMU_R, g, e, T(0));
+        mu[3] = interp(tab, nt, T_LMU_PP, g, e, a.tb.thr_pp);
+        mt = mu[0] + mu[1] + mu[2] + mu[3];
+      }
+      auto att = [&](uint32_t vv) -> double {
+        if constexpr (MMF) {
+          const uint32_t m = a.mat[vv];
+          const T mm = m == 0u ? mtm[0] : (m == 1u ? mtm[1] : (m == 2u ? mtm[2] : mtm[3]));
+          return double(a.rho[vv]) * double(mm);
+        } else {
+          return double(a.rho[vv]);
+        }
+      };
       ls.flights++;
-      double tau = double(-M<T>::log(uni<T>(p.rng)) / mt);
+      double tau = MMF ? double(-M<T>::log(uni<T>(p.rng))) : double(-M<T>::log(uni<T>(p.rng)) / mt);
       // incremental DDA: tn[k] = distance along the ray to the next face
       // normal to axis k, advanced by the voxel pitch over |d_k| per crossing
       const double o[3] = {a.ox, a.oy, a.oz};
@@ -305,7 +354,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
       // faces per unit length along each axis (|d_k| / pitch), for counting
       // the faces a cube crossing passes
       const double it[3] = {fabs(double(p.d[0])) * a.idx, fabs(double(p.d[1])) * a.idy, fabs(double(p.d[2])) * a.idz};
-      double rho_v = double(a.rho[v]);
+      double rho_v = att(v);
       uint32_t cube_v = a.cube[v];
       // replay B: the history's centred weighted score times d ln p / d rho_j
       // of this free flight (-mu l_j per voxel, +1/rho at the interaction)
@@ -407,9 +456,9 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
         }
         double rr[kWalk];
 #pragma unroll
-        for (int j = 0; j < kWalk; ++j) rr[j] = double(a.rho[vs[j]]);
+        for (int j = 0; j < kWalk; ++j) rr[j] = att(vs[j]);
         // the voxel after the last segment: where the next pass starts
-        const double rho_n = double(a.rho[vs[kWalk]]);
+        const double rho_n = att(vs[kWalk]);
         const uint32_t cube_n = a.cube[vs[kWalk]];
 #pragma unroll
         for (int j = 0; j < kWalk; ++j) {
@@ -444,6 +493,15 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
       }
       move(p, t);
       if (!escaped) {
+        if constexpr (MMF) {
+          // the interaction by the tables of the voxel the photon stops in
+          const T* tm = tab + int(a.mat[v]) * T_PHOTON_END * nt;
+          mu[0] = interp(tm, nt, T_LMU_C, g, e, T(0));
+          mu[1] = interp(tm, nt, T_LMU_PE, g, e, T(0));
+          mu[2] = interp(tm, nt, T_LMU_R, g, e, T(0));
+          mu[3] = interp(tm, nt, T_LMU_PP, g, e, a.tb.thr_pp);
+          mt = mu[0] + mu[1] + mu[2] + mu[3];
+        }
         const T u = uni<T>(p.rng) * mt;
         T cum = T(0);
 #pragma unroll
@@ -582,7 +640,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
         event(a, p, EV_PHOTO, v);
       } else if (q == 2) {
         stat_add(&bs, S_RAYLEIGH);
-        const T ct = sample_rayleigh(p.rng, p.e, a.tb.ray_a);
+        const T ct = sample_rayleigh(p.rng, p.e, several(F) ? mat_const(a.tb, a.mat[v]).ray_a : a.tb.ray_a);
         const T phi = T(2.0 * kPi) * uni<T>(p.rng);
         rotate(p.d, ct, phi);
         keep = true;
@@ -719,9 +777,8 @@ __device__ __forceinline__ T sigma_annih(const Tab<T>& tb, T e) {
 // in the optional physics (straggling, annihilation in flight), each behind
 // its run-time switch.
 template <typename T, bool EXT>
-__device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1, Child<T>& c2, DepAcc& acc,
-                       LaneStats& ls, BlockStats* bs) {
-  const Tab<T>& tb = a.tb;
+__device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const T* soft, Part<T>& p, Child<T>& c1,
+                       Child<T>& c2, DepAcc& acc, LaneStats& ls, BlockStats* bs) {
   const int nt = tb.n;
   const int lep = p.type == POSITRON ? 1 : 0;
   const int base = T_E + lep * T_ES;
@@ -807,7 +864,7 @@ __device__ bool e_step(const KArgs<T>& a, const T* tab, Part<T>& p, Child<T>& c1
   }
   const T t1s = interp(tab, nt, base + O_LT1S, g, e, T(0));
   const T mbar = T(0.5) * (T(1) - M<T>::exp(-T(double(rho) * len) * t1s));
-  const T A = soft_a(mbar, tab + T_NCH * nt);
+  const T A = soft_a(mbar, soft);
   const T u3 = uni<T>(p.rng);
   const T mu = A * u3 / (T(1) + A - u3);
   const T phi = T(2.0 * kPi) * uni<T>(p.rng);
@@ -980,7 +1037,15 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
   __shared__ BlockStats bs;
   LaneStats ls;
   stats_init(&bs, ls);
-  stage(a.tb, tab, T_NCH, kSoftN);
+  constexpr bool MMF = several(F);
+  const int ntab = a.tb.n;
+  if constexpr (MMF) {
+    // several materials: the soft-law table (after material 0's block) in
+    // LDS; each step reads its material's channels from the table block
+    for (int k = threadIdx.x; k < kSoftN; k += blockDim.x) tab[k] = a.tb.t[T_NCH * ntab + k];
+  } else {
+    stage(a.tb, tab, T_NCH, kSoftN);
+  }
   __syncthreads();
   const Bank<T>& in = a.q[q_ein(par)];
   const int ge = q_eout(par), gg = q_gout(par);
@@ -1027,7 +1092,21 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     c1.on = false;
     c2.on = false;
     if (alive) {
-      alive = e_step<T, extended(F)>(a, tab, p, c1, c2, acc, ls, &bs);
+      if constexpr (MMF) {
+        // the step stays in its voxel, so in one material
+        const uint32_t m = a.mat[vlin(a, p.ix)];
+        const MatConst<T> mc = mat_const(a.tb, m);
+        Tab<T> tbm = a.tb;
+        tbm.k_coef = mc.k_coef;
+        tbm.eta_a = mc.eta_a;
+        tbm.eta_b = mc.eta_b;
+        tbm.strag_k = mc.strag_k;
+        tbm.strag_b = mc.strag_b;
+        tbm.annih_k = mc.annih_k;
+        alive = e_step<T, true>(a, tbm, a.tb.t + mat_block(int(m), ntab), tab, p, c1, c2, acc, ls, &bs);
+      } else {
+        alive = e_step<T, extended(F)>(a, a.tb, tab, tab + T_NCH * ntab, p, c1, c2, acc, ls, &bs);
+      }
       ++used;
     }
     dep_flush_pending(a, acc, ls);
