@@ -247,6 +247,8 @@ def main():
     ap.add_argument("--electron", action="store_true", help="also time the 20 MeV electron workload")
     ap.add_argument("--straggling", action="store_true",
                     help="also time the mixed step with soft energy-loss straggling on")
+    ap.add_argument("--materials", action="store_true",
+                    help="also time the mixed step on the same phantom with bone spheres of a second material")
     ap.add_argument("--annih-flight", action="store_true",
                     help="also time the mixed step with positron annihilation in flight on")
     ap.add_argument("--no-fp64", action="store_true")
@@ -356,6 +358,20 @@ def main():
                                  esteps_per_history=st_sg["esteps"] / n, annihilations_per_history=st_sg["annih"] / n,
                                  dose_vs_main=dict(high_dose_deviation(d_sg, d_mix), z_rms=float(np.sqrt(np.mean(z ** 2))),
                                                    z_mean=float(np.mean(z))))
+    if args.materials:
+        wm = W.workload("hetero_mm_128", n)
+        sm = mcx.Simulator(mcx.MIXED, 0).setup(wm)
+        sm.set_launch(args.bank, 256, 128)
+        run_steps(sm, n, warm_seeds, sync)
+        t_mm = run_steps(sm, n, seeds, sync)
+        d_mm, _ = sm.dose()
+        st_mm = sm.stats()
+        sm.close()
+        out["several_materials"] = dict(workload="hetero_mm_128: the same field and phantom, bone spheres of a second "
+                                                 "material (synthetic cortical bone)",
+                                        value=n * len(t_mm) / sum(t_mm), ms_per_step=1e3 * sum(t_mm) / len(t_mm),
+                                        esteps_per_history=st_mm["esteps"] / n,
+                                        summed_dose_ratio_to_one_material=float(d_mm.sum() / d_mix.sum()))
     if not args.no_gradient:
         out["gradient"] = gradient_timing(mcx, W, sync)
     if args.beamlets:

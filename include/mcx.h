@@ -265,6 +265,24 @@ int mcx_reset_tallies(mcx_ctx* ctx);
 /* Statistics since the last reset. */
 int mcx_get_stats(mcx_ctx* ctx, mcx_stats* out);
 
+/* CT calibration, the role of the DICOM import of a transport code without
+ * its file I/O: Hounsfield units to mass density by the piecewise-linear
+ * curve through (hu[i], rho[i]), i < n_points (hu strictly increasing, rho
+ * > 0; constant beyond the end points), and to a material index by
+ * thresholds: a voxel takes material k, the number of thresholds mat_hu[j]
+ * (strictly increasing, at most 3) at or below its HU. */
+typedef struct {
+  int n_points;
+  const double* hu;
+  const double* rho;
+  int n_thresholds;
+  const double* mat_hu;
+} mcx_ct_calibration;
+/* Convert nvox HU values (host arrays) into densities (g/cm^3) and material
+ * indices (mat may be NULL) for mcx_phantom_desc.  Host code only: needs no
+ * context and no device.  MCX_E_INVALID for a malformed calibration. */
+int mcx_ct_to_phantom(const mcx_ct_calibration* cal, const int16_t* hu, uint64_t nvox, double* rho, uint8_t* mat);
+
 /* Per-source dose influence (one source = one beamlet): with on != 0, every
  * later run also accumulates, per (source, voxel) pair that received
  * energy, the per-history scores q of that source's histories: Sum q and

@@ -35,7 +35,7 @@ ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
                "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune",
                "mcx_synchronize", "mcx_cancel", "mcx_checkpoint", "mcx_restore", "mcx_workspace_size",
-               "mcx_set_workspace", "mcx_set_influence", "mcx_get_influence")
+               "mcx_set_workspace", "mcx_set_influence", "mcx_get_influence", "mcx_ct_to_phantom")
 
 
 class MaterialDesc(C.Structure):
@@ -60,6 +60,30 @@ class Source(C.Structure):
     _fields_ = [("particle", C.c_int), ("kind", C.c_int), ("energy", C.c_double),
                 ("pos", C.c_double * 3), ("dir", C.c_double * 3), ("width", C.c_double * 2),
                 ("n_hist", C.c_uint64)]
+
+
+class CTCalibration(C.Structure):
+    _fields_ = [("n_points", C.c_int), ("hu", C.c_void_p), ("rho", C.c_void_p), ("n_thresholds", C.c_int),
+                ("mat_hu", C.c_void_p)]
+
+
+def ct_to_phantom(hu, hu_points, rho_points, mat_thresholds=()):
+    """(rho, mat) arrays of the shape of `hu` from a CT calibration:
+    piecewise-linear HU -> density through (hu_points, rho_points), and the
+    material index = number of thresholds at or below each HU (host code,
+    mcx_ct_to_phantom)."""
+    h = np.ascontiguousarray(hu, dtype=np.int16)
+    xp = np.ascontiguousarray(hu_points, dtype=np.float64)
+    fp = np.ascontiguousarray(rho_points, dtype=np.float64)
+    th = np.ascontiguousarray(mat_thresholds, dtype=np.float64)
+    cal = CTCalibration(n_points=len(xp), hu=xp.ctypes.data, rho=fp.ctypes.data, n_thresholds=len(th),
+                        mat_hu=th.ctypes.data if len(th) else None)
+    rho = np.zeros(h.shape)
+    mat = np.zeros(h.shape, dtype=np.uint8)
+    rc = lib().mcx_ct_to_phantom(C.byref(cal), h.ctypes.data, h.size, rho.ctypes.data, mat.ctypes.data)
+    if rc != 0:
+        raise MCXError(f"mcx_ct_to_phantom: {ERRORS.get(rc, rc)}")
+    return rho, mat
 
 
 _STATS_U64_A = ("histories", "flights", "compton", "photo", "rayleigh", "pair", "esteps", "hard_el", "hard_in",
@@ -138,6 +162,7 @@ def lib():
         L.mcx_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.mcx_set_workspace.argtypes = [vp, vp, C.c_size_t]
         L.mcx_set_influence.argtypes = [vp, C.c_int, C.c_uint32]
+        L.mcx_ct_to_phantom.argtypes = [C.POINTER(CTCalibration), vp, C.c_uint64, vp, vp]
         L.mcx_get_influence.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, C.POINTER(C.c_uint64)]
         for f in ABI_SYMBOLS:
             if f not in ("mcx_destroy", "mcx_last_error"):

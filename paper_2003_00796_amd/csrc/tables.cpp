@@ -290,3 +290,39 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
 }
 
 }  // namespace mcx
+
+// CT calibration (see mcx_ct_to_phantom in mcx.h): piecewise-linear HU ->
+// density, thresholds HU -> material index
+extern "C" int mcx_ct_to_phantom(const mcx_ct_calibration* cal, const int16_t* hu, uint64_t nvox, double* rho,
+                                 uint8_t* mat) {
+  if (!cal || !hu || !rho || cal->n_points < 1 || !cal->hu || !cal->rho) return MCX_E_INVALID;
+  if (cal->n_thresholds < 0 || cal->n_thresholds > mcx::kMaxMat - 1 || (cal->n_thresholds > 0 && !cal->mat_hu))
+    return MCX_E_INVALID;
+  const int np = cal->n_points;
+  for (int i = 0; i < np; ++i) {
+    if (!(cal->rho[i] > 0.0) || !std::isfinite(cal->hu[i])) return MCX_E_INVALID;
+    if (i > 0 && !(cal->hu[i] > cal->hu[i - 1])) return MCX_E_INVALID;
+  }
+  for (int j = 1; j < cal->n_thresholds; ++j)
+    if (!(cal->mat_hu[j] > cal->mat_hu[j - 1])) return MCX_E_INVALID;
+  for (uint64_t v = 0; v < nvox; ++v) {
+    const double x = double(hu[v]);
+    double r;
+    if (x <= cal->hu[0]) {
+      r = cal->rho[0];
+    } else if (x >= cal->hu[np - 1]) {
+      r = cal->rho[np - 1];
+    } else {
+      int i = int(std::upper_bound(cal->hu, cal->hu + np, x) - cal->hu) - 1;  // hu[i] <= x < hu[i + 1]
+      const double f = (x - cal->hu[i]) / (cal->hu[i + 1] - cal->hu[i]);
+      r = cal->rho[i] + f * (cal->rho[i + 1] - cal->rho[i]);
+    }
+    rho[v] = r;
+    if (mat) {
+      int k = 0;
+      while (k < cal->n_thresholds && x >= cal->mat_hu[k]) ++k;
+      mat[v] = uint8_t(k);
+    }
+  }
+  return MCX_OK;
+}

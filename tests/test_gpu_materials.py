@@ -59,7 +59,19 @@ def layered():
     return dict(W.workload("hetero_mm_64"), phantom=ph, sources=[W.pencil(0, 1.0, (50.0, 50.0, 0.0), 4000)])
 
 
+def ct_case():
+    """A CT-like volume through a calibration (density by linear
+    interpolation, bone at and above 300 HU), converted here with numpy so
+    that the oracle's input does not come from the library."""
+    hu = W.ct_hu_volume(32)
+    rho = np.interp(hu.astype(np.float64), [-1000.0, -700.0, 0.0, 100.0, 1500.0], [0.0012, 0.3, 1.0, 1.07, 1.9])
+    mat = (hu >= 300).astype(np.uint8)
+    ph = dict(shape=hu.shape, voxel=(0.5, 0.5, 0.5), origin=(0.0, 0.0, 0.0), rho=rho, mat=mat)
+    return dict(W.workload("hetero_mm_64"), phantom=ph, sources=[W.rect_field(0, 6.0, (8.0, 8.0, 0.0), (6.0, 6.0), 3000)])
+
+
 CASES = {
+    "ct_volume": (ct_case, 6.0),
     "bone_spheres": (lambda: W.workload("hetero_mm_64", 3000), 6.0),
     "layers_1MeV": (layered, 1.0),
     "electron_layers": (lambda: dict(layered(), transport=W.transport(100.0, 250),

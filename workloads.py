@@ -122,6 +122,16 @@ def hetero_mm_phantom(n: int, size: float = 25.6, seed: int = 2) -> dict:
     return ph
 
 
+def ct_hu_volume(n: int = 32, seed: int = 7, sigma: float = 2.0) -> np.ndarray:
+    """A CT-like volume of Hounsfield units (int16, [nz][ny][nx]): Gaussian-
+    smoothed white noise mapped affinely to [-900, 1400] HU (lung to bone)."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = gaussian_filter(rng.standard_normal((n, n, n)), sigma)
+    s = (s - s.min()) / (s.max() - s.min())
+    return np.round(-900.0 + 2300.0 * s).astype(np.int16)
+
+
 def ct_noise_phantom(n: int = 256, d: float = 0.2, seed: int = 3, sigma: float = 4.0) -> dict:
     """Gaussian-smoothed (sigma in voxels) white noise, affinely mapped to [0.2, 1.9]."""
     from scipy.ndimage import gaussian_filter
