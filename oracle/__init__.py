@@ -50,7 +50,8 @@ class Material(C.Structure):
 class Transport(C.Structure):
     _fields_ = [("n_grid", C.c_int), ("e_min", C.c_double), ("e_max", C.c_double),
                 ("eabs", C.c_double * 3), ("c1", C.c_double), ("c2", C.c_double),
-                ("wcc", C.c_double), ("wcr", C.c_double), ("flags", C.c_uint32)]
+                ("wcc", C.c_double), ("wcr", C.c_double), ("flags", C.c_uint32),
+                ("force_in", C.c_double), ("force_br", C.c_double)]
 
 
 class Phantom(C.Structure):
@@ -165,6 +166,8 @@ def transport_struct(t: dict) -> Transport:
     s.c1, s.c2 = float(t["c1"]), float(t["c2"])
     s.wcc, s.wcr = float(t["wcc"]), float(t["wcr"])
     s.flags = int(t.get("flags", 0))
+    s.force_in = float(t.get("force_in", 1.0))
+    s.force_br = float(t.get("force_br", 1.0))
     return s
 
 

@@ -39,6 +39,12 @@
  *     rho mu_m(E) l voxel by voxel and interacts by the tables of the voxel it
  *     stops in; an e+- step uses the tables of its voxel (every face ends a
  *     step, so a step stays in one material).
+ *  R11 interaction forcing (optional variance reduction): the hard inelastic
+ *     and bremsstrahlung cross sections are multiplied by F_in, F_br >= 1; a
+ *     forced event emits its secondary with weight w/F and changes the
+ *     primary (energy loss, deflection) only with probability 1/F, drawn
+ *     after the event's azimuth; every particle carries a weight and every
+ *     deposit and escape is weighted, so the tallies stay unbiased.
  *  R8 straggling of the soft energy loss (optional): mean = the CSDA loss over
  *     the step's mass path s, variance = s times the second moment of the
  *     soft part of the energy-loss DCS (Bohr's variance from the leading
@@ -420,8 +426,9 @@ orc_tables* orc_tables_create(const orc_material* m, const orc_transport* t) {
       }
       tb->el[p][CH_S][i] = ss;
       tb->el[p][CH_EL][i] = sig_h;
-      tb->el[p][CH_IN][i] = sig_in;
-      tb->el[p][CH_BR][i] = sig_br;
+      /* R11: forced channels (the soft stopping power above stays analog) */
+      tb->el[p][CH_IN][i] = t->force_in > 1.0 ? sig_in * t->force_in : sig_in;
+      tb->el[p][CH_BR][i] = t->force_br > 1.0 ? sig_br * t->force_br : sig_br;
       tb->el[p][CH_T1S][i] = sig1s;
     }
     /* range: exact integral of 1/S over the piecewise power-law S */
@@ -590,6 +597,7 @@ typedef struct {
   stream rng;
   uint32_t nchild;
   uint64_t hash;
+  double w;  /* statistical weight (R11) */
 } part;
 
 typedef struct {
@@ -692,6 +700,7 @@ static void deposit(ctx* c, const part* p, double e) {
     c->tmp[v] = 0.0;
     c->touched[c->n_touched++] = v;
   }
+  e *= p->w;
   c->tmp[v] += e;
   c->led[ORC_LED_DEP] += e;
   c->st->deposits++;
@@ -752,6 +761,7 @@ static void secondary(ctx* c, part* p, int type, double e, const double d[3]) {
   s.rng.hist = p->rng.hist;
   s.rng.uid = orc_child_uid(p->rng.uid, k);
   s.rng.ctr = 0;
+  s.w = p->w;
   push(c, &s);
 }
 
@@ -895,7 +905,7 @@ static int photon_flight_mm(ctx* c, part* p, double* mu, double* mt_out) {
     tau -= att * s;
     if (cross(c, p, s, a)) {
       st->escaped++;
-      c->led[ORC_LED_ESC] += p->e;
+      c->led[ORC_LED_ESC] += p->e * p->w;
       event(c, p, EV_PH_ESCAPE, v);
       finish(c, p);
       return 1;
@@ -946,7 +956,7 @@ static void photon_track(ctx* c, part* p) {
       int64_t v = lin(c, p->ix);
       if (cross(c, p, s, a)) {
         st->escaped++;
-        c->led[ORC_LED_ESC] += p->e;
+        c->led[ORC_LED_ESC] += p->e * p->w;
         event(c, p, EV_PH_ESCAPE, v);
         finish(c, p);
         return;
@@ -995,8 +1005,8 @@ static void e_absorb(ctx* c, part* p) {
 
 static void e_escape(ctx* c, part* p, int64_t v) {
   c->st->escaped++;
-  c->led[ORC_LED_ESC] += p->e;
-  if (p->type == ORC_POSITRON) c->led[ORC_LED_POSESC] += 1.0;
+  c->led[ORC_LED_ESC] += p->e * p->w;
+  if (p->type == ORC_POSITRON) c->led[ORC_LED_POSESC] += p->w;
   event(c, p, EV_E_ESCAPE, v);
   p->e = 0.0;
   finish(c, p);
@@ -1095,12 +1105,21 @@ static void e_hard(ctx* c, part* p, int which) {
     double k = ti == 0 ? sample_moller(&p->rng, p->e, c->t->wcc) : sample_bhabha(&p->rng, p->e, c->t->wcc);
     double phi = 2.0 * PI * draw(&p->rng);
     double e = p->e, w = k * e;
+    /* R11: a forced collision changes the primary with probability 1/F and
+     * emits the knock-on electron with weight w/F */
+    double f = c->t->force_in > 1.0 ? c->t->force_in : 1.0;
+    int apply = f > 1.0 ? draw(&p->rng) * f < 1.0 : 1;
     double cp = binary_cos(e, w, 1), cs = binary_cos(e, w, 0);
     double ds[3] = {p->d[0], p->d[1], p->d[2]};
     rotate(ds, cs, phi + PI);
-    rotate(p->d, cp, phi);
-    p->e = e - w;
+    if (apply) {
+      rotate(p->d, cp, phi);
+      p->e = e - w;
+    }
+    double w0 = p->w;
+    p->w = w0 / f;
     secondary(c, p, ORC_ELECTRON, w, ds);
+    p->w = w0;
     event(c, p, EV_HARD_IN, v);
   } else if (which == 3) {
     /* R9: the positron annihilates with an electron at rest */
@@ -1124,10 +1143,17 @@ static void e_hard(ctx* c, part* p, int which) {
     double w = wcr * pow(e / wcr, draw(&p->rng));
     double ct = leading_angle(beta_of(e), draw(&p->rng));
     double phi = 2.0 * PI * draw(&p->rng);
+    /* R11: a forced emission changes the primary with probability 1/F and
+     * emits the photon with weight w/F */
+    double f = c->t->force_br > 1.0 ? c->t->force_br : 1.0;
+    int apply = f > 1.0 ? draw(&p->rng) * f < 1.0 : 1;
     double dg[3] = {p->d[0], p->d[1], p->d[2]};
     rotate(dg, ct, phi);
-    p->e = e - w;
+    if (apply) p->e = e - w;
+    double w0 = p->w;
+    p->w = w0 / f;
     secondary(c, p, ORC_PHOTON, w, dg);
+    p->w = w0;
     event(c, p, EV_HARD_BR, v);
   }
 }
@@ -1309,6 +1335,7 @@ static int run_body(const orc_tables* const* tbs, int n_mat, const orc_transport
     p.rng.seed = seed;
     p.rng.hist = (uint32_t)h;
     p.rng.uid = 1;
+    p.w = 1.0;
     memcpy(p.x, so->pos, sizeof(p.x));
     memcpy(p.d, so->dir, sizeof(p.d));
     if (so->kind == ORC_SRC_RECT) {
@@ -1383,7 +1410,7 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
   /* the estimator has no term for the score of a straggled soft loss, and
    * the replays of the device path run the main step only */
-  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || ph->mat) return -4;
+  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || ph->mat || t->force_in > 1.0 || t->force_br > 1.0) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));

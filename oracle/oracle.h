@@ -77,6 +77,9 @@ typedef struct {
   double c1, c2;       /* Class II elastic / energy-loss step parameters */
   double wcc, wcr;     /* hard inelastic / hard bremsstrahlung cutoffs */
   uint32_t flags;
+  /* interaction forcing (R11): hard inelastic and hard bremsstrahlung cross
+   * sections multiplied by these factors (values <= 1: no forcing) */
+  double force_in, force_br;
 } orc_transport;
 
 typedef struct {
