@@ -251,6 +251,8 @@ def main():
                     help="also time the mixed step on the same phantom with bone spheres of a second material")
     ap.add_argument("--annih-flight", action="store_true",
                     help="also time the mixed step with positron annihilation in flight on")
+    ap.add_argument("--forcing", type=float, nargs=2, metavar=("F_IN", "F_BR"), default=None,
+                    help="also time the workload with interaction forcing of hard collisions and bremsstrahlung")
     ap.add_argument("--no-fp64", action="store_true")
     # records per event queue: 2^26 puts a quarter of it, 16.8 M particles,
     # in flight at once (all histories of a 1e7 step are admitted together)
@@ -358,6 +360,27 @@ def main():
                                  esteps_per_history=st_sg["esteps"] / n, annihilations_per_history=st_sg["annih"] / n,
                                  dose_vs_main=dict(high_dose_deviation(d_sg, d_mix), z_rms=float(np.sqrt(np.mean(z ** 2))),
                                                    z_mean=float(np.mean(z))))
+    if args.forcing:
+        f_in, f_br = args.forcing
+        t = dict(wl["transport"], force_in=f_in, force_br=f_br)
+        sf = mcx.Simulator(mcx.MIXED, 0).setup(dict(wl, transport=t))
+        sf.set_launch(args.bank, 256, 128)
+        run_steps(sf, n, warm_seeds, sync)
+        t_f = run_steps(sf, n, seeds, sync)
+        d_f, s_f = sf.dose()
+        st_f = sf.stats()
+        sf.close()
+        hi = d_mix >= 0.5 * d_mix.max()
+        z = (d_f[hi] - d_mix[hi]) / np.sqrt(s_f[hi] ** 2 + s_mix[hi] ** 2)
+        # efficiency 1 / (sigma^2 T) of the high-dose voxels, forced over analog
+        eff = (np.mean(s_mix[hi] ** 2) * sum(t_mix)) / (np.mean(s_f[hi] ** 2) * sum(t_f))
+        out["interaction_forcing"] = dict(force_in=f_in, force_br=f_br, value=n * len(t_f) / sum(t_f),
+                                          ms_per_step=1e3 * sum(t_f) / len(t_f),
+                                          esteps_per_history=st_f["esteps"] / n,
+                                          hard_br_per_history=st_f["hard_br"] / n,
+                                          high_dose_efficiency_vs_analog=float(eff),
+                                          dose_vs_main=dict(z_rms=float(np.sqrt(np.mean(z ** 2))),
+                                                            z_mean=float(np.mean(z))))
     if args.materials:
         wm = W.workload("hetero_mm_128", n)
         sm = mcx.Simulator(mcx.MIXED, 0).setup(wm)

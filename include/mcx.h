@@ -117,6 +117,17 @@ typedef struct {
   double c1, c2;
   double wcc, wcr;
   uint32_t flags;
+  /* Interaction forcing (the variance reduction of the disc example with
+   * forced bremsstrahlung and hard collisions, PENELOPE example tests of
+   * the Validation section): the hard inelastic-collision
+   * and bremsstrahlung cross sections are multiplied by force_in, force_br;
+   * a forced event emits its secondary with the weight w/F and changes the
+   * primary (energy loss, deflection) with probability 1/F, so that every
+   * expectation is unchanged while F times more secondaries are produced.
+   * 0 or 1 = analog; otherwise F in [1, 1e5] (MCX_E_INVALID if not).
+   * Runs on one-material phantoms (mcx_run returns MCX_E_UNSUPPORTED with a
+   * material index array) and not in mcx_dose_backward. */
+  double force_in, force_br;
 } mcx_transport;
 
 /* Voxel phantom.  nx, ny, nz <= 1024; voxel sizes > 0; rho > 0 everywhere

@@ -21,8 +21,8 @@ static hipError_t launch_flavor(const KArgs<float>& a, int par, uint32_t target,
   const size_t sm_f = size_t(T_PHOTON_END) * a.tb.n * sizeof(float);
   const size_t sm_e = (size_t(T_NCH) * a.tb.n + kSoftN) * sizeof(float);
   if (ev) (void)hipEventRecord(ev[0], s);
-  constexpr int B = base_flavor(F);  // the extended physics changes the e+- step only
-  hipLaunchKernelGGL((k_source<float, B>), dim3(grid), dim3(block), 0, s, a, par);
+  // the optional physics changes the e+- step only; weights reach every kernel
+  hipLaunchKernelGGL((k_source<float, source_flavor(F)>), dim3(grid), dim3(block), 0, s, a, par);
   if (ev) (void)hipEventRecord(ev[1], s);
   constexpr int PF = photon_flavor(F);
   hipLaunchKernelGGL((k_flight<float, PF>), dim3(grid), dim3(block), several(F) ? sm_f * size_t(a.tb.nmat) : sm_f, s, a, par);
@@ -41,6 +41,9 @@ hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int
   // replays never write the test outputs
   if (a.mode == 1) return launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev);
   if (a.mode == 2) return launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev);
+  if (a.vr)
+    return a.test_mode ? launch_flavor<FL_VR_TEST>(a, par, target, grid, block, s, ev)
+                       : launch_flavor<FL_VR>(a, par, target, grid, block, s, ev);
   if (a.mm)
     return a.test_mode ? launch_flavor<FL_MM_TEST>(a, par, target, grid, block, s, ev)
                        : launch_flavor<FL_MM>(a, par, target, grid, block, s, ev);
@@ -73,7 +76,9 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
                              reinterpret_cast<const void*>(&k_estep<float, FL_EXT>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_EXT_TEST>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_MM>),
-                             reinterpret_cast<const void*>(&k_estep<float, FL_MM_TEST>)};
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MM_TEST>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_VR>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_VR_TEST>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

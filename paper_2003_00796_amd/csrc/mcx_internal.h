@@ -27,6 +27,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxGrid = 512;
 // materials per phantom (per-voxel index, one table block each)
 constexpr int kMaxMat = 4;
+constexpr double kMaxForce = 1.0e5;  // largest interaction-forcing factor
 constexpr int kMaxBlock = 256;  // kernels are compiled for blocks of at most 256 threads
 constexpr uint64_t kEmptyKey = ~0ull;
 
@@ -131,6 +132,7 @@ template <typename T>
 struct Bank {
   Chunk* c[kMaxChunks];
   uint64_t* hash;  // event hash (test mode)
+  double* w;       // statistical weight (interaction forcing)
 };
 
 struct SourceDev {
@@ -218,6 +220,8 @@ struct KArgs {
   int straggle;          // soft energy-loss straggling on (selects the kernel flavour)
   int annih;             // positron annihilation in flight on (selects the kernel flavour)
   int mm;                // several materials (selects the kernel flavour)
+  int vr;                // interaction forcing: weighted particles (selects the kernel flavour)
+  double f_in, f_br;     // forcing factors of hard inelastic collisions and bremsstrahlung
   const double* adj_w;   // per voxel: dL/dD_v * 1e6 / (rho_v V)
   double* adj_q;         // per history of the run: Q_h
   double* adj_grad;      // per voxel accumulator

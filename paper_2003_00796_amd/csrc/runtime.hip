@@ -165,6 +165,8 @@ int dalloc(mcx_ctx* c, DevBuf& b, size_t bytes, const char* what) {
 }
 
 bool fp64(const mcx_ctx* c) { return c->precision == MCX_FP64; }
+// interaction forcing on: a factor above 1 (0 and 1 mean analog)
+bool forced(const mcx_transport& t) { return t.force_in > 1.0 || t.force_br > 1.0; }
 size_t tsize(const mcx_ctx* c) { return fp64(c) ? sizeof(double) : sizeof(float); }
 uint64_t nvox(const mcx_ctx* c) { return uint64_t(c->nx) * c->ny * c->nz; }
 
@@ -182,12 +184,14 @@ void carve_banks(mcx_ctx* c, KArgs<T>& a) {
     for (int k = 0; k < kMaxChunks; ++k)
       b.c[k] = k < rec_chunks<T>() ? reinterpret_cast<Chunk*>(take(n * sizeof(Chunk))) : nullptr;
     b.hash = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
+    b.w = reinterpret_cast<double*>(take(n * sizeof(double)));
   }
 }
 
 size_t queue_bytes(const mcx_ctx* c) {
   const size_t n = c->cap;
-  const size_t per = ((n * sizeof(Chunk) + 255) / 256 * 256) * (fp64(c) ? 5 : 4) + (n * 8 + 255) / 256 * 256;
+  // records, event hashes, weights
+  const size_t per = ((n * sizeof(Chunk) + 255) / 256 * 256) * (fp64(c) ? 5 : 4) + 2 * ((n * 8 + 255) / 256 * 256);
   return per * Q_NQ;
 }
 
@@ -335,6 +339,9 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
   a.annih = (mode == 0 && (c->tr.flags & MCX_ANNIH_FLIGHT)) ? 1 : 0;
   a.mm = (mode == 0 && c->d_vmat.p) ? 1 : 0;
+  a.vr = (mode == 0 && forced(c->tr)) ? 1 : 0;
+  a.f_in = c->tr.force_in > 1.0 ? c->tr.force_in : 1.0;
+  a.f_br = c->tr.force_br > 1.0 ? c->tr.force_br : 1.0;
   if (mode) {
     a.test_mode = 0;
     a.adj_w = static_cast<const double*>(c->d_adj_w.p);
@@ -576,6 +583,9 @@ int mcx_set_transport(mcx_ctx* c, const mcx_transport* t) {
   if (!(t->wcc > 0.0) || !(t->wcr > 0.0)) return fail(c, MCX_E_INVALID, "Wcc and Wcr must be positive");
   for (int i = 0; i < 3; ++i)
     if (!(t->eabs[i] >= t->e_min)) return fail(c, MCX_E_INVALID, "Eabs must be >= e_min");
+  for (double f : {t->force_in, t->force_br})
+    if (!(f == 0.0 || (f >= 1.0 && f <= kMaxForce)))
+      return fail(c, MCX_E_INVALID, "forcing factors must be 0 (none) or in [1, %g]", kMaxForce);
   c->tr = *t;
   c->have_transport = true;
   c->have_material = false;
@@ -932,6 +942,8 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
   if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
   for (int k = 0; k <= c->vmat_max; ++k)
     if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
+  if (forced(c->tr) && c->d_vmat.p)
+    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing runs on one-material phantoms");
   if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
@@ -974,9 +986,10 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
-  if ((c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT)) || c->d_vmat.p)
+  if ((c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT)) || c->d_vmat.p || forced(c->tr))
     return fail(c, MCX_E_UNSUPPORTED,
-                "the gradient replays run the main path only (one material, no straggling, no annihilation in flight)");
+                "the gradient replays run the main path only (one material, no straggling, no annihilation in "
+                "flight, no forcing)");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

@@ -207,6 +207,10 @@ bool build_tables(const mcx_material_desc& m, const mcx_transport& t, BuiltTable
         if (ei > t.wcr) sig_br = m.brems_b * std::log(ei / t.wcr);
       }
       const double ss = md.s_collision(lep, ei) - s_hard + s_rad;
+      // interaction forcing: the hard channels' cross sections times F (the
+      // soft stopping power above keeps the analog split)
+      if (t.force_in > 1.0) sig_in *= t.force_in;
+      if (t.force_br > 1.0) sig_br *= t.force_br;
       if (!(ss > 0.0)) {
         *err = "soft stopping power is not positive at E = " + std::to_string(ei) + " MeV";
         return false;

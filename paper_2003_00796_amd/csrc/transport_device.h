@@ -246,6 +246,7 @@ struct Part {
   uint32_t hist;
   uint64_t uid;
   uint64_t hash;
+  double w;  // statistical weight (1 without interaction forcing)
   Rng<T> rng;
 };
 
@@ -269,7 +270,7 @@ __device__ __forceinline__ uint32_t pack_vox(const int ix[3]) {
 template <typename T>
 __device__ __forceinline__ void store_record(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
                                              const T d[3], T e, uint64_t uid, uint32_t ctr, uint32_t flags,
-                                             uint64_t hash) {
+                                             uint64_t hash, double w) {
   Chunk c0, c1, cm;
   split_f64(p.x[0], c0.x, c0.y);
   split_f64(p.x[1], c0.z, c0.w);
@@ -300,6 +301,7 @@ __device__ __forceinline__ void store_record(const KArgs<T>& a, const Bank<T>& b
     b.c[3][i] = cm;
   }
   if (a.test_mode) b.hash[i] = hash;
+  if (a.vr) b.w[i] = w;
 }
 
 template <typename T>
@@ -330,12 +332,13 @@ __device__ __forceinline__ void load_part(const KArgs<T>& a, const Bank<T>& b, u
   p.type = cm.w & 3u;
   p.nchild = cm.w >> 2;
   p.hash = a.test_mode ? b.hash[i] : 0ull;
+  p.w = a.vr ? b.w[i] : 1.0;
   rng_init(p.rng, a.seed, p.hist, p.uid, cm.y);
 }
 
 template <typename T>
 __device__ __forceinline__ void store_part(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p) {
-  store_record(a, b, i, p, p.d, p.e, p.uid, p.rng.ctr, p.type | (p.nchild << 2), p.hash);
+  store_record(a, b, i, p, p.d, p.e, p.uid, p.rng.ctr, p.type | (p.nchild << 2), p.hash, p.w);
 }
 
 // a secondary waiting to be appended: shares position/voxel/history with its parent
@@ -345,13 +348,14 @@ struct Child {
   T e;
   uint32_t type;
   uint64_t uid;
+  double w;
   bool on;
 };
 
 template <typename T>
 __device__ __forceinline__ void store_child(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
                                             const Child<T>& c) {
-  store_record(a, b, i, p, c.d, c.e, c.uid, 0u, c.type, 0ull);
+  store_record(a, b, i, p, c.d, c.e, c.uid, 0u, c.type, 0ull, c.w);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,7 +560,7 @@ __device__ __forceinline__ void deposit(const KArgs<T>& a, DepAcc& acc, LaneStat
     acc.key = key;
     acc.q = 0.0;
   }
-  acc.q += double(e);
+  acc.q += a.vr ? double(e) * p.w : double(e);  // weighted under interaction forcing
   ls.deposits++;
 }
 
@@ -586,12 +590,13 @@ __device__ __forceinline__ void finish(const KArgs<T>& a, const Part<T>& p) {
 template <typename T>
 __device__ __forceinline__ void ledger_escape(const KArgs<T>& a, BlockStats* st, const Part<T>& p) {
   stat_add(st, S_ESCAPED);
-  atomicAdd(&st->e_esc, double(p.e));
+  const double ew = a.vr ? double(p.e) * p.w : double(p.e);
+  atomicAdd(&st->e_esc, ew);
   if (p.type == POSITRON) stat_add(st, S_POSESC);
   if (!a.test_mode) return;
   const uint64_t h = p.hist - a.cnt->run_first;
-  unsafeAtomicAdd(&a.hist_led[3 * h + 1], double(p.e));
-  if (p.type == POSITRON) unsafeAtomicAdd(&a.hist_led[3 * h + 2], 1.0);
+  unsafeAtomicAdd(&a.hist_led[3 * h + 1], ew);
+  if (p.type == POSITRON) unsafeAtomicAdd(&a.hist_led[3 * h + 2], a.vr ? p.w : 1.0);
 }
 
 // ---------------------------------------------------------------------------

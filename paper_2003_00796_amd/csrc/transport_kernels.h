@@ -44,19 +44,25 @@ enum Flavor : int {
                       // straggling, positron annihilation in flight (run-time switches)
   FL_EXT_TEST = 5,    // the same with the per-history test outputs
   FL_MM = 6,          // several materials (per-voxel index), with the optional physics
-  FL_MM_TEST = 7      // the same with the per-history test outputs
+  FL_MM_TEST = 7,     // the same with the per-history test outputs
+  FL_VR = 8,          // interaction forcing: weighted particles, with the optional physics
+  FL_VR_TEST = 9      // the same with the per-history test outputs
 };
-constexpr int kFlavors = 8;
+constexpr int kFlavors = 10;
 
 // the optional physics changes the e+- step only: the other kernels of an
 // extended flavour are those of the flavour without it; several materials
 // change the photon flight and interactions too
 constexpr int base_flavor(int f) {
-  return (f == FL_EXT || f == FL_MM) ? FL_FWD : ((f == FL_EXT_TEST || f == FL_MM_TEST) ? FL_TEST : f);
+  return (f == FL_EXT || f == FL_MM || f == FL_VR) ? FL_FWD
+                                                   : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST) ? FL_TEST : f);
 }
 constexpr bool extended(int f) { return f >= FL_EXT; }
 constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST; }
-constexpr int photon_flavor(int f) { return several(f) ? f : base_flavor(f); }
+// weighted particles: every kernel carries the weights
+constexpr bool weighted(int f) { return f == FL_VR || f == FL_VR_TEST; }
+constexpr int photon_flavor(int f) { return several(f) || weighted(f) ? f : base_flavor(f); }
+constexpr int source_flavor(int f) { return weighted(f) ? f : base_flavor(f); }
 
 // constants of material m (selects over the kMaxMat entries: no indexing of
 // the argument block by a run-time value)
@@ -70,6 +76,8 @@ __device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
   constexpr int B = base_flavor(F);
   __builtin_assume(a.test_mode == (B == FL_TEST ? 1 : 0));
   __builtin_assume(a.mode == (B == FL_ADJ_A ? 1 : (B == FL_ADJ_B ? 2 : 0)));
+  constexpr int W = weighted(F) ? 1 : 0;
+  __builtin_assume(a.vr == W);
 }
 
 // striped queues: this block's stripe, the records of a stripe, the prefix
@@ -148,6 +156,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
       p.uid = 1ull;
       p.nchild = 0u;
       p.hash = 0ull;
+      p.w = 1.0;
       rng_init(p.rng, a.seed, p.hist, 1ull, 0u);
       p.x[0] = s.pos[0]; p.x[1] = s.pos[1]; p.x[2] = s.pos[2];
       p.d[0] = T(s.dir[0]); p.d[1] = T(s.dir[1]); p.d[2] = T(s.dir[2]);
@@ -578,6 +587,7 @@ __device__ __forceinline__ void make_child(const KArgs<T>& a, Part<T>& p, Child<
   }
   c.on = true;
   c.type = type;
+  c.w = p.w;
   c.e = e;
   c.d[0] = d[0]; c.d[1] = d[1]; c.d[2] = d[2];
   c.uid = child_uid(p.uid, k);
@@ -1005,9 +1015,26 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     // electron on the opposite azimuth, the photon on the drawn one
     T dc[3] = {p.d[0], p.d[1], p.d[2]};
     rotate(dc, cos_c, kind == 2 ? ph + T(kPi) : ph);
-    if (kind == 2) rotate(p.d, cos_p, ph);
-    p.e = e1 - w;
+    // interaction forcing: the channel's cross section is F times the
+    // analog one; the event changes the primary with probability 1/F (a draw
+    // after the azimuth's) and its secondary carries weight w/F
+    bool apply = true;
+    double fw = 1.0;
+    if (a.vr) {
+      const double f = kind == 2 ? a.f_in : a.f_br;
+      if (f > 1.0) {
+        apply = double(uni<T>(p.rng)) * f < 1.0;
+        fw = f;
+      }
+    }
+    if (apply) {
+      if (kind == 2) rotate(p.d, cos_p, ph);
+      p.e = e1 - w;
+    }
+    const double w0 = p.w;
+    p.w = w0 / fw;
     make_child(a, p, c1, kind == 2 ? ELECTRON : PHOTON, w, dc, acc, ls, bs);
+    p.w = w0;
   } else {
     rotate(p.d, cos_p, ph);
   }

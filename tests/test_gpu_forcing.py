@@ -1,0 +1,120 @@
+"""GPU parity of interaction forcing (weighted particles, the forced
+inelastic-collision and bremsstrahlung channels) against the FP64 oracle
+with the same forcing factors, through the C ABI: event sequences, weighted
+per-history ledgers, doses within 3 combined standard errors; the mixed
+precision path against FP64; refusals."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+MC2 = W.MC2
+
+
+def _mcx():
+    import paper_2003_00796_amd as mcx
+    return mcx
+
+
+def gpu_run(wl, n, precision=0, test=True):
+    mcx = _mcx()
+    sim = mcx.Simulator(precision, 0).setup(wl)
+    sim.set_test_mode(test)
+    sim.run(wl["seed"], 0, n)
+    h, led = sim.history_results(n) if test else (None, None)
+    d, s = sim.dose()
+    st = sim.stats()
+    sim.close()
+    return dict(hash=h, led=led, dose=d, sigma=s, stats=st)
+
+
+def oracle_run(wl, n):
+    r = O.run(O.Tables(wl["material"], wl["transport"]), wl["phantom"], wl["sources"], wl["seed"], 0, n,
+              hashes=True, ledger=True)
+    d, s = O.dose(wl["phantom"], r)
+    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, stats=r.stats.as_dict())
+
+
+def check_dose_3sigma(g, o, frac=0.01):
+    hi = o["dose"] > frac * o["dose"].max()
+    diff = np.abs(g["dose"] - o["dose"])[hi]
+    comb = np.sqrt(g["sigma"][hi] ** 2 + o["sigma"][hi] ** 2)
+    assert np.all(diff <= 3 * comb + 1e-12 * o["dose"].max()), float(np.max(diff / (comb + 1e-300)))
+
+
+def layers(particle, energy, n, flags=0, force_in=4.0, force_br=20.0):
+    rho = np.array([1.0, 1.85, 0.3, 1.85, 1.0, 0.26, 1.85, 1.0] * 2)
+    ph = W.slab_phantom(len(rho), 1.0, rho)
+    t = dict(W.transport(100.0, 250, flags=flags), force_in=force_in, force_br=force_br)
+    return dict(W.workload("electron_200"), phantom=ph, transport=t, material=W.WATER,
+                sources=[W.pencil(particle, energy, (50.0, 50.0, 0.0), n)])
+
+
+CASES = {
+    "electrons_10MeV": lambda: layers(1, 10.0, 400),
+    "photons_6MeV": lambda: layers(0, 6.0, 3000),
+    "positrons_5MeV_brems_only": lambda: layers(2, 5.0, 800, force_in=0.0, force_br=50.0),
+    "electrons_straggling_annihilation": lambda: layers(1, 10.0, 300, flags=O.STRAGGLING | O.ANNIH_FLIGHT),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_forcing_parity(case):
+    wl = CASES[case]()
+    n = wl["sources"][0]["n_hist"]
+    g, o = gpu_run(wl, n), oracle_run(wl, n)
+    same = g["hash"] == o["hash"]
+    print(case, "identical hashes", same.mean(), "hard br", g["stats"]["hard_br"], o["stats"]["hard_br"])
+    assert same.mean() >= 0.99
+    # weighted deposits, escapes and positron escapes of the same histories
+    assert np.allclose(g["led"][same], o["led"][same][:, [0, 1, 2]], rtol=0, atol=1e-8)
+    assert abs(g["stats"]["hard_br"] - o["stats"]["hard_br"]) <= 0.01 * o["stats"]["hard_br"] + 5
+    check_dose_3sigma(g, o)
+
+
+def test_forcing_mixed_precision_and_unbiased_balance():
+    wl = layers(1, 10.0, 20_000)
+    g64 = gpu_run(wl, 20_000, 0)
+    g32 = gpu_run(wl, 20_000, 1)
+    check_dose_3sigma(g32, g64)
+    for g in (g64, g32):
+        bal = g["led"][:, 0] + g["led"][:, 1] + 2 * MC2 * g["led"][:, 2]
+        assert abs(bal.mean() - 10.0) <= 5 * bal.std(ddof=1) / np.sqrt(bal.size)
+
+
+def test_forced_bremsstrahlung_rate():
+    """Bremsstrahlung forced by F = 20 with analog collisions and photons
+    that escape without interacting: the electrons (primaries and knock-ons)
+    follow the analog law, so the emissions are F times the analog count in
+    expectation."""
+    flags = O.NO_COMPTON | O.NO_PHOTO | O.NO_RAYLEIGH | O.NO_PAIR
+    wl = layers(1, 10.0, 20_000, flags=flags, force_in=0.0, force_br=20.0)
+    f = gpu_run(wl, 20_000, 1, test=False)
+    a = gpu_run(dict(wl, transport=dict(wl["transport"], force_br=0.0)), 20_000, 1, test=False)
+    ratio = f["stats"]["hard_br"] / a["stats"]["hard_br"]
+    print("analog emissions", a["stats"]["hard_br"], "ratio", ratio)
+    assert 18.5 < ratio < 21.5, ratio
+
+
+def test_forcing_refusals():
+    mcx = _mcx()
+    wl = layers(1, 10.0, 100)
+    sim = mcx.Simulator(0, 0)
+    with pytest.raises(mcx.MCXError, match="INVALID"):
+        sim.set_transport(dict(wl["transport"], force_br=0.5))
+    with pytest.raises(mcx.MCXError, match="INVALID"):
+        sim.set_transport(dict(wl["transport"], force_in=1e6))
+    sim.close()
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.run(wl["seed"], 0, 100)
+    with pytest.raises(mcx.MCXError, match="UNSUPPORTED"):
+        sim.dose_backward(np.zeros(sim.shape))
+    sim.close()
+    mm = dict(W.workload("hetero_mm_64", 100))
+    mm["transport"] = dict(mm["transport"], force_br=10.0)
+    sim = mcx.Simulator(0, 0).setup(mm)
+    with pytest.raises(mcx.MCXError, match="UNSUPPORTED"):
+        sim.run(mm["seed"], 0, 100)
+    sim.close()
