@@ -51,7 +51,7 @@ class Transport(C.Structure):
     _fields_ = [("n_grid", C.c_int), ("e_min", C.c_double), ("e_max", C.c_double),
                 ("eabs", C.c_double * 3), ("c1", C.c_double), ("c2", C.c_double),
                 ("wcc", C.c_double), ("wcr", C.c_double), ("flags", C.c_uint32),
-                ("force_in", C.c_double), ("force_br", C.c_double)]
+                ("force_in", C.c_double), ("force_br", C.c_double), ("split_br", C.c_int)]
 
 
 class Phantom(C.Structure):
@@ -168,6 +168,7 @@ def transport_struct(t: dict) -> Transport:
     s.flags = int(t.get("flags", 0))
     s.force_in = float(t.get("force_in", 1.0))
     s.force_br = float(t.get("force_br", 1.0))
+    s.split_br = int(t.get("split_br", 1))
     return s
 
 

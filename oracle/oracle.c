@@ -45,6 +45,10 @@
  *     primary (energy loss, deflection) only with probability 1/F, drawn
  *     after the event's azimuth; every particle carries a weight and every
  *     deposit and escape is weighted, so the tallies stay unbiased.
+ *  R12 bremsstrahlung splitting (optional variance reduction, S = 1 or 2):
+ *     each emission yields S photons of the sampled energy W with weight
+ *     w/(F S); the first takes the event's angles, each further one draws
+ *     its own polar cosine and azimuth; the primary loses W once.
  *  R8 straggling of the soft energy loss (optional): mean = the CSDA loss over
  *     the step's mass path s, variance = s times the second moment of the
  *     soft part of the energy-loss DCS (Bohr's variance from the leading
@@ -1147,12 +1151,22 @@ static void e_hard(ctx* c, part* p, int which) {
      * emits the photon with weight w/F */
     double f = c->t->force_br > 1.0 ? c->t->force_br : 1.0;
     int apply = f > 1.0 ? draw(&p->rng) * f < 1.0 : 1;
+    /* R12: split into S photons of energy W, each with its own polar and
+     * azimuthal angle (drawn after the above) and weight w/(F S) */
+    int ns = c->t->split_br == 2 ? 2 : 1;
     double dg[3] = {p->d[0], p->d[1], p->d[2]};
+    double d2[3] = {p->d[0], p->d[1], p->d[2]};
     rotate(dg, ct, phi);
+    if (ns == 2) {
+      double ct2 = leading_angle(beta_of(e), draw(&p->rng));
+      double phi2 = 2.0 * PI * draw(&p->rng);
+      rotate(d2, ct2, phi2);
+    }
     if (apply) p->e = e - w;
     double w0 = p->w;
-    p->w = w0 / f;
+    p->w = w0 / (f * ns);
     secondary(c, p, ORC_PHOTON, w, dg);
+    if (ns == 2) secondary(c, p, ORC_PHOTON, w, d2);
     p->w = w0;
     event(c, p, EV_HARD_BR, v);
   }
@@ -1410,7 +1424,9 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
   /* the estimator has no term for the score of a straggled soft loss, and
    * the replays of the device path run the main step only */
-  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || ph->mat || t->force_in > 1.0 || t->force_br > 1.0) return -4;
+  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || ph->mat || t->force_in > 1.0 || t->force_br > 1.0 ||
+      t->split_br == 2)
+    return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));

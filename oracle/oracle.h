@@ -80,6 +80,7 @@ typedef struct {
   /* interaction forcing (R11): hard inelastic and hard bremsstrahlung cross
    * sections multiplied by these factors (values <= 1: no forcing) */
   double force_in, force_br;
+  int split_br; /* bremsstrahlung photons emitted per event, 1 or 2 (R12) */
 } orc_transport;
 
 typedef struct {

@@ -11,7 +11,9 @@ variance-reduction extension of the main path).
   agree with the analog run's within their combined standard errors, at
   step parameters small enough that the Class II result no longer depends
   on the step length (forced events end steps);
-- the gradient refuses a forced transport.
+- bremsstrahlung splitting (S = 2) doubles the escaping photons of a thin
+  slab and keeps the weighted escaped energy's mean;
+- the gradient refuses a forced or split transport.
 """
 import numpy as np
 import pytest
@@ -25,7 +27,7 @@ EL_IN, EL_BR = 4 + 3, 4 + 4  # electron hard inelastic and bremsstrahlung channe
 
 def test_unit_forcing_is_the_analog_run():
     wl = W.workload("electron_200", 200)
-    t1 = dict(wl["transport"], force_in=1.0, force_br=1.0)
+    t1 = dict(wl["transport"], force_in=1.0, force_br=1.0, split_br=1)
     a = O.run(O.Tables(wl["material"], wl["transport"]), wl["phantom"], wl["sources"], 1, 0, 200, hashes=True,
               ledger=True)
     b = O.run(O.Tables(wl["material"], t1), wl["phantom"], wl["sources"], 1, 0, 200, hashes=True, ledger=True)
@@ -69,7 +71,7 @@ def test_forcing_leaves_the_depth_dose_unbiased():
     base = W.transport(100.0, 250, c1=0.01, c2=0.01)
     src = [W.pencil(1, e0, (50.0, 50.0, 0.0), n)]
     a = O.run(O.Tables(W.WATER, base), ph, src, 3, 0, n, ledger=True)
-    b = O.run(O.Tables(W.WATER, dict(base, force_in=4.0, force_br=20.0)), ph, src, 3, 0, n, ledger=True)
+    b = O.run(O.Tables(W.WATER, dict(base, force_in=4.0, force_br=20.0, split_br=2)), ph, src, 3, 0, n, ledger=True)
     assert b.stats.hard_br > 10 * a.stats.hard_br
     assert b.stats.hard_in > 3 * a.stats.hard_in
     for r in (a, b):
@@ -85,9 +87,28 @@ def test_forcing_leaves_the_depth_dose_unbiased():
     assert abs(ea.mean() - eb.mean()) <= 5 * np.hypot(ea.std(ddof=1), eb.std(ddof=1)) / np.sqrt(n)
 
 
+def test_bremsstrahlung_splitting_in_a_thin_slab():
+    e0, dz, n = 10.0, 0.05, 4000
+    ph = W.slab_phantom(1, dz, np.array([1.0]))
+    base = W.transport(100.0, 250, flags=O.NO_HARD_ELASTIC | O.NO_HARD_INELASTIC | O.NO_COMPTON | O.NO_PHOTO
+                       | O.NO_RAYLEIGH | O.NO_PAIR)
+    src = [W.pencil(1, e0, (50.0, 50.0, 0.0), n)]
+    a = O.run(O.Tables(W.WATER, dict(base, force_br=10.0)), ph, src, 5, 0, n, ledger=True)
+    b = O.run(O.Tables(W.WATER, dict(base, force_br=10.0, split_br=2)), ph, src, 5, 0, n, ledger=True)
+    # the primaries follow the same law: one escape each; photons escape unscattered
+    ga, gb = a.stats.escaped - n, b.stats.escaped - n
+    assert gb == 2 * b.stats.hard_br and ga == a.stats.hard_br
+    assert abs(b.stats.hard_br - a.stats.hard_br) <= 5 * np.sqrt(a.stats.hard_br)
+    esc_a, esc_b = a.ledger[:, O.LED_ESC], b.ledger[:, O.LED_ESC]
+    assert abs(esc_a.mean() - esc_b.mean()) <= 5 * np.hypot(esc_a.std(ddof=1), esc_b.std(ddof=1)) / np.sqrt(n)
+
+
 def test_gradient_refuses_forcing():
     wl = W.workload("electron_200", 10)
     tf = dict(wl["transport"], force_br=5.0)
     one = np.ones(wl["phantom"]["rho"].shape)
     with pytest.raises(RuntimeError):
         O.gradient(O.Tables(wl["material"], tf), wl["phantom"], wl["sources"], 1, 0, 10, one, one)
+    with pytest.raises(RuntimeError):
+        O.gradient(O.Tables(wl["material"], dict(wl["transport"], split_br=2)), wl["phantom"], wl["sources"], 1, 0,
+                   10, one, one)
