@@ -253,6 +253,8 @@ def main():
                     help="also time the mixed step with positron annihilation in flight on")
     ap.add_argument("--forcing", type=float, nargs=2, metavar=("F_IN", "F_BR"), default=None,
                     help="also time the workload with interaction forcing of hard collisions and bremsstrahlung")
+    ap.add_argument("--split-br", type=int, default=0, choices=(0, 1, 2),
+                    help="with --forcing: bremsstrahlung photons per emission")
     ap.add_argument("--no-fp64", action="store_true")
     # records per event queue: 2^26 puts a quarter of it, 16.8 M particles,
     # in flight at once (all histories of a 1e7 step are admitted together)
@@ -362,7 +364,7 @@ def main():
                                                    z_mean=float(np.mean(z))))
     if args.forcing:
         f_in, f_br = args.forcing
-        t = dict(wl["transport"], force_in=f_in, force_br=f_br)
+        t = dict(wl["transport"], force_in=f_in, force_br=f_br, split_br=args.split_br)
         sf = mcx.Simulator(mcx.MIXED, 0).setup(dict(wl, transport=t))
         sf.set_launch(args.bank, 256, 128)
         run_steps(sf, n, warm_seeds, sync)
@@ -374,7 +376,7 @@ def main():
         z = (d_f[hi] - d_mix[hi]) / np.sqrt(s_f[hi] ** 2 + s_mix[hi] ** 2)
         # efficiency 1 / (sigma^2 T) of the high-dose voxels, forced over analog
         eff = (np.mean(s_mix[hi] ** 2) * sum(t_mix)) / (np.mean(s_f[hi] ** 2) * sum(t_f))
-        out["interaction_forcing"] = dict(force_in=f_in, force_br=f_br, value=n * len(t_f) / sum(t_f),
+        out["interaction_forcing"] = dict(force_in=f_in, force_br=f_br, split_br=args.split_br, value=n * len(t_f) / sum(t_f),
                                           ms_per_step=1e3 * sum(t_f) / len(t_f),
                                           esteps_per_history=st_f["esteps"] / n,
                                           hard_br_per_history=st_f["hard_br"] / n,

@@ -128,6 +128,12 @@ typedef struct {
    * Runs on one-material phantoms (mcx_run returns MCX_E_UNSUPPORTED with a
    * material index array) and not in mcx_dose_backward. */
   double force_in, force_br;
+  /* Bremsstrahlung splitting (the same example splits emitted photons by 2):
+   * with split_br = 2 each emission yields two photons of the sampled energy,
+   * the second with its own polar and azimuthal angle, each with half the
+   * weight; the primary loses the energy once.  0 or 1 = no splitting;
+   * other values MCX_E_INVALID.  Same restrictions as forcing. */
+  int split_br;
 } mcx_transport;
 
 /* Voxel phantom.  nx, ny, nz <= 1024; voxel sizes > 0; rho > 0 everywhere

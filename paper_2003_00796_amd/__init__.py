@@ -48,7 +48,7 @@ class Transport(C.Structure):
     _fields_ = [("n_grid", C.c_int), ("e_min", C.c_double), ("e_max", C.c_double),
                 ("eabs", C.c_double * 3), ("c1", C.c_double), ("c2", C.c_double),
                 ("wcc", C.c_double), ("wcr", C.c_double), ("flags", C.c_uint32),
-                ("force_in", C.c_double), ("force_br", C.c_double)]
+                ("force_in", C.c_double), ("force_br", C.c_double), ("split_br", C.c_int)]
 
 
 class PhantomDesc(C.Structure):
@@ -223,6 +223,7 @@ class Simulator:
         s.flags = int(t.get("flags", 0))
         s.force_in = float(t.get("force_in", 0.0))
         s.force_br = float(t.get("force_br", 0.0))
+        s.split_br = int(t.get("split_br", 0))
         self._check(self._L.mcx_set_transport(self._h, C.byref(s)), "set_transport")
 
     def load_material(self, m: dict, mat_id: int = 0):

@@ -222,6 +222,7 @@ struct KArgs {
   int mm;                // several materials (selects the kernel flavour)
   int vr;                // interaction forcing: weighted particles (selects the kernel flavour)
   double f_in, f_br;     // forcing factors of hard inelastic collisions and bremsstrahlung
+  int split_br;          // bremsstrahlung photons per emission (1 or 2)
   const double* adj_w;   // per voxel: dL/dD_v * 1e6 / (rho_v V)
   double* adj_q;         // per history of the run: Q_h
   double* adj_grad;      // per voxel accumulator

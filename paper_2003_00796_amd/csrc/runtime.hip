@@ -167,6 +167,8 @@ int dalloc(mcx_ctx* c, DevBuf& b, size_t bytes, const char* what) {
 bool fp64(const mcx_ctx* c) { return c->precision == MCX_FP64; }
 // interaction forcing on: a factor above 1 (0 and 1 mean analog)
 bool forced(const mcx_transport& t) { return t.force_in > 1.0 || t.force_br > 1.0; }
+// weighted particles: forcing or bremsstrahlung splitting
+bool weighted_run(const mcx_transport& t) { return forced(t) || t.split_br == 2; }
 size_t tsize(const mcx_ctx* c) { return fp64(c) ? sizeof(double) : sizeof(float); }
 uint64_t nvox(const mcx_ctx* c) { return uint64_t(c->nx) * c->ny * c->nz; }
 
@@ -339,7 +341,8 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
   a.annih = (mode == 0 && (c->tr.flags & MCX_ANNIH_FLIGHT)) ? 1 : 0;
   a.mm = (mode == 0 && c->d_vmat.p) ? 1 : 0;
-  a.vr = (mode == 0 && forced(c->tr)) ? 1 : 0;
+  a.vr = (mode == 0 && weighted_run(c->tr)) ? 1 : 0;
+  a.split_br = c->tr.split_br == 2 ? 2 : 1;
   a.f_in = c->tr.force_in > 1.0 ? c->tr.force_in : 1.0;
   a.f_br = c->tr.force_br > 1.0 ? c->tr.force_br : 1.0;
   if (mode) {
@@ -586,6 +589,7 @@ int mcx_set_transport(mcx_ctx* c, const mcx_transport* t) {
   for (double f : {t->force_in, t->force_br})
     if (!(f == 0.0 || (f >= 1.0 && f <= kMaxForce)))
       return fail(c, MCX_E_INVALID, "forcing factors must be 0 (none) or in [1, %g]", kMaxForce);
+  if (t->split_br < 0 || t->split_br > 2) return fail(c, MCX_E_INVALID, "split_br must be 0, 1 or 2");
   c->tr = *t;
   c->have_transport = true;
   c->have_material = false;
@@ -942,8 +946,8 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
   if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
   for (int k = 0; k <= c->vmat_max; ++k)
     if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
-  if (forced(c->tr) && c->d_vmat.p)
-    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing runs on one-material phantoms");
+  if (weighted_run(c->tr) && c->d_vmat.p)
+    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing and splitting run on one-material phantoms");
   if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
@@ -986,10 +990,10 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
-  if ((c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT)) || c->d_vmat.p || forced(c->tr))
+  if ((c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT)) || c->d_vmat.p || weighted_run(c->tr))
     return fail(c, MCX_E_UNSUPPORTED,
                 "the gradient replays run the main path only (one material, no straggling, no annihilation in "
-                "flight, no forcing)");
+                "flight, no forcing or splitting)");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

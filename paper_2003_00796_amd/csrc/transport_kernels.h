@@ -1027,6 +1027,17 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
         fw = f;
       }
     }
+    // bremsstrahlung splitting: a second photon of the same energy with its
+    // own polar cosine and azimuth (drawn after the above), each of the two
+    // with half the weight; it takes the second child slot
+    const bool split = a.vr && kind == 3 && a.split_br == 2;
+    T d2[3] = {p.d[0], p.d[1], p.d[2]};
+    if (split) {
+      const T c2c = leading_angle(beta_of(e1), uni<T>(p.rng));
+      const T ph2 = T(2.0 * kPi) * uni<T>(p.rng);
+      rotate(d2, c2c, ph2);
+      fw *= 2.0;
+    }
     if (apply) {
       if (kind == 2) rotate(p.d, cos_p, ph);
       p.e = e1 - w;
@@ -1034,6 +1045,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     const double w0 = p.w;
     p.w = w0 / fw;
     make_child(a, p, c1, kind == 2 ? ELECTRON : PHOTON, w, dc, acc, ls, bs);
+    if (split) make_child(a, p, c2, PHOTON, w, d2, acc, ls, bs);
     p.w = w0;
   } else {
     rotate(p.d, cos_p, ph);

@@ -1,5 +1,6 @@
-"""GPU parity of interaction forcing (weighted particles, the forced
-inelastic-collision and bremsstrahlung channels) against the FP64 oracle
+"""GPU parity of interaction forcing and bremsstrahlung splitting (weighted
+particles, the forced inelastic-collision and bremsstrahlung channels, two
+photons per emission) against the FP64 oracle
 with the same forcing factors, through the C ABI: event sequences, weighted
 per-history ledgers, doses within 3 combined standard errors; the mixed
 precision path against FP64; refusals."""
@@ -44,10 +45,10 @@ def check_dose_3sigma(g, o, frac=0.01):
     assert np.all(diff <= 3 * comb + 1e-12 * o["dose"].max()), float(np.max(diff / (comb + 1e-300)))
 
 
-def layers(particle, energy, n, flags=0, force_in=4.0, force_br=20.0):
+def layers(particle, energy, n, flags=0, force_in=4.0, force_br=20.0, split_br=0):
     rho = np.array([1.0, 1.85, 0.3, 1.85, 1.0, 0.26, 1.85, 1.0] * 2)
     ph = W.slab_phantom(len(rho), 1.0, rho)
-    t = dict(W.transport(100.0, 250, flags=flags), force_in=force_in, force_br=force_br)
+    t = dict(W.transport(100.0, 250, flags=flags), force_in=force_in, force_br=force_br, split_br=split_br)
     return dict(W.workload("electron_200"), phantom=ph, transport=t, material=W.WATER,
                 sources=[W.pencil(particle, energy, (50.0, 50.0, 0.0), n)])
 
@@ -57,6 +58,8 @@ CASES = {
     "photons_6MeV": lambda: layers(0, 6.0, 3000),
     "positrons_5MeV_brems_only": lambda: layers(2, 5.0, 800, force_in=0.0, force_br=50.0),
     "electrons_straggling_annihilation": lambda: layers(1, 10.0, 300, flags=O.STRAGGLING | O.ANNIH_FLIGHT),
+    "electrons_forced_and_split": lambda: layers(1, 10.0, 400, split_br=2),
+    "electrons_split_only": lambda: layers(1, 20.0, 300, force_in=0.0, force_br=0.0, split_br=2),
 }
 
 
@@ -106,6 +109,8 @@ def test_forcing_refusals():
         sim.set_transport(dict(wl["transport"], force_br=0.5))
     with pytest.raises(mcx.MCXError, match="INVALID"):
         sim.set_transport(dict(wl["transport"], force_in=1e6))
+    with pytest.raises(mcx.MCXError, match="INVALID"):
+        sim.set_transport(dict(wl["transport"], split_br=3))
     sim.close()
     sim = mcx.Simulator(0, 0).setup(wl)
     sim.run(wl["seed"], 0, 100)
