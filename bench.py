@@ -97,6 +97,31 @@ def roofline(st: dict) -> dict:
     return out
 
 
+def target_detector_efficiency(mcx, W, sync, args, n: int = 1_000_000) -> dict:
+    """Efficiency 1/(sigma^2 T) of the energy deposited in the first 0.5 cm
+    detector layer behind the target (reached by bremsstrahlung photons
+    only), forced over analog, mixed precision, one run of n histories each."""
+    wl = W.workload("target_detector", n)
+    res = {}
+    for key, t in (("analog", wl["transport"]),
+                   ("forced", dict(wl["transport"], force_in=args.forcing[0], force_br=args.forcing[1],
+                                   split_br=args.split_br))):
+        sim = mcx.Simulator(mcx.MIXED, 0).setup(dict(wl, transport=t))
+        sim.set_launch(args.bank, 256, 128)  # forced emissions: tens of photons per history
+        run_steps(sim, n, [91], sync)
+        tt = run_steps(sim, n, [92], sync)[0]
+        q, q2 = sim.tally()
+        sim.close()
+        det_q, det_q2 = q[23], q2[23]
+        # variance of the mean energy per history in the first detector
+        # layer (Eq. (2) of the paper: histories are independent)
+        var = (det_q2 / n - (det_q / n) ** 2) / n
+        res[key] = dict(seconds=tt, mean_mev=det_q / n, var=var)
+    eff = (res["analog"]["var"] * res["analog"]["seconds"]) / (res["forced"]["var"] * res["forced"]["seconds"])
+    return dict(workload="target_detector: 2 MeV e- pencil, 1.5 cm water target, 10 cm air, 2 cm water detector",
+                histories=n, analog=res["analog"], forced=res["forced"], efficiency_gain=float(eff))
+
+
 def run_steps(sim, n, seeds, sync):
     times = []
     for s in seeds:
@@ -383,6 +408,8 @@ def main():
                                           high_dose_efficiency_vs_analog=float(eff),
                                           dose_vs_main=dict(z_rms=float(np.sqrt(np.mean(z ** 2))),
                                                             z_mean=float(np.mean(z))))
+    if args.forcing:
+        out["interaction_forcing"]["target_detector"] = target_detector_efficiency(mcx, W, sync, args)
     if args.materials:
         wm = W.workload("hetero_mm_128", n)
         sm = mcx.Simulator(mcx.MIXED, 0).setup(wm)

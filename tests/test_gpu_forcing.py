@@ -101,6 +101,24 @@ def test_forced_bremsstrahlung_rate():
     assert 18.5 < ratio < 21.5, ratio
 
 
+def test_forcing_reduces_the_variance_behind_a_target():
+    """2 MeV electrons stopped in a water target; only bremsstrahlung photons
+    reach the detector layers behind the air gap.  Forcing the emissions by
+    50 leaves the detector dose unchanged and cuts its variance per history
+    by more than 9."""
+    n = 1_000_000
+    wl = W.workload("target_detector", n)
+    a = gpu_run(wl, n, 1, test=False)
+    f = gpu_run(dict(wl, transport=dict(wl["transport"], force_br=50.0)), n, 1, test=False)
+    det = slice(23, 27)
+    da, sa = a["dose"][det].ravel(), a["sigma"][det].ravel()
+    df, sf = f["dose"][det].ravel(), f["sigma"][det].ravel()
+    print("detector dose", da, df, "sigma", sa, sf)
+    assert np.all(da > 0) and np.all(np.abs(da - df) <= 4 * np.hypot(sa, sf))
+    assert np.all(sf < sa / 3)
+    assert a["dose"][:3].sum() == pytest.approx(f["dose"][:3].sum(), rel=0.01)
+
+
 def test_forcing_refusals():
     mcx = _mcx()
     wl = layers(1, 10.0, 100)

@@ -217,4 +217,13 @@ def workload(name: str, n_hist: int | None = None) -> dict:
         return dict(name=name, phantom=hetero_mm_phantom(nn),
                     sources=[rect_field(0, 6.0, (12.8, 12.8, 0.0), (10.0, 10.0), n)],
                     transport=transport(10.0, 200), seed=1, material=WATER, materials=[WATER, BONE])
+    if name == "target_detector":
+        # 2 MeV electrons stopped in a 1.5 cm water target, a 10 cm air gap,
+        # a 2 cm water detector that only bremsstrahlung photons reach
+        # (layers of 0.5 cm, laterally 100 cm)
+        n = n_hist or 10_000_000
+        rho = [1.0] * 3 + [0.0012] * 20 + [1.0] * 4
+        return dict(name=name, phantom=slab_phantom(len(rho), 0.5, rho),
+                    sources=[pencil(1, 2.0, (50.0, 50.0, 0.0), n)],
+                    transport=transport(10.0, 200), seed=1, material=WATER)
     raise KeyError(name)
