@@ -144,6 +144,10 @@ def lib():
         L.orc_run_gradient.argtypes = [C.c_void_p, C.POINTER(Transport), C.POINTER(Phantom),
                                        C.POINTER(Source), C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
                                        dp, dp, dp, dp, dp]
+        L.orc_run_gradient_mm.restype = C.c_int
+        L.orc_run_gradient_mm.argtypes = [C.c_void_p, C.c_int, C.POINTER(Transport), C.POINTER(Phantom),
+                                          C.POINTER(Source), C.c_int, C.c_uint32, C.c_uint64, C.c_uint64,
+                                          dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -353,8 +357,13 @@ def gradient(tables: Tables, phantom: dict, sources, seed: int, first: int, n: i
     p = np.zeros(rho.size)
     sq = C.c_double(0.0)
     src = source_array(sources)
-    rc = lib().orc_run_gradient(tables.h, C.byref(tables.t), C.byref(ph), src, len(sources), seed, first, n,
-                                _dp(w), _dp(a), _dp(b), _dp(p), C.byref(sq))
+    if isinstance(tables, (list, tuple)):
+        arr = (C.c_void_p * len(tables))(*[tb.h for tb in tables])
+        rc = lib().orc_run_gradient_mm(arr, len(tables), C.byref(tables[0].t), C.byref(ph), src, len(sources), seed,
+                                       first, n, _dp(w), _dp(a), _dp(b), _dp(p), C.byref(sq))
+    else:
+        rc = lib().orc_run_gradient(tables.h, C.byref(tables.t), C.byref(ph), src, len(sources), seed, first, n,
+                                    _dp(w), _dp(a), _dp(b), _dp(p), C.byref(sq))
     if rc:
         raise RuntimeError(f"orc_run_gradient failed: {rc}")
     qbar = sq.value / n

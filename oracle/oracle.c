@@ -903,9 +903,12 @@ static int photon_flight_mm(ctx* c, part* p, double* mu, double* mt_out) {
     int64_t v = lin(c, p->ix);
     double att = c->ph->rho[v] * mtm[c->mat[v]];
     if (att * s >= tau) {
+      /* the flight ends inside this voxel: d ln p / d rho = -mu_m l + 1/rho */
+      if (c->w) score(c, v, -mtm[c->mat[v]] * (tau / att) + 1.0 / c->ph->rho[v]);
       move(p, tau / att);
       break;
     }
+    if (c->w) score(c, v, -mtm[c->mat[v]] * s);
     tau -= att * s;
     if (cross(c, p, s, a)) {
       st->escaped++;
@@ -1421,10 +1424,16 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
                      const orc_source* src, int n_src, uint32_t seed, uint64_t first,
                      uint64_t n, const double* w, double* a_acc, double* b_acc,
                      double* p_acc, double* sum_q_h) {
+  return orc_run_gradient_mm(&tb, 1, t, ph, src, n_src, seed, first, n, w, a_acc, b_acc, p_acc, sum_q_h);
+}
+
+int orc_run_gradient_mm(const orc_tables* const* tbs, int n_mat, const orc_transport* t, const orc_phantom* ph,
+                        const orc_source* src, int n_src, uint32_t seed, uint64_t first, uint64_t n,
+                        const double* w, double* a_acc, double* b_acc, double* p_acc, double* sum_q_h) {
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
   /* the estimator has no term for the score of a straggled soft loss, and
-   * the replays of the device path run the main step only */
-  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || ph->mat || t->force_in > 1.0 || t->force_br > 1.0 ||
+   * weighted particles are not scored */
+  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || t->force_in > 1.0 || t->force_br > 1.0 ||
       t->split_br == 2)
     return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
@@ -1432,7 +1441,7 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));
   orc_stats st;
   memset(&st, 0, sizeof(st));
-  int rc = run_body(&tb, 1, t, ph, src, n_src, seed, first, n, q, q2, &st, NULL, NULL, w, a_acc, b_acc,
+  int rc = run_body(tbs, n_mat, t, ph, src, n_src, seed, first, n, q, q2, &st, NULL, NULL, w, a_acc, b_acc,
                     p_acc, sum_q_h);
   free(q);
   free(q2);

@@ -203,6 +203,12 @@ int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_pha
                      const orc_source* src, int n_src, uint32_t seed, uint64_t first,
                      uint64_t n, const double* w, double* a_acc, double* b_acc,
                      double* p_acc, double* sum_q_h);
+/* The same with several materials (R10): the flight score of voxel j uses
+ * its material's mu_m(E), -mu_m l_j, and 1/rho_k where the flight ends;
+ * the soft-loss term uses the voxel's material's S_soft. */
+int orc_run_gradient_mm(const orc_tables* const* tbs, int n_mat, const orc_transport* t, const orc_phantom* ph,
+                        const orc_source* src, int n_src, uint32_t seed, uint64_t first, uint64_t n,
+                        const double* w, double* a_acc, double* b_acc, double* p_acc, double* sum_q_h);
 
 /* Dose (eV/g per history) and its standard error from the counters,
  * Eq. (1)-(3) with the square root of Eq. (2) restored. */

@@ -98,3 +98,46 @@ def test_kerma_mode_gradient_vs_crn_finite_differences():
         z = (mean[v] - fd) / math.sqrt(sem[v] ** 2 + fd_sem ** 2)
         print(v, mean[v], sem[v], fd, fd_sem, z)
         assert abs(z) < 4.0
+
+
+def test_two_material_layered_absorber_gradient_closed_form():
+    """Layers of water and bone (photoelectric only, electrons absorbed where
+    created): E[q_j] = E0 T_j (1 - e^{-mu_j rho_j dz}), T_j =
+    exp(-dz sum_{i<j} mu_i rho_i) with each layer's own mu_m; the gradient of
+    a linear dose loss is known exactly and the several-material score must
+    reproduce it."""
+    e0, dz = 0.03, 0.5
+    rho = np.array([1.0, 0.3, 1.8, 1.0, 0.5, 2.2, 1.0, 1.3, 0.26, 1.1])
+    mat = np.array([0, 0, 1, 0, 0, 1, 1, 0, 0, 1], dtype=np.uint8)
+    nz = rho.size
+    ph = W.slab_phantom(nz, dz, rho)
+    ph["mat"] = np.broadcast_to(mat[:, None, None], ph["rho"].shape).copy()
+    t = W.transport(flags=O.NO_COMPTON | O.NO_RAYLEIGH | O.NO_PAIR, eabs=(0.01, 1e9, 1e9))
+    tbs = [O.Tables(W.WATER, t), O.Tables(W.BONE, t)]
+    mu = np.array([tb.eval(O.MU_PHOTO, e0) for tb in tbs])[mat]
+    vol = 100.0 * 100.0 * dz
+    rng = np.random.default_rng(7)
+    c = rng.uniform(-1.0, 1.0, size=nz)
+    cum = np.concatenate([[0.0], np.cumsum(mu * rho * dz)])
+    T = np.exp(-cum[:-1])
+    a = 1.0 - np.exp(-mu * rho * dz)
+    D = e0 * T * a * 1e6 / (rho * vol)
+    exact = np.zeros(nz)
+    for k in range(nz):
+        for j in range(nz):
+            if k < j:
+                deq = e0 * (-mu[k] * dz) * T[j] * a[j]
+            elif k == j:
+                deq = e0 * T[j] * mu[j] * dz * math.exp(-mu[j] * rho[j] * dz)
+            else:
+                deq = 0.0
+            exact[k] += c[j] * (1e6 / (rho[j] * vol) * deq - (D[j] / rho[j] if k == j else 0.0))
+    src = [W.pencil(0, e0, (50.0, 50.0, 0.0), 20000)]
+    mean, sem = _grad_batches(tbs, ph, src, c.reshape(nz, 1, 1), 10, 20000)
+    z = (mean - exact) / sem
+    print("z", np.round(z, 2))
+    assert np.all(np.abs(z) < 4.5)
+    assert abs(z.mean()) < 1.5
+    # the one-material score (water's mu everywhere) misses the bone layers
+    wrong = O.Tables(W.WATER, t).eval(O.MU_PHOTO, e0)
+    assert mu.max() / wrong > 5.0
