@@ -262,12 +262,15 @@ int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, v
  * w_v = dL/dD_v * 1e6 / (rho_v V) and the local derivative of the soft energy
  * loss of electron/positron steps stopped by a voxel face; the second adds
  * (Q_h - mean Q) times the likelihood-ratio score of every photon free flight
- * (-mu l_j per traversed voxel, +1/rho at the interaction).  The explicit
+ * (-mu l_j per traversed voxel with mu of the voxel's material, +1/rho at
+ * the interaction).  The explicit
  * mass term -dL/dD_v D_v / rho_v completes the gradient.  Unbiased when
  * electrons are absorbed where they are created; with Class II transport the
  * downstream effect of density on electron tracks is not included.  Requires
  * that the tallies hold exactly one mcx_run since the last reset
- * (MCX_E_STATE otherwise).  The tallies and statistics are unchanged. */
+ * (MCX_E_STATE otherwise).  Runs with straggling, annihilation in flight,
+ * forcing or splitting are refused (MCX_E_UNSUPPORTED); several-material
+ * phantoms are supported.  The tallies and statistics are unchanged. */
 int mcx_dose_backward(mcx_ctx* ctx, const double* dl_ddose, double* dl_drho, int on_device, void* stream);
 
 /* Dose (eV/g per history) and its standard error per voxel from the

@@ -46,19 +46,24 @@ enum Flavor : int {
   FL_MM = 6,          // several materials (per-voxel index), with the optional physics
   FL_MM_TEST = 7,     // the same with the per-history test outputs
   FL_VR = 8,          // interaction forcing: weighted particles, with the optional physics
-  FL_VR_TEST = 9      // the same with the per-history test outputs
+  FL_VR_TEST = 9,     // the same with the per-history test outputs
+  FL_MM_ADJ_A = 10,   // the density-gradient replays on several-material phantoms
+  FL_MM_ADJ_B = 11
 };
-constexpr int kFlavors = 10;
+constexpr int kFlavors = 12;
 
 // the optional physics changes the e+- step only: the other kernels of an
 // extended flavour are those of the flavour without it; several materials
 // change the photon flight and interactions too
 constexpr int base_flavor(int f) {
-  return (f == FL_EXT || f == FL_MM || f == FL_VR) ? FL_FWD
-                                                   : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST) ? FL_TEST : f);
+  return (f == FL_EXT || f == FL_MM || f == FL_VR)
+             ? FL_FWD
+             : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST)
+                    ? FL_TEST
+                    : (f == FL_MM_ADJ_A ? FL_ADJ_A : (f == FL_MM_ADJ_B ? FL_ADJ_B : f)));
 }
 constexpr bool extended(int f) { return f >= FL_EXT; }
-constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST; }
+constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST || f == FL_MM_ADJ_A || f == FL_MM_ADJ_B; }
 // weighted particles: every kernel carries the weights
 constexpr bool weighted(int f) { return f == FL_VR || f == FL_VR_TEST; }
 constexpr int photon_flavor(int f) { return several(f) || weighted(f) ? f : base_flavor(f); }
@@ -315,6 +320,15 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
         mu[3] = interp(tab, nt, T_LMU_PP, g, e, a.tb.thr_pp);
         mt = mu[0] + mu[1] + mu[2] + mu[3];
       }
+      // replay B: mu of voxel vv's material (several materials), else mu
+      auto mu_of = [&](uint32_t vv) -> double {
+        if constexpr (MMF) {
+          const uint32_t m = a.mat[vv];
+          return double(m == 0u ? mtm[0] : (m == 1u ? mtm[1] : (m == 2u ? mtm[2] : mtm[3])));
+        } else {
+          return double(mt);
+        }
+      };
       auto att = [&](uint32_t vv) -> double {
         if constexpr (MMF) {
           const uint32_t m = a.mat[vv];
@@ -403,7 +417,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
                 const bool a1 = !a0 && m1 > 0 && (m2 <= 0 || u1 <= u2);
                 const bool a2 = !a0 && !a1;
                 const double uk = a0 ? u0 : (a1 ? u1 : u2);
-                unsafeAtomicAdd(&a.adj_grad[vlin(a, jx)], cq * (-mud * (uk - tc)));
+                unsafeAtomicAdd(&a.adj_grad[vlin(a, jx)], cq * (-(MMF ? mu_of(v) : mud) * (uk - tc)));
                 tc = uk;
                 u0 = a0 ? u0 + dt[0] : u0;
                 u1 = a1 ? u1 + dt[1] : u1;
@@ -475,8 +489,12 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
           const bool act = !ended;
           const bool hit = act & (rho * sj >= tau);
           const bool pass = act & !hit;
-          if (cq != 0.0 && act)
-            unsafeAtomicAdd(&a.adj_grad[vs[j]], hit ? cq * (-mud * (tau / rho) + 1.0 / rho) : cq * (-mud * sj));
+          if (cq != 0.0 && act) {
+            // several materials: rho here is rho mu_m, tau an optical depth
+            const double muj = MMF ? mu_of(vs[j]) : mud;
+            const double rj = MMF ? double(a.rho[vs[j]]) : rho;
+            unsafeAtomicAdd(&a.adj_grad[vs[j]], hit ? cq * (-muj * (tau / rho) + 1.0 / rj) : cq * (-muj * sj));
+          }
           t = hit ? t + tau / rho : (pass ? tend[j] : t);
           tau = pass ? tau - rho * sj : tau;
           p.ix[0] += (pass & (axs[j] == 0)) ? stp[0] : 0;

@@ -163,3 +163,62 @@ def test_autograd_function_quadratic_loss():
     sim.close()
     assert np.allclose(g, g2, rtol=1e-9, atol=1e-12 * np.abs(g2).max())
     assert np.isfinite(g).all() and np.abs(g).max() > 0
+
+
+def test_several_material_gradient_matches_oracle():
+    """The replays on a several-material phantom (the bone-sphere phantom,
+    kerma mode with full photon physics, then full Class II transport)
+    against the oracle's several-material score-function gradient on the
+    same histories; the layered water/bone absorber against its closed
+    form."""
+    rng = np.random.default_rng(11)
+    wl = dict(W.workload("hetero_mm_64", 4000))
+    wl["transport"] = W.transport(eabs=(0.01, 1e9, 1e9))
+    c = rng.uniform(-1, 1, size=wl["phantom"]["shape"])
+    tbs = [O.Tables(m, wl["transport"]) for m in wl["materials"]]
+    r = O.run(tbs, wl["phantom"], wl["sources"], 1, 0, 4000)
+    do, _ = O.dose(wl["phantom"], r)
+    go, _ = O.gradient(tbs, wl["phantom"], wl["sources"], 1, 0, 4000, c, do)
+    g, d, _ = gpu_grad(wl, 4000, c)
+    rel = np.abs(g - go) / np.abs(go).max()
+    print("several materials, kerma: voxels within 1e-9", np.mean(rel <= 1e-9), "max", rel.max())
+    assert np.mean(rel <= 1e-9) >= 0.99 and rel.max() < 0.05
+    wl = W.workload("hetero_mm_64", 2000)
+    tbs = [O.Tables(m, wl["transport"]) for m in wl["materials"]]
+    r = O.run(tbs, wl["phantom"], wl["sources"], 1, 0, 2000)
+    do, _ = O.dose(wl["phantom"], r)
+    go, _ = O.gradient(tbs, wl["phantom"], wl["sources"], 1, 0, 2000, c, do)
+    g, d, _ = gpu_grad(wl, 2000, c)
+    scale = np.abs(go).max()
+    rel = np.abs(g - go) / scale
+    print("several materials, Class II: voxels within 1e-6", np.mean(rel <= 1e-6), "max", rel.max())
+    assert np.mean(rel <= 1e-6) >= 0.98 and rel.max() < 0.05
+    # layered water/bone absorber, photoelectric only: closed form
+    e0, dz = 0.03, 0.5
+    rho = np.array([1.0, 0.3, 1.8, 1.0, 0.5, 2.2, 1.0, 1.3, 0.26, 1.1])
+    mat = np.array([0, 0, 1, 0, 0, 1, 1, 0, 0, 1], dtype=np.uint8)
+    nz = rho.size
+    ph = W.slab_phantom(nz, dz, rho)
+    ph["mat"] = np.broadcast_to(mat[:, None, None], ph["rho"].shape).copy()
+    t = W.transport(flags=O.NO_COMPTON | O.NO_RAYLEIGH | O.NO_PAIR, eabs=(0.01, 1e9, 1e9))
+    mu = np.array([O.Tables(m, t).eval(O.MU_PHOTO, e0) for m in (W.WATER, W.BONE)])[mat]
+    vol = 100.0 * 100.0 * dz
+    cz = rng.uniform(-1.0, 1.0, size=nz)
+    cum = np.concatenate([[0.0], np.cumsum(mu * rho * dz)])
+    T = np.exp(-cum[:-1])
+    a = 1.0 - np.exp(-mu * rho * dz)
+    D = e0 * T * a * 1e6 / (rho * vol)
+    exact = np.zeros(nz)
+    for k in range(nz):
+        for j in range(nz):
+            deq = (e0 * (-mu[k] * dz) * T[j] * a[j] if k < j else
+                   (e0 * T[j] * mu[j] * dz * math.exp(-mu[j] * rho[j] * dz) if k == j else 0.0))
+            exact[k] += cz[j] * (1e6 / (rho[j] * vol) * deq - (D[j] / rho[j] if k == j else 0.0))
+    n = 200_000
+    wl = dict(name="slab_mm", phantom=ph, transport=t, material=W.WATER, materials=[W.WATER, W.BONE],
+              sources=[W.pencil(0, e0, (50.0, 50.0, 0.0), n)], seed=1)
+    gs = np.array([gpu_grad(wl, n, cz.reshape(nz, 1, 1), seed=s)[0].ravel() for s in range(1, 9)])
+    mean, sem = gs.mean(0), gs.std(0, ddof=1) / math.sqrt(len(gs))
+    z = (mean - exact) / sem
+    print("z", np.round(z, 2))
+    assert np.all(np.abs(z) < 4.5)

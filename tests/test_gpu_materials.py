@@ -132,8 +132,8 @@ def test_several_materials_mixed_precision_and_refusals():
         sim.run(wl["seed"], 0, 100)  # bone (1) not loaded
     sim.load_material(W.BONE, 1)
     sim.run(wl["seed"], 0, 100)
-    with pytest.raises(mcx.MCXError, match="UNSUPPORTED"):
-        sim.dose_backward(np.zeros(sim.shape))
+    g = sim.dose_backward(np.zeros(sim.shape))  # the replays run on several materials too
+    assert g.shape == tuple(sim.shape) and np.all(g == 0.0)
     with pytest.raises(mcx.MCXError):
         sim.load_material(W.BONE, 4)
     sim.close()
