@@ -141,3 +141,35 @@ def test_forcing_refusals():
     with pytest.raises(mcx.MCXError, match="UNSUPPORTED"):
         sim.run(mm["seed"], 0, 100)
     sim.close()
+
+
+def test_full_size_sampled_histories_forced_and_split():
+    """The forced workload the benchmark times (1e7 histories of the 6 MeV
+    field on the 128^3 heterogeneous phantom, hard collisions forced by 4,
+    bremsstrahlung by 20 and split by 2; 2^26 records per queue, blocks of
+    256, 128 steps per visit), FP64: a sample of histories over the whole
+    range re-run one by one by the oracle with the same forcing."""
+    mcx = _mcx()
+    wl = W.workload("hetero_broad_128")
+    wl["transport"] = dict(wl["transport"], force_in=4.0, force_br=20.0, split_br=2)
+    n = wl["sources"][0]["n_hist"]
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.set_launch(1 << 26, 256, 128)
+    sim.set_test_mode(True)
+    sim.run(wl["seed"], 0, n)
+    h, led = sim.history_results(n)
+    st = sim.stats()
+    sim.close()
+    assert st["histories"] == n
+    tb = O.Tables(wl["material"], wl["transport"])
+    sample = np.sort(np.random.default_rng(13).choice(n, size=200, replace=False))
+    same = 0
+    for k in sample:
+        r = O.run(tb, wl["phantom"], wl["sources"], wl["seed"], int(k), 1, hashes=True, ledger=True)
+        if r.hashes[0] == h[k]:
+            same += 1
+            assert np.allclose(led[k], r.ledger[0][[0, 1, 2]], rtol=0, atol=1e-8), int(k)
+    print("sampled identical hashes", same, "of", len(sample))
+    assert same >= 0.99 * len(sample)
+    bal = led[:, 0] + led[:, 1] + 2 * MC2 * led[:, 2]
+    assert abs(bal.mean() - 6.0) <= 5 * bal.std(ddof=1) / np.sqrt(n)

@@ -137,3 +137,33 @@ def test_several_materials_mixed_precision_and_refusals():
     with pytest.raises(mcx.MCXError):
         sim.load_material(W.BONE, 4)
     sim.close()
+
+
+def test_full_size_sampled_histories_several_materials():
+    """The several-material workload the benchmark times (1e7 histories of
+    the 6 MeV field on the 128^3 phantom with bone spheres of the second
+    material, 2^26 records per queue, blocks of 256, 128 steps per visit),
+    FP64: a sample of histories over the whole range re-run one by one by
+    the oracle; every history conserves energy."""
+    mcx = _mcx()
+    wl = W.workload("hetero_mm_128")
+    n = wl["sources"][0]["n_hist"]
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.set_launch(1 << 26, 256, 128)
+    sim.set_test_mode(True)
+    sim.run(wl["seed"], 0, n)
+    h, led = sim.history_results(n)
+    st = sim.stats()
+    sim.close()
+    assert st["histories"] == n
+    check_balance(led, 6.0, 1e-12)
+    tbs = [O.Tables(m, wl["transport"]) for m in wl["materials"]]
+    sample = np.sort(np.random.default_rng(12).choice(n, size=200, replace=False))
+    same = 0
+    for k in sample:
+        r = O.run(tbs, wl["phantom"], wl["sources"], wl["seed"], int(k), 1, hashes=True, ledger=True)
+        if r.hashes[0] == h[k]:
+            same += 1
+            assert np.allclose(led[k], r.ledger[0][[0, 1, 2]], rtol=0, atol=1e-8), int(k)
+    print("sampled identical hashes", same, "of", len(sample))
+    assert same >= 0.99 * len(sample)
