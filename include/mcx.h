@@ -126,7 +126,8 @@ typedef struct {
    * expectation is unchanged while F times more secondaries are produced.
    * 0 or 1 = analog; otherwise F in [1, 1e5] (MCX_E_INVALID if not).
    * Runs on one-material phantoms (mcx_run returns MCX_E_UNSUPPORTED with a
-   * material index array) and not in mcx_dose_backward. */
+   * material index array); mcx_dose_backward weights the deposits and
+   * soft-loss terms (the photon-flight scores are the analog ones). */
   double force_in, force_br;
   /* Bremsstrahlung splitting (the same example splits emitted photons by 2):
    * with split_br = 2 each emission yields two photons of the sampled energy,
@@ -268,9 +269,9 @@ int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, v
  * electrons are absorbed where they are created; with Class II transport the
  * downstream effect of density on electron tracks is not included.  Requires
  * that the tallies hold exactly one mcx_run since the last reset
- * (MCX_E_STATE otherwise).  Runs with straggling, annihilation in flight,
- * forcing or splitting are refused (MCX_E_UNSUPPORTED); several-material
- * phantoms are supported.  The tallies and statistics are unchanged. */
+ * (MCX_E_STATE otherwise).  Runs with straggling or annihilation in flight
+ * are refused (MCX_E_UNSUPPORTED); several-material phantoms, forcing and
+ * splitting are supported.  The tallies and statistics are unchanged. */
 int mcx_dose_backward(mcx_ctx* ctx, const double* dl_ddose, double* dl_drho, int on_device, void* stream);
 
 /* Dose (eV/g per history) and its standard error per voxel from the

@@ -1228,7 +1228,7 @@ static void electron_track(ctx* c, part* p) {
       deposit(c, p, e - e1);
       c->led[ORC_LED_PATH] += rho * db;
       /* loss over the geometric length db: d(E - E')/d rho = db S_soft(E') */
-      if (c->w && e1 < e) c->p_acc[v] += c->w[v] * db * interp(tb, tb->el[ti][CH_S], 0.0, e1);
+      if (c->w && e1 < e) c->p_acc[v] += c->w[v] * db * interp(tb, tb->el[ti][CH_S], 0.0, e1) * p->w;
       p->e = e1;
       event(c, p, EV_CROSS, v);
       if (cross(c, p, db, a)) { e_escape(c, p, v); return; }
@@ -1431,11 +1431,10 @@ int orc_run_gradient_mm(const orc_tables* const* tbs, int n_mat, const orc_trans
                         const orc_source* src, int n_src, uint32_t seed, uint64_t first, uint64_t n,
                         const double* w, double* a_acc, double* b_acc, double* p_acc, double* sum_q_h) {
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
-  /* the estimator has no term for the score of a straggled soft loss, and
-   * weighted particles are not scored */
-  if ((t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) || t->force_in > 1.0 || t->force_br > 1.0 ||
-      t->split_br == 2)
-    return -4;
+  /* the estimator has no term for the score of a straggled soft loss; with
+   * forcing or splitting (R11, R12) the scores are those of the analog
+   * photon flights, the deposits and the soft-loss term carry the weights */
+  if (t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));

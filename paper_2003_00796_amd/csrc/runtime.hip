@@ -341,7 +341,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
   a.annih = (mode == 0 && (c->tr.flags & MCX_ANNIH_FLIGHT)) ? 1 : 0;
   a.mm = c->d_vmat.p ? 1 : 0;
-  a.vr = (mode == 0 && weighted_run(c->tr)) ? 1 : 0;
+  a.vr = weighted_run(c->tr) ? 1 : 0;
   a.split_br = c->tr.split_br == 2 ? 2 : 1;
   a.f_in = c->tr.force_in > 1.0 ? c->tr.force_in : 1.0;
   a.f_br = c->tr.force_br > 1.0 ? c->tr.force_br : 1.0;
@@ -990,9 +990,8 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
-  if ((c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT)) || weighted_run(c->tr))
-    return fail(c, MCX_E_UNSUPPORTED,
-                "the gradient replays run without straggling, annihilation in flight, forcing and splitting");
+  if (c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT))
+    return fail(c, MCX_E_UNSUPPORTED, "the gradient replays run without straggling and annihilation in flight");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

@@ -48,9 +48,11 @@ enum Flavor : int {
   FL_VR = 8,          // interaction forcing: weighted particles, with the optional physics
   FL_VR_TEST = 9,     // the same with the per-history test outputs
   FL_MM_ADJ_A = 10,   // the density-gradient replays on several-material phantoms
-  FL_MM_ADJ_B = 11
+  FL_MM_ADJ_B = 11,
+  FL_VR_ADJ_A = 12,   // the density-gradient replays with weighted particles
+  FL_VR_ADJ_B = 13
 };
-constexpr int kFlavors = 12;
+constexpr int kFlavors = 14;
 
 // the optional physics changes the e+- step only: the other kernels of an
 // extended flavour are those of the flavour without it; several materials
@@ -60,12 +62,13 @@ constexpr int base_flavor(int f) {
              ? FL_FWD
              : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST)
                     ? FL_TEST
-                    : (f == FL_MM_ADJ_A ? FL_ADJ_A : (f == FL_MM_ADJ_B ? FL_ADJ_B : f)));
+                    : ((f == FL_MM_ADJ_A || f == FL_VR_ADJ_A) ? FL_ADJ_A
+                                                              : ((f == FL_MM_ADJ_B || f == FL_VR_ADJ_B) ? FL_ADJ_B : f)));
 }
 constexpr bool extended(int f) { return f >= FL_EXT; }
 constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST || f == FL_MM_ADJ_A || f == FL_MM_ADJ_B; }
 // weighted particles: every kernel carries the weights
-constexpr bool weighted(int f) { return f == FL_VR || f == FL_VR_TEST; }
+constexpr bool weighted(int f) { return f == FL_VR || f == FL_VR_TEST || f == FL_VR_ADJ_A || f == FL_VR_ADJ_B; }
 constexpr int photon_flavor(int f) { return several(f) || weighted(f) ? f : base_flavor(f); }
 constexpr int source_flavor(int f) { return weighted(f) ? f : base_flavor(f); }
 
@@ -876,7 +879,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
       // replay A: d(loss over the geometric length db)/d rho = db S_soft(E')
       const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
       const T s1 = interp(tab, nt, base + O_LS, g1, e1, T(0));
-      unsafeAtomicAdd(&a.adj_grad[v], a.adj_w[v] * db * double(s1));
+      unsafeAtomicAdd(&a.adj_grad[v], a.adj_w[v] * db * double(s1) * (a.vr ? p.w : 1.0));
     }
     event(a, p, EV_CROSS, v);
     if (cross(a, p, db, ax, ls)) {
