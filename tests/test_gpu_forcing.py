@@ -189,3 +189,28 @@ def test_full_size_sampled_histories_forced_and_split():
     assert same >= 0.99 * len(sample)
     bal = led[:, 0] + led[:, 1] + 2 * MC2 * led[:, 2]
     assert abs(bal.mean() - 6.0) <= 5 * bal.std(ddof=1) / np.sqrt(n)
+
+
+def test_forced_runs_split_merge_and_influence():
+    """Weighted runs keep the run-control invariants: two partial runs give
+    the tallies of one run (FP64 summation order aside), and the
+    per-beamlet influence entries add up to the weighted tallies."""
+    mcx = _mcx()
+    wl = layers(0, 6.0, 6000, split_br=2)
+    wl["sources"] = [W.pencil(0, 6.0, (50.0, 50.0, 0.0), 2500), W.pencil(0, 2.0, (50.0, 50.0, 0.0), 3500)]
+    one = mcx.Simulator(0, 0).setup(wl)
+    one.run(wl["seed"], 0, 6000)
+    q1, s1 = one.tally()
+    one.close()
+    two = mcx.Simulator(0, 0).setup(wl)
+    two.set_influence(True, 16)
+    two.run(wl["seed"], 0, 2000)
+    two.run(wl["seed"], 2000, 4000)
+    q2, s2 = two.tally()
+    src, vox, iq, iq2 = two.influence()
+    two.close()
+    assert np.allclose(q1, q2, rtol=1e-11, atol=1e-14) and np.allclose(s1, s2, rtol=1e-11, atol=1e-14)
+    tot = np.zeros(q2.size)
+    np.add.at(tot, vox.astype(np.int64), iq)
+    assert set(np.unique(src)) == {0, 1}
+    assert np.allclose(tot, q2, rtol=1e-11, atol=1e-14)
