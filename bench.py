@@ -93,7 +93,9 @@ def roofline(st: dict) -> dict:
     out.update(bound="alu", achieved=wi / avg_s / 1e9, peak=VALU_ISSUE_PEAK, unit="G VALU wave-instr/s",
                frac=wi / avg_s / 1e9 / VALU_ISSUE_PEAK, traffic=traffic,
                valu_wave_instr_per_estep=prof["valu_wave_instr_per_estep"],
-               valu_lane_utilisation=prof["valu_lane_utilisation"], hbm=hbm)
+               valu_lane_utilisation=prof["valu_lane_utilisation"], hbm=hbm,
+               valu_lane_utilisation_per_kernel={k: v["lane_utilisation"] for k, v in
+                                                 prof.get("valu_lane_utilisation_per_kernel", {}).items()})
     return out
 
 
