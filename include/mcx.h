@@ -83,8 +83,7 @@ extern "C" {
  * (bounded over a step by its value at the step's lowest energy, since it
  * falls with energy); the softer photon's share of E + 2mc^2 is drawn from
  * Heitler's DCS and both photon directions follow from energy and momentum
- * conservation.  Off by default (positrons then annihilate at rest only);
- * not supported by mcx_dose_backward. */
+ * conservation.  Off by default (positrons then annihilate at rest only). */
 #define MCX_ANNIH_FLIGHT (1u << 8)
 
 typedef struct mcx_ctx mcx_ctx;
@@ -269,9 +268,10 @@ int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, v
  * electrons are absorbed where they are created; with Class II transport the
  * downstream effect of density on electron tracks is not included.  Requires
  * that the tallies hold exactly one mcx_run since the last reset
- * (MCX_E_STATE otherwise).  Runs with straggling or annihilation in flight
- * are refused (MCX_E_UNSUPPORTED); several-material phantoms, forcing and
- * splitting are supported.  The tallies and statistics are unchanged. */
+ * (MCX_E_STATE otherwise).  Runs with straggling are refused
+ * (MCX_E_UNSUPPORTED: the estimator has no term for a straggled loss);
+ * annihilation in flight (an unscored e+ hard event like the others),
+ * several-material phantoms, forcing and splitting are supported.  The tallies and statistics are unchanged. */
 int mcx_dose_backward(mcx_ctx* ctx, const double* dl_ddose, double* dl_drho, int on_device, void* stream);
 
 /* Dose (eV/g per history) and its standard error per voxel from the

@@ -1433,8 +1433,10 @@ int orc_run_gradient_mm(const orc_tables* const* tbs, int n_mat, const orc_trans
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
   /* the estimator has no term for the score of a straggled soft loss; with
    * forcing or splitting (R11, R12) the scores are those of the analog
-   * photon flights, the deposits and the soft-loss term carry the weights */
-  if (t->flags & (ORC_STRAGGLING | ORC_ANNIH_FLIGHT)) return -4;
+   * photon flights, the deposits and the soft-loss term carry the weights;
+   * annihilation in flight (R9) is an e+ hard event like the others, which
+   * the estimator does not score */
+  if (t->flags & ORC_STRAGGLING) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));
   double* q2 = (double*)calloc((size_t)nv, sizeof(double));

@@ -34,11 +34,13 @@ hipError_t launch_iteration(const KArgs<double>& a, int par, uint32_t target, in
   if (a.mode == 1)
     return a.mm ? launch_flavor<FL_MM_ADJ_A>(a, par, target, grid, block, s, ev)
                 : (a.vr ? launch_flavor<FL_VR_ADJ_A>(a, par, target, grid, block, s, ev)
-                        : launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev));
+                        : (a.annih ? launch_flavor<FL_EXT_ADJ_A>(a, par, target, grid, block, s, ev)
+                                   : launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev)));
   if (a.mode == 2)
     return a.mm ? launch_flavor<FL_MM_ADJ_B>(a, par, target, grid, block, s, ev)
                 : (a.vr ? launch_flavor<FL_VR_ADJ_B>(a, par, target, grid, block, s, ev)
-                        : launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev));
+                        : (a.annih ? launch_flavor<FL_EXT_ADJ_B>(a, par, target, grid, block, s, ev)
+                                   : launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev)));
   if (a.vr)
     return a.test_mode ? launch_flavor<FL_VR_TEST>(a, par, target, grid, block, s, ev)
                        : launch_flavor<FL_VR>(a, par, target, grid, block, s, ev);
@@ -94,7 +96,9 @@ hipError_t configure_fp64(int n_grid) {
                              reinterpret_cast<const void*>(&k_estep<double, FL_MM_ADJ_A>),
                              reinterpret_cast<const void*>(&k_estep<double, FL_MM_ADJ_B>),
                              reinterpret_cast<const void*>(&k_estep<double, FL_VR_ADJ_A>),
-                             reinterpret_cast<const void*>(&k_estep<double, FL_VR_ADJ_B>)};
+                             reinterpret_cast<const void*>(&k_estep<double, FL_VR_ADJ_B>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_EXT_ADJ_A>),
+                             reinterpret_cast<const void*>(&k_estep<double, FL_EXT_ADJ_B>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

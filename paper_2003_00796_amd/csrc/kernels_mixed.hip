@@ -42,11 +42,13 @@ hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int
   if (a.mode == 1)
     return a.mm ? launch_flavor<FL_MM_ADJ_A>(a, par, target, grid, block, s, ev)
                 : (a.vr ? launch_flavor<FL_VR_ADJ_A>(a, par, target, grid, block, s, ev)
-                        : launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev));
+                        : (a.annih ? launch_flavor<FL_EXT_ADJ_A>(a, par, target, grid, block, s, ev)
+                                   : launch_flavor<FL_ADJ_A>(a, par, target, grid, block, s, ev)));
   if (a.mode == 2)
     return a.mm ? launch_flavor<FL_MM_ADJ_B>(a, par, target, grid, block, s, ev)
                 : (a.vr ? launch_flavor<FL_VR_ADJ_B>(a, par, target, grid, block, s, ev)
-                        : launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev));
+                        : (a.annih ? launch_flavor<FL_EXT_ADJ_B>(a, par, target, grid, block, s, ev)
+                                   : launch_flavor<FL_ADJ_B>(a, par, target, grid, block, s, ev)));
   if (a.vr)
     return a.test_mode ? launch_flavor<FL_VR_TEST>(a, par, target, grid, block, s, ev)
                        : launch_flavor<FL_VR>(a, par, target, grid, block, s, ev);
@@ -88,7 +90,9 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
                              reinterpret_cast<const void*>(&k_estep<float, FL_MM_ADJ_A>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_MM_ADJ_B>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_VR_ADJ_A>),
-                             reinterpret_cast<const void*>(&k_estep<float, FL_VR_ADJ_B>)};
+                             reinterpret_cast<const void*>(&k_estep<float, FL_VR_ADJ_B>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_ADJ_A>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_ADJ_B>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

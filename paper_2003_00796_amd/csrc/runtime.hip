@@ -338,8 +338,8 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.cap = c->cap;
   a.steps = c->steps;
   a.mode = mode;
-  a.straggle = (mode == 0 && (c->tr.flags & MCX_STRAGGLING)) ? 1 : 0;
-  a.annih = (mode == 0 && (c->tr.flags & MCX_ANNIH_FLIGHT)) ? 1 : 0;
+  a.straggle = (c->tr.flags & MCX_STRAGGLING) ? 1 : 0;
+  a.annih = (c->tr.flags & MCX_ANNIH_FLIGHT) ? 1 : 0;
   a.mm = c->d_vmat.p ? 1 : 0;
   a.vr = weighted_run(c->tr) ? 1 : 0;
   a.split_br = c->tr.split_br == 2 ? 2 : 1;
@@ -990,8 +990,8 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
   if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
-  if (c->tr.flags & (MCX_STRAGGLING | MCX_ANNIH_FLIGHT))
-    return fail(c, MCX_E_UNSUPPORTED, "the gradient replays run without straggling and annihilation in flight");
+  if (c->tr.flags & MCX_STRAGGLING)
+    return fail(c, MCX_E_UNSUPPORTED, "the gradient has no term for a straggled soft loss");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   const uint64_t nv = nvox(c), n = c->run_n;

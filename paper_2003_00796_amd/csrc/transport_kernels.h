@@ -50,9 +50,11 @@ enum Flavor : int {
   FL_MM_ADJ_A = 10,   // the density-gradient replays on several-material phantoms
   FL_MM_ADJ_B = 11,
   FL_VR_ADJ_A = 12,   // the density-gradient replays with weighted particles
-  FL_VR_ADJ_B = 13
+  FL_VR_ADJ_B = 13,
+  FL_EXT_ADJ_A = 14,  // the density-gradient replays with annihilation in flight
+  FL_EXT_ADJ_B = 15
 };
-constexpr int kFlavors = 14;
+constexpr int kFlavors = 16;
 
 // the optional physics changes the e+- step only: the other kernels of an
 // extended flavour are those of the flavour without it; several materials
@@ -62,8 +64,9 @@ constexpr int base_flavor(int f) {
              ? FL_FWD
              : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST)
                     ? FL_TEST
-                    : ((f == FL_MM_ADJ_A || f == FL_VR_ADJ_A) ? FL_ADJ_A
-                                                              : ((f == FL_MM_ADJ_B || f == FL_VR_ADJ_B) ? FL_ADJ_B : f)));
+                    : ((f == FL_MM_ADJ_A || f == FL_VR_ADJ_A || f == FL_EXT_ADJ_A)
+                           ? FL_ADJ_A
+                           : ((f == FL_MM_ADJ_B || f == FL_VR_ADJ_B || f == FL_EXT_ADJ_B) ? FL_ADJ_B : f)));
 }
 constexpr bool extended(int f) { return f >= FL_EXT; }
 constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST || f == FL_MM_ADJ_A || f == FL_MM_ADJ_B; }

@@ -139,9 +139,22 @@ def test_annihilation_majorant_and_conservation(flags):
         assert np.max(np.abs(bal - etot)) <= 1e-12 * etot
 
 
-def test_gradient_refuses_annihilation_in_flight():
-    t = W.transport(flags=O.ANNIH_FLIGHT)
-    tb = O.Tables(W.WATER, t)
+def test_gradient_with_annihilation_in_flight():
+    """The gradient accepts annihilation in flight (an e+ hard event, which
+    the estimator does not score) and refuses straggling.  With e+- absorbed
+    where they are created no positron flies, so the flag changes nothing:
+    the gradient is the one without it, bit for bit."""
     ph = W.water_cube(8, 8.0)
-    with pytest.raises(Exception):
-        O.gradient(tb, ph, [W.pencil(0, 1.0, (4, 4, 0), 10)], 1, 0, 10, np.ones((8, 8, 8)))
+    ph["rho"] = np.random.default_rng(2).uniform(0.5, 1.8, size=ph["rho"].shape)
+    src = [W.pencil(0, 8.0, (4.0, 4.0, 0.0), 2000)]
+    c = np.random.default_rng(3).uniform(-1, 1, size=ph["rho"].shape)
+    out = []
+    for flags in (0, O.ANNIH_FLIGHT):
+        tb = O.Tables(W.WATER, W.transport(flags=flags, eabs=(0.01, 1e9, 1e9)))
+        r = O.run(tb, ph, src, 1, 0, 2000)
+        d, _ = O.dose(ph, r)
+        out.append(O.gradient(tb, ph, src, 1, 0, 2000, c, d)[0])
+    assert np.array_equal(out[0], out[1])
+    tb = O.Tables(W.WATER, W.transport(flags=O.STRAGGLING))
+    with pytest.raises(RuntimeError):
+        O.gradient(tb, ph, src, 1, 0, 10, c, c)
