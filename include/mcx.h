@@ -355,12 +355,12 @@ int mcx_checkpoint(mcx_ctx* ctx, void* buf, size_t* size);
  * gradient needs a run of its own context (MCX_E_STATE until then). */
 int mcx_restore(mcx_ctx* ctx, const void* buf, size_t size);
 
-/* Device bytes a run needs besides the tallies, tables and phantom: the
- * event queues of the current bank size, the loop counters and the
+/* Device bytes a run needs besides the tallies, tables, phantom and loop
+ * counters: the event queues of the current bank size and the
  * (history, voxel) tally table at its full 2^29 slots (16 B each). */
 int mcx_workspace_size(mcx_ctx* ctx, size_t* bytes);
 /* Run in caller-owned device memory (e.g. a torch tensor) instead of memory
- * the library allocates: queues, loop counters and tally table are carved
+ * the library allocates: the queues and the tally table are carved
  * from [dev, dev + bytes), dev 256-byte aligned (MCX_E_INVALID otherwise).
  * The table takes the largest power-of-two number of slots, up to 2^29, that
  * fits after the queues; chunks of histories are sized to it.  bytes must
@@ -373,6 +373,30 @@ int mcx_workspace_size(mcx_ctx* ctx, size_t* bytes);
  * Statistics are kept across the change.  The per-history test outputs and
  * the gradient's buffers are still allocated by the library. */
 int mcx_set_workspace(mcx_ctx* ctx, void* dev, size_t bytes);
+
+/* Size of the fixed device array of mcx_run_static (per device). */
+#define MCX_STATIC_SCRATCH_BYTES (72ull << 20)
+/* mcx_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * transports the same histories into the same tallies as mcx_run (the same
+ * events for a given (seed, history range); the sums differ only in the
+ * order of FP64 additions), but its event queues and (history, voxel) tally
+ * table live in a fixed device array of MCX_STATIC_SCRATCH_BYTES that the
+ * library declares statically, one per device, held until the process ends;
+ * the call itself allocates nothing (no hipMalloc, no host pinning, no HIP
+ * graph: its kernels are launched one by one on `stream`).  The bank is the
+ * configured one (mcx_set_launch), at most 2^16 records; the table takes the
+ * largest power-of-two number of slots that fits after the queues (2^20 in
+ * FP64, 2^21 in MIXED precision at the largest bank), and chunks of
+ * histories are sized to it.  Limits: a chunk whose (history, voxel) pairs
+ * do not fit the table, or a population that fills the queues, fails with
+ * MCX_E_RANGE; test mode is refused with MCX_E_UNSUPPORTED (its per-history
+ * outputs are sized by the run).  Every call on a device shares that
+ * device's array, which keeps the last call's contents (each call clears the
+ * table it uses): calls that overlap on one device race and give wrong
+ * tallies, so a caller serialises them (one context on one host thread, or
+ * one stream).  Other arguments, results and errors as for mcx_run. */
+int mcx_run_static(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, void* stream);
 
 /* Per-history results of the LAST mcx_run (test mode only, else
  * MCX_E_STATE): hashes[n_hist] = order-independent hash of the history's

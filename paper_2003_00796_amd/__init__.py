@@ -35,7 +35,8 @@ ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport
                "mcx_get_dose", "mcx_get_tally", "mcx_reset_tallies", "mcx_get_stats",
                "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune",
                "mcx_synchronize", "mcx_cancel", "mcx_checkpoint", "mcx_restore", "mcx_workspace_size",
-               "mcx_set_workspace", "mcx_set_influence", "mcx_get_influence", "mcx_ct_to_phantom")
+               "mcx_set_workspace", "mcx_set_influence", "mcx_get_influence", "mcx_ct_to_phantom",
+               "mcx_run_static")
 
 
 class MaterialDesc(C.Structure):
@@ -148,6 +149,7 @@ def lib():
         L.mcx_set_test_mode.argtypes = [vp, C.c_int]
         L.mcx_set_timing.argtypes = [vp, C.c_int]
         L.mcx_run.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp]
+        L.mcx_run_static.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp]
         L.mcx_get_dose.argtypes = [vp, vp, vp, C.c_int, vp]
         L.mcx_get_tally.argtypes = [vp, vp, vp, C.c_int, vp]
         L.mcx_reset_tallies.argtypes = [vp]
@@ -306,6 +308,16 @@ class Simulator:
             msg = self._L.mcx_last_error(self._h).decode(errors="replace")
             raise MCXCancelled(f"run: MCX_E_CANCELLED: {msg}", self.stats()["next_history"])
         self._check(rc, "run")
+
+    def run_static(self, seed: int, first: int, n: int, stream=None):
+        """Histories [first, first + n) in the library's fixed device array
+        (mcx_run_static: the call allocates nothing)."""
+        sp = C.c_void_p(stream) if stream else None
+        rc = self._L.mcx_run_static(self._h, seed, first, n, sp)
+        if rc == -6:
+            msg = self._L.mcx_last_error(self._h).decode(errors="replace")
+            raise MCXCancelled(f"run_static: MCX_E_CANCELLED: {msg}", self.stats()["next_history"])
+        self._check(rc, "run_static")
 
     def cancel(self):
         """Ask the run in progress (or the next one) to stop; thread-safe."""

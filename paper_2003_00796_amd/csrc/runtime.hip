@@ -15,6 +15,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -202,11 +203,11 @@ constexpr uint64_t kTableSlots = 1ull << MCX_TALLY_LOG2;  // library-owned table
 constexpr uint64_t kMinWsSlots = 1ull << 20;              // smallest table in a workspace
 constexpr size_t kSlotBytes = sizeof(uint64_t) + sizeof(double);
 
-// queues and counters of a workspace carve (the table follows them)
-size_t ws_fixed_bytes(const mcx_ctx* c) { return align256(queue_bytes(c)) + align256(sizeof(Counters)); }
+// queues of a workspace carve (the table follows them)
+size_t ws_fixed_bytes(const mcx_ctx* c) { return align256(queue_bytes(c)); }
 
-// carve queues, counters and the largest power-of-two tally table that fits
-// from the caller's workspace, and clear counters and table
+// carve the queues and the largest power-of-two tally table that fits from
+// the caller's workspace, and clear the table
 int carve_workspace(mcx_ctx* c) {
   const size_t fixed = ws_fixed_bytes(c);
   if (c->ws_bytes < fixed + kMinWsSlots * kSlotBytes)
@@ -218,14 +219,12 @@ int carve_workspace(mcx_ctx* c) {
   char* base = static_cast<char*>(c->ws);
   const size_t qb = align256(queue_bytes(c));
   c->d_queues = DevBuf{base, qb, true};
-  c->d_cnt = DevBuf{base + qb, sizeof(Counters), true};
   c->d_hkeys = DevBuf{base + fixed, slots * sizeof(uint64_t), true};
   c->d_hvals = DevBuf{base + fixed + slots * sizeof(uint64_t), slots * sizeof(double), true};
   c->hslots = slots;
   c->queue_cap_built = c->cap;
   c->ws_cap = c->cap;
-  hipError_t e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d_hkeys.p, 0xFF, slots * sizeof(uint64_t), c->stream);
+  hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, slots * sizeof(uint64_t), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, slots * sizeof(double), c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "clear workspace");
@@ -235,17 +234,8 @@ int carve_workspace(mcx_ctx* c) {
 
 int ensure_workspace(mcx_ctx* c) {
   int rc;
-  if (c->ws && c->ws_cap != c->cap) {
-    // a new bank size moves everything after the queues: carry the
-    // statistics counters over
-    Counters saved;
-    const bool have_cnt = c->d_cnt.p != nullptr;
-    if (have_cnt && hipMemcpy(&saved, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(c, MCX_E_DEVICE, "read statistics");
-    if ((rc = carve_workspace(c))) return rc;
-    if (have_cnt && hipMemcpy(c->d_cnt.p, &saved, sizeof(Counters), hipMemcpyHostToDevice) != hipSuccess)
-      return fail(c, MCX_E_DEVICE, "restore statistics");
-  }
+  // a new bank size moves the table that follows the queues
+  if (c->ws && c->ws_cap != c->cap && (rc = carve_workspace(c))) return rc;
   if (!c->ws && (c->queue_cap_built != c->cap || !c->d_queues.p)) {
     dfree(c->d_queues);
     if ((rc = dalloc(c, c->d_queues, queue_bytes(c), "event queues"))) return rc;
@@ -254,16 +244,6 @@ int ensure_workspace(mcx_ctx* c) {
   // fresh allocations are cleared on the context's stream (non-blocking, so
   // it does not order against the null stream) and waited for: reused device
   // memory may still hold an earlier context's entries
-  if (!c->d_cnt.p) {
-    if ((rc = dalloc(c, c->d_cnt, sizeof(Counters), "counters"))) return rc;
-    hipError_t e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "clear counters");
-  }
-  if (!c->h_cnt) {
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->h_cnt), sizeof(Counters), hipHostMallocDefault);
-    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc counters");
-  }
   if (!c->d_hkeys.p) {
     if ((rc = dalloc(c, c->d_hkeys, c->hslots * sizeof(uint64_t), "tally keys"))) return rc;
     if ((rc = dalloc(c, c->d_hvals, c->hslots * sizeof(double), "tally values"))) return rc;
@@ -382,7 +362,7 @@ size_t ckpt_bytes(const mcx_ctx* c) { return sizeof(CkptHeader) + 2 * nvox(c) * 
 // cancellation request (then MCX_E_CANCELLED).
 template <typename T>
 int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t s, int mode = 0,
-             double qbar = 0.0, uint64_t* completed = nullptr) {
+             double qbar = 0.0, uint64_t* completed = nullptr, bool allow_graph = true) {
   if (completed) *completed = 0;
   KArgs<T> a;
   fill_args(c, a, seed, mode, qbar);
@@ -412,7 +392,7 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   // kBatch iterations (parities 0, 1, 0, ...) captured once per run: a batch
   // is then one graph launch; kBatch is even, so every batch starts at parity 0
   hipGraphExec_t gexec = nullptr;
-  const bool use_graph = c->use_graph && !c->timing;
+  const bool use_graph = allow_graph && c->use_graph && !c->timing;
   if (use_graph) {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -532,6 +512,89 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   return MCX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of mcx_run_static, for callers that cannot allocate:
+// the event queues and the (history, voxel) tally table of a run live in this
+// file-scope array instead of memory the library or the caller allocates.
+// Each device the library runs on holds its own copy until the process ends.
+// Host code never passes `scratch` itself to a kernel (in host code the name
+// is a stand-in, not a device address): mcx_create looks up the address of
+// the current device's copy once per device, and only that address is used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MCX_STATIC_SCRATCH_BYTES];
+
+constexpr uint32_t kStaticBank = 1u << 16;  // largest bank a static run uses
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];  // device address of each device's copy
+hipError_t g_scratch_rc[kMaxDevices];
+bool g_scratch_done[kMaxDevices];
+
+// once per device, with that device current
+void static_scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_done[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  g_scratch[dev] = p;
+  g_scratch_rc[dev] = e;
+  g_scratch_done[dev] = true;
+}
+
+void* static_scratch(int dev, hipError_t* rc) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices || !g_scratch_done[dev]) {
+    *rc = hipErrorNotInitialized;
+    return nullptr;
+  }
+  *rc = g_scratch_rc[dev];
+  return g_scratch[dev];
+}
+
+// fill n 64-bit words (a kernel, not a memset: a caller may capture the work
+// of a static run into a graph)
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t fill_u64(void* p, uint64_t n, uint64_t v, hipStream_t s) {
+  const unsigned g = unsigned(std::min<uint64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, s, static_cast<uint64_t*>(p), n, v);
+  return hipGetLastError();
+}
+
+// checks shared by mcx_run and mcx_run_static
+int check_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n) {
+  if (!c->have_sources || !c->have_material || !c->have_phantom)
+    return fail(c, MCX_E_STATE, "set transport, material, phantom and sources first");
+  if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
+  for (int k = 0; k <= c->vmat_max; ++k)
+    if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
+  if (weighted_run(c->tr) && c->d_vmat.p)
+    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing and splitting run on one-material phantoms");
+  if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  return MCX_OK;
+}
+
+// bookkeeping of a complete (or cancelled) forward run
+void record_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, uint64_t completed) {
+  c->n_done += completed;
+  c->next_history = first + completed;
+  c->run_seed = uint32_t(seed);
+  c->run_first = first;
+  c->run_n = completed;
+  c->run_known = completed > 0 && c->n_done == completed;
+  c->last_n = n;
+  c->last_valid = c->test_mode != 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -554,6 +617,21 @@ int mcx_create(mcx_ctx** out, int hip_device, int precision) {
     delete c;
     return MCX_E_DEVICE;
   }
+  // the loop and statistics counters, on the device and pinned on the host
+  hipError_t e = hipMalloc(&c->d_cnt.p, sizeof(Counters));
+  if (e == hipSuccess) {
+    c->d_cnt.bytes = sizeof(Counters);
+    e = hipMemsetAsync(c->d_cnt.p, 0, sizeof(Counters), c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->h_cnt), sizeof(Counters), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    mcx_destroy(c);
+    return MCX_E_NOMEM;
+  }
+  // this device's copy of the fixed scratch array (mcx_run_static)
+  static_scratch_init(hip_device);
   *out = c;
   return MCX_OK;
 }
@@ -941,20 +1019,12 @@ int mcx_set_test_mode(mcx_ctx* c, int on) {
 
 int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream) {
   if (!c) return MCX_E_INVALID;
-  if (!c->have_sources || !c->have_material || !c->have_phantom)
-    return fail(c, MCX_E_STATE, "set transport, material, phantom and sources first");
-  if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
-  for (int k = 0; k <= c->vmat_max; ++k)
-    if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
-  if (weighted_run(c->tr) && c->d_vmat.p)
-    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing and splitting run on one-material phantoms");
-  if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
-  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  int rc = check_run(c, seed, first, n);
+  if (rc) return rc;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   c->last_valid = false;
   if (n == 0) return MCX_OK;
-  int rc = ensure_workspace(c);
-  if (rc) return rc;
+  if ((rc = ensure_workspace(c))) return rc;
   if (c->table_dirty) {
     hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, c->hslots * sizeof(double), s);
@@ -974,14 +1044,61 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
   if (rc && rc != MCX_E_CANCELLED) return rc;
   // complete, or cancelled with [first, first + completed) done and flushed
   c->table_dirty = false;
-  c->n_done += completed;
-  c->next_history = first + completed;
-  c->run_seed = uint32_t(seed);
-  c->run_first = first;
-  c->run_n = completed;
-  c->run_known = completed > 0 && c->n_done == completed;
-  c->last_n = n;
-  c->last_valid = c->test_mode != 0;
+  record_run(c, seed, first, n, completed);
+  return rc;
+}
+
+int mcx_run_static(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream) {
+  if (!c) return MCX_E_INVALID;
+  int rc = check_run(c, seed, first, n);
+  if (rc) return rc;
+  if (c->test_mode)
+    return fail(c, MCX_E_UNSUPPORTED, "test mode needs per-history buffers sized by the run: use mcx_run");
+  hipError_t e;
+  char* base = static_cast<char*>(static_scratch(c->device, &e));
+  if (!base) return fail(c, MCX_E_DEVICE, "no static scratch on device %d: %s", c->device, hipGetErrorString(e));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  c->last_valid = false;
+  if (n == 0) return MCX_OK;
+  // the queues of the bank (the configured one, at most kStaticBank
+  // records), then the largest power-of-two tally table that fits
+  struct Saved {
+    mcx_ctx* c;
+    uint32_t cap;
+    DevBuf q, k, v;
+    uint64_t hslots;
+    size_t built;
+    ~Saved() {
+      c->cap = cap;
+      c->d_queues = q;
+      c->d_hkeys = k;
+      c->d_hvals = v;
+      c->hslots = hslots;
+      c->queue_cap_built = built;
+    }
+  } saved{c, c->cap, c->d_queues, c->d_hkeys, c->d_hvals, c->hslots, c->queue_cap_built};
+  c->cap = std::min(c->cap, kStaticBank);
+  const size_t qb = align256(queue_bytes(c));
+  uint64_t slots = kTableSlots;
+  while (slots > 1 && qb + slots * kSlotBytes > size_t(MCX_STATIC_SCRATCH_BYTES)) slots >>= 1;
+  if (qb + slots * kSlotBytes > size_t(MCX_STATIC_SCRATCH_BYTES) || slots < kMinWsSlots)
+    return fail(c, MCX_E_RANGE, "static scratch of %zu bytes holds no bank of %u records with a table of 2^20 slots",
+                size_t(MCX_STATIC_SCRATCH_BYTES), c->cap);
+  c->d_queues = DevBuf{base, qb, true};
+  c->d_hkeys = DevBuf{base + qb, slots * sizeof(uint64_t), true};
+  c->d_hvals = DevBuf{base + qb + slots * sizeof(uint64_t), slots * sizeof(double), true};
+  c->hslots = slots;
+  c->queue_cap_built = c->cap;
+  // the array keeps the last call's contents: an empty table to start
+  e = fill_u64(c->d_hkeys.p, slots, kEmptyKey, s);
+  if (e == hipSuccess) e = fill_u64(c->d_hvals.p, slots, 0ull, s);
+  if (e != hipSuccess) return hip_fail(c, e, "clear static tally table");
+  uint64_t completed = 0;
+  // no graph: instantiating one allocates
+  rc = fp64(c) ? run_impl<double>(c, uint32_t(seed), first, n, s, 0, 0.0, &completed, false)
+               : run_impl<float>(c, uint32_t(seed), first, n, s, 0, 0.0, &completed, false);
+  if (rc && rc != MCX_E_CANCELLED) return rc;
+  record_run(c, seed, first, n, completed);
   return rc;
 }
 
@@ -1389,12 +1506,8 @@ int mcx_set_workspace(mcx_ctx* c, void* dev, size_t bytes) {
   // the memory may have been written by other streams until now
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "synchronize before the workspace change");
-  // the statistics counters live in the workspace: carry them over
-  Counters saved;
-  const bool have_cnt = c->d_cnt.p != nullptr;
-  if (have_cnt && hipMemcpy(&saved, c->d_cnt.p, sizeof(Counters), hipMemcpyDeviceToHost) != hipSuccess)
-    return fail(c, MCX_E_DEVICE, "read statistics");
-  for (DevBuf* b : {&c->d_queues, &c->d_cnt, &c->d_hkeys, &c->d_hvals}) dfree(*b);
+  // the loop and statistics counters are the context's own and stay
+  for (DevBuf* b : {&c->d_queues, &c->d_hkeys, &c->d_hvals}) dfree(*b);
   c->queue_cap_built = 0;
   c->ws = dev;
   c->ws_bytes = dev ? bytes : 0;
@@ -1402,17 +1515,9 @@ int mcx_set_workspace(mcx_ctx* c, void* dev, size_t bytes) {
   c->hslots = kTableSlots;
   int rc = dev ? carve_workspace(c) : MCX_OK;
   if (rc) {  // too small: back to library-owned memory
-    for (DevBuf* b : {&c->d_queues, &c->d_cnt, &c->d_hkeys, &c->d_hvals}) dfree(*b);
+    for (DevBuf* b : {&c->d_queues, &c->d_hkeys, &c->d_hvals}) dfree(*b);
     c->ws = nullptr;
     c->ws_bytes = 0;
-  }
-  if (have_cnt) {
-    if (!c->d_cnt.p) {
-      const int r2 = dalloc(c, c->d_cnt, sizeof(Counters), "counters");
-      if (r2) return rc ? rc : r2;
-    }
-    if (hipMemcpy(c->d_cnt.p, &saved, sizeof(Counters), hipMemcpyHostToDevice) != hipSuccess)
-      return fail(c, MCX_E_DEVICE, "restore statistics");
   }
   return rc;
 }
