@@ -672,6 +672,7 @@ int mcx_set_transport(mcx_ctx* c, const mcx_transport* t) {
   c->have_transport = true;
   c->have_material = false;
   for (bool& h : c->have_mat) h = false;
+  c->run_known = false;  // the gradient replays would run other physics
   return MCX_OK;
 }
 
@@ -689,6 +690,7 @@ int mcx_load_material(mcx_ctx* c, int mat_id, const mcx_material_desc* m) {
   BuiltTables b;
   if (!build_tables(*m, c->tr, &b, &err)) return fail(c, MCX_E_INVALID, "%s", err.c_str());
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
+  c->run_known = false;  // the gradient replays would run other tables
   c->mtabs[mat_id] = std::move(b);
   c->have_mat[mat_id] = true;
   if (mat_id == 0) {
@@ -761,12 +763,27 @@ int mcx_load_phantom(mcx_ctx* c, const mcx_phantom_desc* p) {
       return fail(c, MCX_E_INVALID, "voxel sizes must be positive and origins finite");
   (void)hipSetDevice(c->device);
   const uint64_t nv = uint64_t(p->nx) * p->ny * p->nz;
+  // every check on the host before any device state changes
   std::vector<double> h(nv);
   hipError_t e = hipMemcpy(h.data(), p->rho, nv * sizeof(double),
                            p->rho_on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost);
   if (e != hipSuccess) return hip_fail(c, e, "read densities");
   for (uint64_t v = 0; v < nv; ++v)
     if (!(h[v] > 0.0) || !std::isfinite(h[v])) return fail(c, MCX_E_INVALID, "density must be > 0 (voxel %llu)", (unsigned long long)v);
+  int mx = -1;
+  if (p->mat) {
+    mx = 0;
+    for (uint64_t v = 0; v < nv; ++v) {
+      if (p->mat[v] >= kMaxMat) return fail(c, MCX_E_INVALID, "material index %d >= %d (voxel %llu)", int(p->mat[v]),
+                                            kMaxMat, (unsigned long long)v);
+      mx = std::max(mx, int(p->mat[v]));
+    }
+  }
+  // from here on the old phantom is gone: a failure leaves none (MCX_E_STATE
+  // for runs and gradients until a load succeeds)
+  c->have_phantom = false;
+  c->run_known = false;
+  c->n_done = 0;
   int rc;
   if ((rc = dalloc(c, c->d_rho, nv * tsize(c), "densities"))) return rc;
   if (fp64(c)) {
@@ -780,12 +797,6 @@ int mcx_load_phantom(mcx_ctx* c, const mcx_phantom_desc* p) {
   c->vmat_max = -1;
   dfree(c->d_vmat);
   if (p->mat) {
-    int mx = 0;
-    for (uint64_t v = 0; v < nv; ++v) {
-      if (p->mat[v] >= kMaxMat) return fail(c, MCX_E_INVALID, "material index %d >= %d (voxel %llu)", int(p->mat[v]),
-                                            kMaxMat, (unsigned long long)v);
-      mx = std::max(mx, int(p->mat[v]));
-    }
     if ((rc = dalloc(c, c->d_vmat, nv, "voxel materials"))) return rc;
     e = hipMemcpy(c->d_vmat.p, p->mat, nv, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(c, e, "copy voxel materials");
@@ -873,6 +884,7 @@ int mcx_set_sources(mcx_ctx* c, const mcx_source* s, int n) {
   c->src = std::move(v);
   c->total_hist = total;
   c->have_sources = true;
+  c->run_known = false;  // the gradient replays would start other histories
   return MCX_OK;
 }
 
@@ -1105,8 +1117,13 @@ int mcx_run_static(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* 
 int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int on_device, void* stream) {
   if (!c) return MCX_E_INVALID;
   if (!dl_ddose || !dl_drho) return fail(c, MCX_E_INVALID, "null gradient array");
-  if (!c->run_known || !c->have_sources || c->run_first + c->run_n > c->total_hist)
-    return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset");
+  if (!c->run_known || !c->have_sources || !c->have_material || !c->have_phantom ||
+      c->run_first + c->run_n > c->total_hist)
+    return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset, with its setup unchanged");
+  for (int k = 0; k <= c->vmat_max; ++k)
+    if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
+  if (weighted_run(c->tr) && c->d_vmat.p)
+    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing and splitting run on one-material phantoms");
   if (c->tr.flags & MCX_STRAGGLING)
     return fail(c, MCX_E_UNSUPPORTED, "the gradient has no term for a straggled soft loss");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");

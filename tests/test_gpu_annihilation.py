@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from tally_checks import check_tally_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -32,16 +33,17 @@ def gpu_run(wl, n, precision=0, test=True):
     sim.run(wl["seed"], 0, n)
     h, led = sim.history_results(n) if test else (None, None)
     d, s = sim.dose()
+    q, q2 = sim.tally()
     st = sim.stats()
     sim.close()
-    return dict(hash=h, led=led, dose=d, sigma=s, stats=st)
+    return dict(hash=h, led=led, dose=d, sigma=s, q=q, q2=q2, stats=st)
 
 
 def oracle_run(wl, n):
     tb = O.Tables(wl["material"], wl["transport"])
     r = O.run(tb, wl["phantom"], wl["sources"], wl["seed"], 0, n, hashes=True, ledger=True)
     d, s = O.dose(wl["phantom"], r)
-    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, stats=r.stats.as_dict())
+    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, q=r.sum_q, q2=r.sum_q2, stats=r.stats.as_dict())
 
 
 def check_balance(led, etot, tol):
@@ -79,6 +81,7 @@ def test_annihilation_in_flight_parity(case, flags):
     assert g["stats"]["annih"] > 0
     check_balance(g["led"], etot, 1e-12)
     check_dose_3sigma(g, o)
+    check_tally_parity(g, o, same=same)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

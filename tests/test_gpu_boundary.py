@@ -199,3 +199,57 @@ def test_run_in_caller_owned_workspace():
     sim.set_workspace(None)
     sim.close()
     del ws, small
+
+
+def test_setup_changes_after_a_run_invalidate_the_gradient_replays():
+    """The gradient replays the last run's histories with the context's
+    physics: once the transport parameters, a material or the sources change
+    after the run, the replays would run other physics or other histories,
+    so mcx_dose_backward refuses with MCX_E_STATE until a new run."""
+    mcx = _mcx()
+    wl = W.workload("water_pencil_32", 2000)
+    g = np.zeros((32, 32, 32))
+    for change in ("transport", "material", "sources"):
+        sim = mcx.Simulator(0, 0).setup(wl)
+        sim.run(wl["seed"], 0, 2000)
+        sim.dose_backward(g)  # valid right after the run
+        if change == "transport":
+            sim.set_transport(dict(wl["transport"], flags=mcx.ANNIH_FLIGHT))
+            sim.load_material(wl["material"], 0)
+        elif change == "material":
+            sim.load_material(wl["material"], 0)
+        else:
+            sim.set_sources(wl["sources"])
+        with pytest.raises(mcx.MCXError, match="STATE"):
+            sim.dose_backward(g)
+        sim.reset()
+        sim.run(wl["seed"], 0, 2000)
+        sim.dose_backward(g)
+        sim.close()
+
+
+def test_rejected_phantom_load_leaves_no_phantom():
+    """A phantom with a material index >= 4 or a non-positive density is
+    rejected by the host checks, which all run before any device state
+    changes: the previous phantom, its tallies and its run (for the gradient)
+    stay intact and usable."""
+    mcx = _mcx()
+    wl = W.workload("water_pencil_32", 2000)
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.run(wl["seed"], 0, 2000)
+    q0, _ = sim.tally()
+    bad = dict(wl["phantom"], mat=np.full((32, 32, 32), 7, dtype=np.uint8))
+    with pytest.raises(mcx.MCXError, match="INVALID"):
+        sim.load_phantom(bad)
+    # validated on the host first: the old phantom, tallies and run are intact
+    q1, _ = sim.tally()
+    assert np.array_equal(q0, q1)
+    sim.dose_backward(np.zeros((32, 32, 32)))
+    neg = dict(wl["phantom"], rho=-np.ones((32, 32, 32)))
+    with pytest.raises(mcx.MCXError, match="INVALID"):
+        sim.load_phantom(neg)
+    sim.reset()
+    sim.run(wl["seed"], 0, 2000)
+    q2, _ = sim.tally()
+    assert np.array_equal(q0 > 0, q2 > 0) and np.allclose(q0, q2, rtol=1e-11, atol=1e-14)
+    sim.close()

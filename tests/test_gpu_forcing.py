@@ -9,6 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from tally_checks import check_tally_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -26,16 +27,17 @@ def gpu_run(wl, n, precision=0, test=True):
     sim.run(wl["seed"], 0, n)
     h, led = sim.history_results(n) if test else (None, None)
     d, s = sim.dose()
+    q, q2 = sim.tally()
     st = sim.stats()
     sim.close()
-    return dict(hash=h, led=led, dose=d, sigma=s, stats=st)
+    return dict(hash=h, led=led, dose=d, sigma=s, q=q, q2=q2, stats=st)
 
 
 def oracle_run(wl, n):
     r = O.run(O.Tables(wl["material"], wl["transport"]), wl["phantom"], wl["sources"], wl["seed"], 0, n,
               hashes=True, ledger=True)
     d, s = O.dose(wl["phantom"], r)
-    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, stats=r.stats.as_dict())
+    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, q=r.sum_q, q2=r.sum_q2, stats=r.stats.as_dict())
 
 
 def check_dose_3sigma(g, o, frac=0.01):
@@ -75,6 +77,7 @@ def test_forcing_parity(case):
     assert np.allclose(g["led"][same], o["led"][same][:, [0, 1, 2]], rtol=0, atol=1e-8)
     assert abs(g["stats"]["hard_br"] - o["stats"]["hard_br"]) <= 0.01 * o["stats"]["hard_br"] + 5
     check_dose_3sigma(g, o)
+    check_tally_parity(g, o, same=same.mean())
 
 
 def test_forcing_mixed_precision_and_unbiased_balance():

@@ -8,6 +8,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from tally_checks import check_tally_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -36,7 +37,7 @@ def oracle_run(wl, n):
     r = O.run(tbs if "materials" in wl else tbs[0], wl["phantom"], wl["sources"], wl["seed"], 0, n, hashes=True,
               ledger=True)
     d, s = O.dose(wl["phantom"], r)
-    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, stats=r.stats.as_dict())
+    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, q=r.sum_q, q2=r.sum_q2, stats=r.stats.as_dict())
 
 
 def check_balance(led, etot, tol):
@@ -91,6 +92,7 @@ def test_several_materials_parity(case):
     check_balance(g["led"], etot, 1e-12)
     assert np.allclose(g["led"][same], o["led"][same][:, [0, 1, 2]], rtol=0, atol=1e-8)
     check_dose_3sigma(g, o)
+    check_tally_parity(g, o, same=same.mean())
 
 
 def test_several_materials_with_straggling_and_annihilation():

@@ -14,6 +14,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from tally_checks import check_tally_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -96,6 +97,9 @@ def test_c0_dose_within_3_sigma(c0):
     hi = o["dose"] > 0.01 * o["dose"].max()
     rel = np.abs(g["dose"] - o["dose"])[hi] / o["dose"][hi]
     assert np.median(rel) < 1e-9
+    # Sum q^2 and sigma too (the 1e5 histories span two chunks of the tally
+    # table: 65,536 histories, then the rest)
+    check_tally_parity(g, o, same=float(np.mean(g["hash"] == o["hash"])))
 
 
 def test_c0_conservation_and_ledger(c0):
@@ -140,6 +144,30 @@ def test_particle_types_parity(case):
     assert same >= 0.99
     check_balance(g["led"], e_total(wl), 1e-12)
     check_dose_3sigma(g, o)
+    check_tally_parity(g, o, same=same)
+
+
+def test_small_tally_table_several_flushes_parity():
+    """The fixed array of mcx_run_static holds a tally table of 2^20 slots, so
+    40,000 histories of the heterogeneous field are flushed in more than one
+    chunk (the first of 4,096 histories, the next sized by the measured pairs
+    per history): Sum q, Sum q^2 and sigma still equal the oracle's, every
+    history complete at the flush of its chunk."""
+    mcx = _mcx()
+    wl = W.workload("hetero_broad_64", 40000)
+    n = 40000
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.run_static(wl["seed"], 0, n)
+    d, s = sim.dose()
+    q, q2 = sim.tally()
+    st = sim.stats()
+    sim.close()
+    print("chunks", st["chunks"])
+    assert st["chunks"] >= 2
+    g = dict(dose=d, sigma=s, q=q, q2=q2)
+    o = oracle_run(wl, n)
+    check_dose_3sigma(g, o)
+    check_tally_parity(g, o)
 
 
 def test_edge_cases_ragged_and_tiny():

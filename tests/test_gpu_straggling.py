@@ -14,6 +14,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from tally_checks import check_tally_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -37,16 +38,17 @@ def gpu_run(wl, n, precision=0):
     sim.run(wl["seed"], 0, n)
     h, led = sim.history_results(n)
     d, s = sim.dose()
+    q, q2 = sim.tally()
     st = sim.stats()
     sim.close()
-    return dict(hash=h, led=led, dose=d, sigma=s, stats=st)
+    return dict(hash=h, led=led, dose=d, sigma=s, q=q, q2=q2, stats=st)
 
 
 def oracle_run(wl, n):
     tb = O.Tables(wl["material"], wl["transport"])
     r = O.run(tb, wl["phantom"], wl["sources"], wl["seed"], 0, n, hashes=True, ledger=True)
     d, s = O.dose(wl["phantom"], r)
-    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, stats=r.stats.as_dict())
+    return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, q=r.sum_q, q2=r.sum_q2, stats=r.stats.as_dict())
 
 
 def e_total(wl):
@@ -78,6 +80,7 @@ def test_straggling_water_pencil_parity():
     check_dose_3sigma(g, o)
     hi = o["dose"] > 0.01 * o["dose"].max()
     assert np.median(np.abs(g["dose"] - o["dose"])[hi] / o["dose"][hi]) < 1e-9
+    check_tally_parity(g, o, same=same.mean())
 
 
 @pytest.mark.parametrize("case", ["electron20", "positron5", "rect_hetero"])
@@ -98,6 +101,7 @@ def test_straggling_particle_types_parity(case):
     assert same >= 0.99
     check_balance(g["led"], e_total(wl), 1e-12)
     check_dose_3sigma(g, o)
+    check_tally_parity(g, o, same=same)
 
 
 def test_straggling_thin_slab_per_history_losses():
