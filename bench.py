@@ -136,13 +136,25 @@ def run_steps(sim, n, seeds, sync):
     return times
 
 
+def smooth_target(d: np.ndarray) -> np.ndarray:
+    """T_v = Dbar (0.5 + s_v): s is Gaussian-smoothed (sigma = 3 voxels) white
+    noise (PCG64 seed 5) scaled to [0, 1]; Dbar the mean dose over the
+    voxels with D >= 10% of the maximum."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.Generator(np.random.PCG64(5))
+    s = gaussian_filter(rng.standard_normal(d.shape), 3.0)
+    s = (s - s.min()) / (s.max() - s.min())
+    dbar = d[d >= 0.1 * d.max()].mean()
+    return dbar * (0.5 + s)
+
+
 def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
     """Forward + backward (two replays) on the 64^3 heterogeneous phantom,
     6 MeV field, loss sum_v (D_v - T_v)^2 with a seeded smooth target."""
-    from scipy.ndimage import gaussian_filter
     wl = W.workload("hetero_broad_64", n)
     sim = mcx.Simulator(mcx.FP64, 0).setup(wl)
     sim.run(777, 0, min(n, 200_000))  # warm-up
+    sim.dose_backward(np.zeros(wl["phantom"]["shape"]))
     sim.reset()
     sync()
     t0 = time.perf_counter()
@@ -150,17 +162,84 @@ def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
     d, _ = sim.dose()
     sync()
     t1 = time.perf_counter()
-    rng = np.random.Generator(np.random.PCG64(5))
-    s = gaussian_filter(rng.standard_normal(d.shape), 3.0)
-    s = (s - s.min()) / (s.max() - s.min())
-    dbar = d[d >= 0.1 * d.max()].mean()
-    target = dbar * (0.5 + s)
+    target = smooth_target(d)
     g = sim.dose_backward(2.0 * (d - target))
     sync()
     t2 = time.perf_counter()
     sim.close()
     return dict(workload="hetero_broad_64: 6 MeV 10x10 field, 64^3 x 4 mm, FP64", histories=n,
-                forward_s=t1 - t0, backward_s=t2 - t1, fwd_bwd_s=t2 - t0, grad_abs_max=float(np.abs(g).max()))
+                forward_s=t1 - t0, backward_s=t2 - t1, fwd_bwd_s=t2 - t0, grad_abs_max=float(np.abs(g).max()),
+                target=target)
+
+
+def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: int = 10, n_vox: int = 16,
+                      h: float = 0.01) -> dict:
+    """The replay gradient against common-random-number central differences
+    on the same workload: 16 voxels drawn (PCG64 seed 6) among those inside
+    the field with D >= 10% of the maximum; each batch b (seed 100 + b,
+    histories [0, n_batch)) gives one replay gradient and, for each voxel,
+    (L(rho + h rho_j) - L(rho - h rho_j)) / (2 h rho_j) with the same seed
+    and histories; L = sum_v (D_v - T_v)^2 with the target frozen.  Means and
+    standard errors over the batches."""
+    wl = W.workload("hetero_broad_64", n_batch)
+    ph = wl["phantom"]
+    sim = mcx.Simulator(mcx.FP64, 0).setup(wl)
+    sim.run(99, 0, n_batch)
+    d0, _ = sim.dose()
+    sim.reset()
+    nz, ny, nx = ph["shape"]
+    dx = ph["voxel"][0]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    xc = (x + 0.5) * dx + ph["origin"][0]
+    yc = (y + 0.5) * dx + ph["origin"][1]
+    src = wl["sources"][0]
+    inside = (np.abs(xc - src["pos"][0]) < 0.5 * src["width"][0] - dx) & \
+             (np.abs(yc - src["pos"][1]) < 0.5 * src["width"][1] - dx)
+    elig = np.argwhere(inside & (d0 >= 0.1 * d0.max()))
+    pick = elig[np.random.Generator(np.random.PCG64(6)).choice(len(elig), size=n_vox, replace=False)]
+    vox = [tuple(int(c) for c in v) for v in pick]
+    est = np.zeros((batches, n_vox))
+    t0 = time.perf_counter()
+    for b in range(batches):
+        sim.reset()
+        sim.run(100 + b, 0, n_batch)
+        d, _ = sim.dose()
+        g = sim.dose_backward(2.0 * (d - target))
+        est[b] = [g[v] for v in vox]
+    t_grad = time.perf_counter() - t0
+    fd = np.zeros((batches, n_vox))
+    t0 = time.perf_counter()
+    for k, v in enumerate(vox):
+        sims = {}
+        for sg in (1, -1):
+            rho = ph["rho"].copy()
+            rho[v] *= 1.0 + sg * h
+            sims[sg] = mcx.Simulator(mcx.FP64, 0).setup(dict(wl, phantom=dict(ph, rho=rho)))
+        for b in range(batches):
+            vals = {}
+            for sg, sm in sims.items():
+                sm.reset()
+                sm.run(100 + b, 0, n_batch)
+                d, _ = sm.dose()
+                vals[sg] = float(((d - target) ** 2).sum())
+            fd[b, k] = (vals[1] - vals[-1]) / (2.0 * h * ph["rho"][v])
+        for sm in sims.values():
+            sm.close()
+    t_fd = time.perf_counter() - t0
+    sim.close()
+    sync()
+    m, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(batches)
+    f, fse = fd.mean(0), fd.std(0, ddof=1) / np.sqrt(batches)
+    zz = (m - f) / np.sqrt(se ** 2 + fse ** 2)
+    # one bias figure: the least-squares slope of the replay gradient on the
+    # finite differences (1 = unbiased), with its standard error from the
+    # batch-to-batch spread of both
+    slope = float(np.dot(m, f) / np.dot(f, f))
+    sl_b = [np.dot(est[b], f) / np.dot(f, f) for b in range(batches)]
+    return dict(voxels=vox, replay=m.tolist(), replay_se=se.tolist(), fd=f.tolist(), fd_se=fse.tolist(),
+                z=zz.tolist(), z_mean=float(zz.mean()), z_rms=float(np.sqrt((zz ** 2).mean())),
+                z_max=float(np.abs(zz).max()), slope=slope, slope_se=float(np.std(sl_b, ddof=1) / np.sqrt(batches)),
+                h=h, batches=batches, histories_per_batch=n_batch, replay_s=t_grad, fd_s=t_fd)
 
 
 def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
@@ -288,6 +367,7 @@ def main():
     ap.add_argument("--bank", type=int, default=1 << 26)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--no-fd-check", action="store_true", help="skip the finite-difference check of the gradient")
     ap.add_argument("--beamlets", type=int, default=0, metavar="TOTAL",
                     help="also time 512 beamlets with TOTAL histories batched vs one run each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -428,6 +508,9 @@ def main():
                                         summed_dose_ratio_to_one_material=float(d_mm.sum() / d_mix.sum()))
     if not args.no_gradient:
         out["gradient"] = gradient_timing(mcx, W, sync)
+        target = out["gradient"].pop("target")
+        if not args.no_fd_check:
+            out["gradient"]["fd_check"] = gradient_fd_check(mcx, W, sync, target)
     if args.beamlets:
         out["beamlets"] = beamlet_comparison(mcx, W, sync, args.beamlets,
                                              os.path.join(ROOT, "gpurun_out", "autotune_cache.jsonl"))

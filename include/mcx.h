@@ -191,6 +191,8 @@ typedef struct {
   /* first history id the last mcx_run did not complete: first_hist + n_hist
    * after a complete run, the cancellation watermark after MCX_E_CANCELLED */
   uint64_t next_history;
+  /* positrons annihilated in flight (MCX_ANNIH_FLIGHT; counted in annih too) */
+  uint64_t annih_flight;
 } mcx_stats;
 
 /* Create a context on HIP device `hip_device` computing in `precision`

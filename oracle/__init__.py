@@ -58,7 +58,8 @@ class Phantom(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("ox", C.c_double), ("oy", C.c_double), ("oz", C.c_double),
-                ("rho", C.POINTER(C.c_double)), ("mat", C.POINTER(C.c_uint8))]
+                ("rho", C.POINTER(C.c_double)), ("mat", C.POINTER(C.c_uint8)),
+                ("step_cap", C.POINTER(C.c_double))]
 
 
 class Source(C.Structure):
@@ -74,7 +75,8 @@ _STAT_FIELDS = ("histories", "flights", "compton", "photo", "rayleigh", "pair",
 
 class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in _STAT_FIELDS] + [
-        ("e_dep", C.c_double), ("e_esc", C.c_double), ("pos_esc", C.c_uint64), ("maj_excess", C.c_uint64)]
+        ("e_dep", C.c_double), ("e_esc", C.c_double), ("pos_esc", C.c_uint64), ("maj_excess", C.c_uint64),
+        ("annih_flight", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -118,6 +120,8 @@ def lib():
         L.orc_mu_cut.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_soft_a.restype = C.c_double
         L.orc_soft_a.argtypes = [C.c_double]
+        L.orc_soft_score.restype = C.c_double
+        L.orc_soft_score.argtypes = [C.c_double] * 5
         L.orc_soft_omega2.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.orc_soft_omega2.restype = C.c_double
         L.orc_sample_straggle.argtypes = [C.c_double, C.c_double, C.c_uint32, C.c_int, dp]
@@ -257,6 +261,10 @@ def sample_straggle(m: float, omega2: float, n: int, seed: int = 7) -> np.ndarra
     return out
 
 
+def soft_score(a: float, mu: float, mbar: float, length: float, t1s: float) -> float:
+    return lib().orc_soft_score(a, mu, mbar, length, t1s)
+
+
 def soft_a(mbar: float) -> float:
     return lib().orc_soft_a(mbar)
 
@@ -293,6 +301,11 @@ def phantom_struct(ph: dict):
         assert mat.size == rho.size
         s.mat = mat.ctypes.data_as(C.POINTER(C.c_uint8))
         s._keep_mat = mat  # the array must outlive the structure
+    if ph.get("step_cap") is not None:
+        sc = np.ascontiguousarray(ph["step_cap"], dtype=np.float64).ravel()
+        assert sc.size == rho.size
+        s.step_cap = _dp(sc)
+        s._keep_step_cap = sc
     return s, rho
 
 

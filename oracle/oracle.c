@@ -631,6 +631,10 @@ typedef struct {
   int64_t* s_touched;
   int64_t n_s_touched;
   double* p_acc;
+  /* the current e+- particle's steps, for the backward sweep of its energy
+   * adjoint when it ends (gradient mode) */
+  struct elog_rec { int64_t v; double coef, r, d; }* elog;
+  int n_elog, cap_elog;
 } ctx;
 
 static int64_t lin(const ctx* c, const int ix[3]) {
@@ -719,6 +723,63 @@ static void score(ctx* c, int64_t v, double s) {
     c->s_touched[c->n_s_touched++] = v;
   }
   c->s_tmp[v] += s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density gradient of the Class II step (reading A25: the terms below, with  */
+/* the step control held at its geometric value)                             */
+/* ------------------------------------------------------------------------ */
+
+/* Term C: d ln p(mu) / d rho of the soft angular law.  p(mu) = A (1 + A) /
+ * (mu + A)^2 on [0, 1] has the mean m(A) = A (1 + A) ln(1 + 1/A) - A, and A is
+ * chosen so that m(A) = <mu> = (1 - exp(-x))/2 with x = rho len t1s, the
+ * step's soft transport at its geometric length len.  So
+ *   d ln p / d rho = [1/A + 1/(1 + A) - 2/(mu + A)] (d<mu>/d rho) / m'(A),
+ *   d<mu>/d rho = len t1s exp(-x) / 2 = len t1s (1/2 - <mu>),
+ *   m'(A) = (1 + 2A) ln(1 + 1/A) - 2 > 0.
+ * Where A is held at its bound (<mu> > 0.49) or vanishes, A does not move
+ * with rho and the term is 0. */
+double orc_soft_score(double a, double mu, double mbar, double len, double t1s) {
+  if (!(a > 0.0) || mbar > 0.49) return 0.0;
+  double dmean = len * t1s * (0.5 - mbar); /* = len t1s exp(-x) / 2 */
+  double dm_da = (1.0 + 2.0 * a) * log1p(1.0 / a) - 2.0;
+  return (1.0 / a + 1.0 / (1.0 + a) - 2.0 / (mu + a)) * dmean / dm_da;
+}
+
+/* Pathwise term of the soft energy loss.  A step of the current e+- particle
+ * in voxel v loses E - E1 over the mass path rho l (l geometric: the face
+ * distance, or the whole step at the hinge).  At fixed l, d(E - E1)/d rho =
+ * l S(E1) (the range is R(E1) = R(E) - rho l, R' = 1/S), and E1 = E - loss
+ * moves every later step of the particle: dE1/dE = S(E1)/S(E) = r.  The
+ * derivative of the particle's weighted deposits from the start of step k
+ * with respect to its energy there, lam_k (the energy adjoint in the CSDA
+ * chain: hard events subtract fixed energies, secondaries keep theirs),
+ * obeys lam_k = d_k (1 - r_k) + r_k lam_{k+1}, d_k = weight x w_v of step k's
+ * voxel, ending at weight x w_v where the particle is absorbed and 0 where it
+ * escapes or annihilates in flight.  Each step adds l S(E1) (d_k - lam_{k+1})
+ * to voxel v: the loss it deposits there minus what the particle then lacks
+ * downstream.  The steps are logged and swept backward at the particle's
+ * end. */
+static void elog_push(ctx* c, int64_t v, double coef, double r, double d) {
+  if (c->n_elog == c->cap_elog) {
+    c->cap_elog = c->cap_elog ? 2 * c->cap_elog : 256;
+    c->elog = (struct elog_rec*)realloc(c->elog, sizeof(*c->elog) * (size_t)c->cap_elog);
+  }
+  c->elog[c->n_elog].v = v;
+  c->elog[c->n_elog].coef = coef;
+  c->elog[c->n_elog].r = r;
+  c->elog[c->n_elog].d = d;
+  c->n_elog++;
+}
+
+static void elog_close(ctx* c, double lam_end) {
+  double lam = lam_end;
+  for (int k = c->n_elog - 1; k >= 0; --k) {
+    const struct elog_rec* e = &c->elog[k];
+    c->p_acc[e->v] += e->coef * (e->d - lam);
+    lam = e->d * (1.0 - e->r) + e->r * lam;
+  }
+  c->n_elog = 0;
 }
 
 /* event codes folded into the particle hash */
@@ -1131,6 +1192,7 @@ static void e_hard(ctx* c, part* p, int which) {
   } else if (which == 3) {
     /* R9: the positron annihilates with an electron at rest */
     c->st->annih++;
+    c->st->annih_flight++;
     double e = p->e;
     double z = sample_annih(&p->rng, e);
     double phi = 2.0 * PI * draw(&p->rng);
@@ -1175,13 +1237,20 @@ static void e_hard(ctx* c, part* p, int which) {
   }
 }
 
-/* Class II step loop of one electron or positron */
+/* Class II step loop of one electron or positron.  In gradient mode (c->w)
+ * each step also adds its terms of reading A25: the score of the majorant
+ * free path (A), the score of the soft deflection (C) and the logged
+ * pathwise soft-loss term, swept backward when the particle ends. */
 static void electron_track(ctx* c, part* p) {
   const orc_transport* t = c->t;
   int ti = p->type == ORC_POSITRON ? 1 : 0;
   double eabs = t->eabs[p->type];
   for (;;) {
-    if (!(p->e > eabs)) { e_absorb(c, p); return; }
+    if (!(p->e > eabs)) {
+      if (c->w) elog_close(c, p->w * c->w[lin(c, p->ix)]);
+      e_absorb(c, p);
+      return;
+    }
     c->st->esteps++;
     double e = p->e;
     int64_t v = lin(c, p->ix);
@@ -1190,8 +1259,11 @@ static void electron_track(ctx* c, part* p) {
     /* step control: maximum mass step and the hard-event majorant */
     double ss = interp(tb, tb->el[ti][CH_S], 0.0, e);
     double tau_max = t->c2 * e / ss;
+    /* (test use: a fixed geometric cap, whose mass the majorant must cover) */
+    const double* cap = c->ph->step_cap;
+    double tau_cap = cap ? rho * cap[v] : tau_max;
     double r0 = range_of(tb, ti, e);
-    double elo = r0 - tau_max > 0.0 ? orc_range_inverse(tb, ti, r0 - tau_max) : tb->e[0];
+    double elo = r0 - tau_cap > 0.0 ? orc_range_inverse(tb, ti, r0 - tau_cap) : tb->e[0];
     if (elo > e) elo = e;
     if (t->flags & ORC_STRAGGLING) {
       /* R14: a straggled loss can exceed the step's CSDA loss: by at most
@@ -1211,9 +1283,20 @@ static void electron_track(ctx* c, part* p) {
     if (annih) smaj += orc_sigma_annih(tb, elo);
     double u1 = draw(&p->rng);
     double tau_h = smaj > 0.0 ? -log(u1) / smaj : INF_D;
-    int capped = !(tau_h <= tau_max);
-    double tau_s = capped ? tau_max : tau_h;
-    double len = tau_s / rho;
+    int capped;
+    double len;
+    if (cap) {
+      capped = !(tau_h / rho <= cap[v]);
+      len = capped ? cap[v] : tau_h / rho;
+    } else {
+      capped = !(tau_h <= tau_max);
+      double tau_s = capped ? tau_max : tau_h;
+      len = tau_s / rho;
+    }
+    /* A25 term A: the geometric free path of the majorant process has the
+     * density rho smaj exp(-rho smaj s) below the cap and the tail
+     * exp(-rho smaj len) at it: d ln p / d rho = -smaj len (+ 1/rho below) */
+    if (c->w) score(c, v, -smaj * len + (capped ? 0.0 : 1.0 / rho));
     double th = draw(&p->rng) * len;
     int a;
     double db = face(c, p, &a);
@@ -1227,11 +1310,17 @@ static void electron_track(ctx* c, part* p) {
       }
       deposit(c, p, e - e1);
       c->led[ORC_LED_PATH] += rho * db;
-      /* loss over the geometric length db: d(E - E')/d rho = db S_soft(E') */
-      if (c->w && e1 < e) c->p_acc[v] += c->w[v] * db * interp(tb, tb->el[ti][CH_S], 0.0, e1) * p->w;
+      if (c->w) {
+        double s1 = interp(tb, tb->el[ti][CH_S], 0.0, e1);
+        elog_push(c, v, db * s1, s1 / ss, p->w * c->w[v]);
+      }
       p->e = e1;
       event(c, p, EV_CROSS, v);
-      if (cross(c, p, db, a)) { e_escape(c, p, v); return; }
+      if (cross(c, p, db, a)) {
+        if (c->w) elog_close(c, 0.0);
+        e_escape(c, p, v);
+        return;
+      }
       continue;
     }
     /* hinge: the soft loss of the whole step is charged here */
@@ -1244,20 +1333,34 @@ static void electron_track(ctx* c, part* p) {
     }
     deposit(c, p, e - e1);
     c->led[ORC_LED_PATH] += rho * len;
+    if (c->w) {
+      double s1 = interp(tb, tb->el[ti][CH_S], 0.0, e1);
+      elog_push(c, v, len * s1, s1 / ss, p->w * c->w[v]);
+    }
     p->e = e1;
-    if (!(e1 > eabs)) { e_absorb(c, p); return; }
+    if (!(e1 > eabs)) {
+      if (c->w) elog_close(c, p->w * c->w[v]);
+      e_absorb(c, p);
+      return;
+    }
     double t1s = interp(tb, tb->el[ti][CH_T1S], 0.0, e);
     double mbar = 0.5 * (1.0 - exp(-rho * len * t1s));
     double aa = orc_soft_a(mbar);
     double u3 = draw(&p->rng);
     double mu = aa * u3 / (1.0 + aa - u3);
+    /* A25 term C */
+    if (c->w) score(c, v, orc_soft_score(aa, mu, mbar, len, t1s));
     double phi = 2.0 * PI * draw(&p->rng);
     rotate(p->d, 1.0 - 2.0 * mu, phi);
     double rem = len - th;
     double db2 = face(c, p, &a);
     if (db2 <= rem) {
       event(c, p, EV_CROSS, v);
-      if (cross(c, p, db2, a)) { e_escape(c, p, v); return; }
+      if (cross(c, p, db2, a)) {
+        if (c->w) elog_close(c, 0.0);
+        e_escape(c, p, v);
+        return;
+      }
       continue;
     }
     move(p, rem);
@@ -1276,6 +1379,8 @@ static void electron_track(ctx* c, part* p) {
     else if (u < s_el + s_in) e_hard(c, p, 1);
     else if (u < s_el + s_in + s_br) e_hard(c, p, 2);
     else if (u < s_el + s_in + s_br + s_an) {
+      /* the photons take the positron's energy away: no adjoint beyond */
+      if (c->w) elog_close(c, 0.0);
       e_hard(c, p, 3);
       return;
     } else {
@@ -1402,6 +1507,7 @@ static int run_body(const orc_tables* const* tbs, int n_mat, const orc_transport
   free(c.s_tmp);
   free(c.s_mark);
   free(c.s_touched);
+  free(c.elog);
   return rc;
 }
 
@@ -1432,10 +1538,10 @@ int orc_run_gradient_mm(const orc_tables* const* tbs, int n_mat, const orc_trans
                         const double* w, double* a_acc, double* b_acc, double* p_acc, double* sum_q_h) {
   if (!w || !a_acc || !b_acc || !p_acc || !sum_q_h) return -1;
   /* the estimator has no term for the score of a straggled soft loss; with
-   * forcing or splitting (R11, R12) the scores are those of the analog
-   * photon flights, the deposits and the soft-loss term carry the weights;
-   * annihilation in flight (R9) is an e+ hard event like the others, which
-   * the estimator does not score */
+   * forcing or splitting (R11, R12) the scores are those of the sampling
+   * laws actually used (the forced majorant), and the deposits and the
+   * soft-loss term carry the weights; annihilation in flight (R9) is a
+   * hard channel of the majorant like the others */
   if (t->flags & ORC_STRAGGLING) return -4;
   int64_t nv = (int64_t)ph->nx * ph->ny * ph->nz;
   double* q = (double*)calloc((size_t)nv, sizeof(double));

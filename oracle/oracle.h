@@ -89,6 +89,10 @@ typedef struct {
   double ox, oy, oz;   /* corner of voxel (0,0,0), cm */
   const double* rho;   /* g/cm^3, x fastest, length nx*ny*nz */
   const uint8_t* mat;  /* material index per voxel (< the number of tables), or NULL */
+  /* test use: a fixed geometric length (cm) of the e+- step cap per voxel,
+   * in place of tau_max(E)/rho, so that the derivative checks can hold the
+   * step control fixed while densities and energies vary; NULL: tau_max/rho */
+  const double* step_cap;
 } orc_phantom;
 
 #define ORC_MAX_MAT 4
@@ -112,6 +116,7 @@ typedef struct {
   double e_dep, e_esc;
   uint64_t pos_esc;
   uint64_t maj_excess;  /* hard selections whose cross sections exceeded the majorant (must stay 0) */
+  uint64_t annih_flight; /* positrons annihilated in flight (counted in annih too) */
 } orc_stats;
 
 /* ledger entries written per history when ledger != NULL */
@@ -136,6 +141,10 @@ double orc_screening(const orc_tables* tb, double e);
 double orc_elastic_k(const orc_tables* tb, double e);
 double orc_mu_cut(const orc_tables* tb, int type, double e);
 double orc_soft_a(double mean_mu);
+/* d ln p(mu) / d rho of the soft angular law of a Class II step of geometric
+ * length len and soft transport coefficient t1s whose mean is mbar and
+ * parameter a = orc_soft_a(mbar) (term C of the gradient, see below). */
+double orc_soft_score(double a, double mu, double mbar, double len, double t1s);
 /* Second moment of the soft energy-loss DCS per unit mass path, MeV^2 cm^2/g,
  * of an electron (type 0) or positron (1) of kinetic energy e: the variance
  * of the soft loss over a path of s g/cm^2 is s times this. */
@@ -188,17 +197,25 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
             uint64_t n, double* sum_q, double* sum_q2, orc_stats* stats,
             uint64_t* hashes, double* ledger);
 
-/* Density gradient of a dose loss by the score-function (likelihood-ratio)
- * estimator, one history at a time.  w[v] = (dL/dD_v) * 1e6 / (rho_v V) is
- * the loss weight per MeV deposited in voxel v.  Per history h:
+/* Density gradient of a dose loss, one history at a time (reading A25).
+ * w[v] = (dL/dD_v) * 1e6 / (rho_v V) is the loss weight per MeV deposited in
+ * voxel v.  Per history h:
  *   Q_h   = sum_v w_v q_hv                       (weighted score of the history)
- *   S_hj  = sum over photon free flights of -mu * l_j (length in voxel j),
- *           + 1/rho_k for the voxel k where a flight ends in an interaction
- *   P_hj  = sum over electron/positron steps stopped by a face of voxel j of
- *           w_j * l * S_soft(E')  (local derivative of the soft loss)
+ *   S_hj  = likelihood-ratio scores d ln p / d rho_j of the history's sampled
+ *           variables whose laws depend on rho_j:
+ *           photon free flights: -mu l_j per voxel crossed, +1/rho_k where the
+ *           flight ends in an interaction (term A, photons);
+ *           e+- steps in voxel j: the geometric free path of the hard-event
+ *           majorant process, -smaj len, +1/rho_j when it ends below the step
+ *           cap (term A, e+-), and the soft deflection of the hinge (term C);
+ *   P_hj  = pathwise soft-loss terms of the e+- steps in voxel j at fixed
+ *           geometric step lengths: l S(E1) (weight w_j - lam), lam the
+ *           particle's CSDA energy adjoint after the step (term D);
  * Accumulated: A_j += Q_h S_hj, B_j += S_hj, P_j += P_hj, *sum_q_h += Q_h.
- * The gradient of E[L] is (A_j - Qbar B_j + P_j)/N - (dL/dD_j) D_j / rho_j,
- * Qbar = sum_q_h / N.  Exact when electrons deposit where they are created. */
+ * The gradient is (A_j - Qbar B_j + P_j)/N - (dL/dD_j) D_j / rho_j (term B),
+ * Qbar = sum_q_h / N.  Exact when electrons deposit where they are created;
+ * with Class II transport the step cap's geometric length, the majorant and
+ * the energy dependence of the later sampling laws are held fixed. */
 int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
                      const orc_source* src, int n_src, uint32_t seed, uint64_t first,
                      uint64_t n, const double* w, double* a_acc, double* b_acc,

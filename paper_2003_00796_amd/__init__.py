@@ -98,7 +98,8 @@ class Stats(C.Structure):
         ("chunks", C.c_uint64), ("tally_pairs", C.c_uint64), ("ms_transport", C.c_double),
         ("ms_flush", C.c_double), ("evisits", C.c_uint64), ("ewrites", C.c_uint64), ("inserts", C.c_uint64),
         ("ms_source", C.c_double), ("ms_flight", C.c_double), ("ms_knock", C.c_double), ("ms_estep", C.c_double),
-        ("timed_iterations", C.c_uint64), ("ms_backward", C.c_double), ("next_history", C.c_uint64)]
+        ("timed_iterations", C.c_uint64), ("ms_backward", C.c_double), ("next_history", C.c_uint64),
+        ("annih_flight", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -72,6 +72,7 @@ enum Stat : int {
   S_EVISITS,    // e+- records read by the step kernel
   S_EWRITES,    // records written by the step kernel (survivors + secondaries)
   S_INSERTS,    // tally-table insertions
+  S_ANNIH_FLIGHT,  // positrons annihilated in flight (counted in S_ANNIH too)
   S_NSTAT
 };
 

@@ -353,7 +353,7 @@ struct CkptHeader {
   double e_dep, e_esc;
 };
 constexpr char kCkptMagic[8] = {'M', 'C', 'X', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;
 
 size_t ckpt_bytes(const mcx_ctx* c) { return sizeof(CkptHeader) + 2 * nvox(c) * sizeof(double) + sizeof(uint64_t); }
 
@@ -1282,6 +1282,7 @@ int mcx_get_stats(mcx_ctx* c, mcx_stats* out) {
   out->evisits = h.stat[S_EVISITS];
   out->ewrites = h.stat[S_EWRITES];
   out->inserts = h.stat[S_INSERTS];
+  out->annih_flight = h.stat[S_ANNIH_FLIGHT];
   out->e_dep = h.e_dep;
   out->e_esc = h.e_esc;
   return MCX_OK;

@@ -82,6 +82,20 @@ __device__ __forceinline__ MatConst<T> mat_const(const Tab<T>& tb, uint32_t m) {
   return m == 0u ? tb.mc[0] : (m == 1u ? tb.mc[1] : (m == 2u ? tb.mc[2] : tb.mc[3]));
 }
 
+// the table constants of material m (several-material kernels)
+template <typename T>
+__device__ __forceinline__ Tab<T> mat_tab(const Tab<T>& tb, uint32_t m) {
+  const MatConst<T> mc = mat_const(tb, m);
+  Tab<T> t = tb;
+  t.k_coef = mc.k_coef;
+  t.eta_a = mc.eta_a;
+  t.eta_b = mc.eta_b;
+  t.strag_k = mc.strag_k;
+  t.strag_b = mc.strag_b;
+  t.annih_k = mc.annih_k;
+  return t;
+}
+
 template <int F, typename T>
 __device__ __forceinline__ void set_flavor(const KArgs<T>& a) {
   constexpr int B = base_flavor(F);
@@ -807,21 +821,59 @@ __device__ __forceinline__ T sigma_annih(const Tab<T>& tb, T e) {
   return tb.annih_k * ((g * g + T(4) * g + T(1)) * M<T>::log(g + p) - (g + T(3)) * p) / ((g + T(1)) * (g * g - T(1)));
 }
 
+// Per-step data of the density gradient (second replay): the step's voxel,
+// its likelihood-ratio scores (majorant free path and soft deflection), its
+// pathwise soft-loss coefficient l S(E1) at fixed geometric length, the CSDA
+// chain factor r = S(E1)/S(E) and the loss weight d = weight x w_v; at the
+// particle's end, lam_end = d of the voxel where it is absorbed, else 0.
+struct EGrad {
+  uint32_t v;
+  double score, coef, r, d, lam_end;
+  bool end;
+};
+
+// d ln p(mu) / d rho of the soft angular law p(mu) = A (1 + A) / (mu + A)^2
+// on [0, 1], whose mean m(A) = A (1 + A) ln(1 + 1/A) - A is matched to
+// <mu> = (1 - exp(-rho len t1s))/2 at the step's geometric length len:
+// [1/A + 1/(1 + A) - 2/(mu + A)] len t1s (1/2 - <mu>) / m'(A),
+// m'(A) = (1 + 2A) ln(1 + 1/A) - 2; 0 where A is held at its bound
+__device__ __forceinline__ double soft_score(double A, double mu, double mbar, double len, double t1s) {
+  if (!(A > 0.0) || mbar > kSoftMHi) return 0.0;
+  const double dm_da = (1.0 + 2.0 * A) * log1p(1.0 / A) - 2.0;
+  return (1.0 / A + 1.0 / (1.0 + A) - 2.0 / (mu + A)) * (len * t1s * (0.5 - mbar)) / dm_da;
+}
+
 // one Class II step; returns false when the particle is gone.  EXT compiles
 // in the optional physics (straggling, annihilation in flight), each behind
-// its run-time switch.
-template <typename T, bool EXT>
+// its run-time switch.  G = 1 also fills eg with the step's gradient data;
+// with `look` set it moves the particle without any other effect (no deposit,
+// secondary, statistic or event): the look-ahead pass of the second replay.
+template <typename T, bool EXT, int G = 0>
 __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const T* soft, Part<T>& p, Child<T>& c1,
-                       Child<T>& c2, DepAcc& acc, LaneStats& ls, BlockStats* bs) {
+                       Child<T>& c2, DepAcc& acc, LaneStats& ls, BlockStats* bs, EGrad& eg, bool look = false) {
+  const bool DRY = G != 0 && look;
   const int nt = tb.n;
   const int lep = p.type == POSITRON ? 1 : 0;
   const int base = T_E + lep * T_ES;
   const T eabs = a.eabs[p.type];
+  if constexpr (G != 0) {
+    eg.v = vlin(a, p.ix);
+    eg.score = 0.0;
+    eg.coef = 0.0;
+    eg.r = 1.0;
+    eg.d = a.adj_w[eg.v] * (a.vr ? p.w : 1.0);
+    eg.lam_end = 0.0;
+    eg.end = false;
+  }
   if (!(p.e > eabs)) {
-    e_absorb(a, p, c1, c2, acc, ls, bs);
+    if constexpr (G != 0) {
+      eg.end = true;
+      eg.lam_end = eg.d;
+    }
+    if (!DRY) e_absorb(a, p, c1, c2, acc, ls, bs);
     return false;
   }
-  ls.esteps++;
+  if (!DRY) ls.esteps++;
   rng_refill(p.rng);
   const T e = p.e;
   const uint32_t v = vlin(a, p.ix);
@@ -855,11 +907,15 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
   const bool capped = !(tau_h <= tau_max);
   const T tau_s = capped ? tau_max : tau_h;
   const double len = double(tau_s / rho);
+  // gradient: score of the majorant process's geometric free path, density
+  // rho smaj exp(-rho smaj s) below the cap and tail exp(-rho smaj len) at it
+  if constexpr (G != 0) eg.score = -double(smaj) * len + (capped ? 0.0 : 1.0 / double(rho));
   const double th = double(uni<T>(p.rng)) * len;
   int ax;
   const double db = face_dist(a, p, &ax);
   if (ax < 0) {
     atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+    if constexpr (G != 0) eg.end = true;
     return false;
   }
   // soft loss over the geometric length travelled: db when the face comes
@@ -875,25 +931,31 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     e1 = e - soft_straggle(tb, lep, e, e - e1, mass_path, p.rng);
     if (!(e1 > T(0))) e1 = T(0);
   }
-  deposit(a, acc, ls, p, e - e1);
+  if (!DRY) deposit(a, acc, ls, p, e - e1);
   p.e = e1;
+  if constexpr (G != 0) {
+    // d(loss)/d rho at fixed geometric length l = l S(E1); dE1/dE = S(E1)/S(E)
+    const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
+    const double s1 = double(interp(tab, nt, base + O_LS, g1, e1, T(0)));
+    eg.coef = (face_first ? db : len) * s1;
+    eg.r = s1 / double(ss);
+  }
   if (face_first) {
-    if (a.mode == 1 && e1 < e) {
-      // replay A: d(loss over the geometric length db)/d rho = db S_soft(E')
-      const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
-      const T s1 = interp(tab, nt, base + O_LS, g1, e1, T(0));
-      unsafeAtomicAdd(&a.adj_grad[v], a.adj_w[v] * db * double(s1) * (a.vr ? p.w : 1.0));
-    }
-    event(a, p, EV_CROSS, v);
+    if (!DRY) event(a, p, EV_CROSS, v);
     if (cross(a, p, db, ax, ls)) {
-      e_escape(a, p, v, bs);
+      if constexpr (G != 0) eg.end = true;
+      if (!DRY) e_escape(a, p, v, bs);
       return false;
     }
     return true;
   }
   move(p, th);
   if (!(e1 > eabs)) {
-    e_absorb(a, p, c1, c2, acc, ls, bs);
+    if constexpr (G != 0) {
+      eg.end = true;
+      eg.lam_end = eg.d;
+    }
+    if (!DRY) e_absorb(a, p, c1, c2, acc, ls, bs);
     return false;
   }
   const T t1s = interp(tab, nt, base + O_LT1S, g, e, T(0));
@@ -901,25 +963,28 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
   const T A = soft_a(mbar, soft);
   const T u3 = uni<T>(p.rng);
   const T mu = A * u3 / (T(1) + A - u3);
+  if constexpr (G != 0) eg.score += soft_score(double(A), double(mu), double(mbar), len, double(t1s));
   const T phi = T(2.0 * kPi) * uni<T>(p.rng);
   rotate(p.d, T(1) - T(2) * mu, phi);
   const double rem = len - th;
   const double db2 = face_dist(a, p, &ax);
   if (ax < 0) {
     atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+    if constexpr (G != 0) eg.end = true;
     return false;
   }
   if (db2 <= rem) {
-    event(a, p, EV_CROSS, v);
+    if (!DRY) event(a, p, EV_CROSS, v);
     if (cross(a, p, db2, ax, ls)) {
-      e_escape(a, p, v, bs);
+      if constexpr (G != 0) eg.end = true;
+      if (!DRY) e_escape(a, p, v, bs);
       return false;
     }
     return true;
   }
   move(p, rem);
   if (capped) {
-    event(a, p, EV_STEP, v);
+    if (!DRY) event(a, p, EV_STEP, v);
     return true;
   }
   // hard event or delta: elastic, inelastic, bremsstrahlung in this order.
@@ -935,12 +1000,17 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     if (kind == 0 && a.annih && lep && u < s_el + s_in + s_br + sigma_annih(tb, e1)) kind = 4;
   }
   if (kind == 0) {
-    stat_add(bs, S_DELTA);
-    event(a, p, EV_STEP, v);
+    if (!DRY) {
+      stat_add(bs, S_DELTA);
+      event(a, p, EV_STEP, v);
+    }
     return true;
   }
   if constexpr (EXT) {
     if (kind == 4) {
+      // the photons take the positron's energy away: no energy adjoint beyond
+      if constexpr (G != 0) eg.end = true;
+      if (DRY) return false;
       // two-photon annihilation with an electron at rest: the softer photon
       // takes the share z of E + 2mc^2, z in [zmin, 1/2], from Heitler's DCS
       // S(z) + S(1-z), S(x) = -(g+1)^2 + (g^2+4g+1)/x - 1/x^2: proposal 1/z
@@ -948,6 +1018,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
       // polar cosines (g + 1 - 1/z)/p from energy-momentum conservation, the
       // photons on opposite azimuths
       stat_add(bs, S_ANNIH);
+      stat_add(bs, S_ANNIH_FLIGHT);
       const T gm = T(1) + e1 / T(kMc2);
       const T pm = M<T>::sqrt(gm * gm - T(1));
       const T zmin = T(1) / (gm + T(1) + pm);
@@ -979,7 +1050,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
   }
   T cos_p = T(1), cos_c = T(1), w = T(0);  // primary and secondary polar cosines, energy lost
   if (kind == 1) {
-    stat_add(bs, S_HARD_EL);
+    if (!DRY) stat_add(bs, S_HARD_EL);
     // screened Rutherford restricted to [mu_c, 1]
     const T p2 = e1 * (e1 + T(2.0 * kMc2));
     const T et = e1 + T(kMc2);
@@ -994,7 +1065,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     m = m < T(0) ? T(0) : (m > T(1) ? T(1) : m);
     cos_p = T(1) - T(2) * m;
   } else if (kind == 2) {
-    stat_add(bs, S_HARD_IN);
+    if (!DRY) stat_add(bs, S_HARD_IN);
     // Moller (e-) or Bhabha (e+) energy transfer k = W/E above kc = Wcc/E:
     // proposal ~ 1/k^2 on [kc, 1/2] (e-) or [kc, 1] (e+), then rejection
     const T kc = a.wcc / e1;
@@ -1029,7 +1100,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     cos_p = binary_cos(e1, w, true);
     cos_c = binary_cos(e1, w, false);
   } else {
-    stat_add(bs, S_HARD_BR);
+    if (!DRY) stat_add(bs, S_HARD_BR);
     w = a.wcr * M<T>::pow(e1 / a.wcr, uni<T>(p.rng));
     cos_c = leading_angle(beta_of(e1), uni<T>(p.rng));
   }
@@ -1038,7 +1109,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     // the secondary leaves from the direction before the event: the knock-on
     // electron on the opposite azimuth, the photon on the drawn one
     T dc[3] = {p.d[0], p.d[1], p.d[2]};
-    rotate(dc, cos_c, kind == 2 ? ph + T(kPi) : ph);
+    if (!DRY) rotate(dc, cos_c, kind == 2 ? ph + T(kPi) : ph);
     // interaction forcing: the channel's cross section is F times the
     // analog one; the event changes the primary with probability 1/F (a draw
     // after the azimuth's) and its secondary carries weight w/F
@@ -1059,22 +1130,24 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     if (split) {
       const T c2c = leading_angle(beta_of(e1), uni<T>(p.rng));
       const T ph2 = T(2.0 * kPi) * uni<T>(p.rng);
-      rotate(d2, c2c, ph2);
+      if (!DRY) rotate(d2, c2c, ph2);
       fw *= 2.0;
     }
     if (apply) {
       if (kind == 2) rotate(p.d, cos_p, ph);
       p.e = e1 - w;
     }
-    const double w0 = p.w;
-    p.w = w0 / fw;
-    make_child(a, p, c1, kind == 2 ? ELECTRON : PHOTON, w, dc, acc, ls, bs);
-    if (split) make_child(a, p, c2, PHOTON, w, d2, acc, ls, bs);
-    p.w = w0;
+    if (!DRY) {
+      const double w0 = p.w;
+      p.w = w0 / fw;
+      make_child(a, p, c1, kind == 2 ? ELECTRON : PHOTON, w, dc, acc, ls, bs);
+      if (split) make_child(a, p, c2, PHOTON, w, d2, acc, ls, bs);
+      p.w = w0;
+    }
   } else {
     rotate(p.d, cos_p, ph);
   }
-  event(a, p, kind == 1 ? EV_HARD_EL : (kind == 2 ? EV_HARD_IN : EV_HARD_BR), v);
+  if (!DRY) event(a, p, kind == 1 ? EV_HARD_EL : (kind == 2 ? EV_HARD_IN : EV_HARD_BR), v);
   return true;
 }
 
@@ -1117,6 +1190,12 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
   Part<T> p;
   DepAcc acc = dep_init();
   bool alive = false, taking = true;
+  constexpr bool ADJB = base_flavor(F) == FL_ADJ_B;
+  // second replay: the look-ahead phase, the particle's input record and its
+  // energy-adjoint sums
+  bool ahead = false;
+  uint32_t rec = 0;
+  double lam_tot = 0.0, lam_pre = 0.0, lam_p = 1.0;
   uint32_t used = 0, dry = 0;
   uint32_t rbase = 0, rleft = 0;  // the wavefront's reserved input records [rbase, rbase + rleft)
   for (;;) {
@@ -1145,6 +1224,14 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
         load_part(a, in, striped_record(sums, idx, cs), p);
         alive = true;
         used = 0;
+        if constexpr (ADJB) {
+          // second replay: first follow the particle's whole remaining track
+          // without effects (the look-ahead), then again from its record
+          ahead = true;
+          rec = striped_record(sums, idx, cs);
+          lam_tot = 0.0;
+          lam_p = 1.0;
+        }
       }
     } else {
       ++dry;
@@ -1155,20 +1242,42 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     c1.on = false;
     c2.on = false;
     if (alive) {
+      EGrad eg;
+      constexpr int G = ADJB ? 1 : 0;
+      const bool look = ADJB && ahead;
       if constexpr (MMF) {
         // the step stays in its voxel, so in one material
         const uint32_t m = a.mat[vlin(a, p.ix)];
-        const MatConst<T> mc = mat_const(a.tb, m);
-        Tab<T> tbm = a.tb;
-        tbm.k_coef = mc.k_coef;
-        tbm.eta_a = mc.eta_a;
-        tbm.eta_b = mc.eta_b;
-        tbm.strag_k = mc.strag_k;
-        tbm.strag_b = mc.strag_b;
-        tbm.annih_k = mc.annih_k;
-        alive = e_step<T, true>(a, tbm, a.tb.t + mat_block(int(m), ntab), tab, p, c1, c2, acc, ls, &bs);
+        alive = e_step<T, true, G>(a, mat_tab(a.tb, m), a.tb.t + mat_block(int(m), ntab), tab, p, c1, c2, acc, ls,
+                                   &bs, eg, look);
       } else {
-        alive = e_step<T, extended(F)>(a, a.tb, tab, tab + T_NCH * ntab, p, c1, c2, acc, ls, &bs);
+        alive = e_step<T, extended(F), G>(a, a.tb, tab, tab + T_NCH * ntab, p, c1, c2, acc, ls, &bs, eg, look);
+      }
+      if constexpr (ADJB) {
+        if (look) {
+          // lam_tot = sum_k d_k (1 - r_k) P_k + lam_end P_K, P_k the product of
+          // the chain factors before step k: every later step's energy
+          // adjoint follows from it and the sums before that step
+          lam_tot += eg.d * (1.0 - eg.r) * lam_p;
+          lam_p *= eg.r;
+          if (!alive) {
+            lam_tot += eg.lam_end * lam_p;
+            load_part(a, in, rec, p);  // back to the record for the second pass
+            alive = true;
+            ahead = false;
+            lam_pre = 0.0;
+            lam_p = 1.0;
+          }
+        } else {
+          // the history's centred score times the step's scores, and the soft
+          // loss it deposits here minus what the particle then lacks downstream
+          lam_pre += eg.d * (1.0 - eg.r) * lam_p;
+          lam_p *= eg.r;
+          const double lam_after = eg.end ? eg.lam_end : (lam_tot - lam_pre) / lam_p;
+          const double cq = a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar;
+          const double gv = cq * eg.score + eg.coef * (eg.d - lam_after);
+          if (gv != 0.0) unsafeAtomicAdd(&a.adj_grad[eg.v], gv);
+        }
       }
       ++used;
     }
@@ -1176,7 +1285,9 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
     // secondaries of this step and particles written back: one atomic per
     // output queue and wavefront, both in flight together
     const bool tail = dry >= MCX_TAIL_MIN && __popcll(__ballot(alive)) < MCX_TAIL_ALIVE;  // wave-uniform
-    const bool park = alive && (used >= a.steps || tail);
+    // (the second replay follows each particle to its end: its look-ahead
+    // covers the whole remaining track)
+    const bool park = !ADJB && alive && (used >= a.steps || tail);
     const bool c1e = c1.on && c1.type != PHOTON, c1g = c1.on && c1.type == PHOTON;
     const uint64_t me1 = __ballot(c1e), mep = __ballot(park), mg1 = __ballot(c1g), mg2 = __ballot(c2.on);
     const uint32_t ne1 = uint32_t(__popcll(me1)), ng1 = uint32_t(__popcll(mg1));

@@ -141,3 +141,88 @@ def test_two_material_layered_absorber_gradient_closed_form():
     # the one-material score (water's mu everywhere) misses the bone layers
     wrong = O.Tables(W.WATER, t).eval(O.MU_PHOTO, e0)
     assert mu.max() / wrong > 5.0
+
+
+def test_soft_deflection_score_reproduces_moment_derivatives():
+    """Term C of the Class II gradient is the score d ln p(mu)/d rho of the
+    soft angular law p(mu) = A(1+A)/(mu+A)^2, A matched to the mean
+    <mu> = (1 - exp(-rho len t1s))/2.  A score must average to 0 and turn
+    any moment into its derivative: E[mu s] = d<mu>/d rho = len t1s (1/2 -
+    <mu>), and E[mu^2 s] = d E[mu^2]/d rho with the closed form
+    E[mu^2] = A(1+A)(1 - 2A ln(1 + 1/A)) + A^2, differentiated numerically
+    through A(<mu>(rho))."""
+    tb = O.Tables(W.WATER, W.transport())
+    length, t1s = 0.07, 3.0
+
+    def m2(mbar):
+        a = O.soft_a(mbar)
+        return a * (1 + a) * (1 - 2 * a * math.log1p(1 / a)) + a * a
+
+    for mbar in (1e-3, 0.02, 0.1, 0.3):
+        rho = -math.log(1 - 2 * mbar) / (length * t1s)
+        a = O.soft_a(mbar)
+        mu = tb.sample("soft", mbar, 300000, seed=3)[0]
+        sc = np.array([O.soft_score(a, m, mbar, length, t1s) for m in mu])
+        n = sc.size
+        assert abs(sc.mean()) < 5 * sc.std() / math.sqrt(n)
+        d1 = length * t1s * (0.5 - mbar)
+        e1 = mu * sc
+        assert abs(e1.mean() - d1) < 5 * e1.std() / math.sqrt(n), (mbar, e1.mean(), d1)
+        h = 1e-5 * rho
+        mb = lambda r: 0.5 * (1 - math.exp(-r * length * t1s))
+        d2 = (m2(mb(rho + h)) - m2(mb(rho - h))) / (2 * h)
+        e2 = mu * mu * sc
+        assert abs(e2.mean() - d2) < 5 * e2.std() / math.sqrt(n), (mbar, e2.mean(), d2)
+
+
+def _csda_layers(n):
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.5, 2.0, size=8)
+    ph = W.slab_phantom(8, 0.2, rho)
+    ph["step_cap"] = np.full(ph["shape"], 0.013)  # a fixed geometric step cap (cm)
+    t = dict(W.transport(), flags=O.NO_HARD_ELASTIC | O.NO_HARD_INELASTIC | O.NO_HARD_BREMS)
+    mat = dict(W.WATER, zz1_mol=W.WATER["zz1_mol"] * 1e-9)  # no angular deflection to speak of
+    tb = O.Tables(mat, t)
+    src = [W.pencil(1, 3.0, (50.0, 50.0, 0.0), n)]
+    c = rng.uniform(-1.0, 1.0, size=8).reshape(8, 1, 1)
+    return ph, tb, src, c
+
+
+def test_pathwise_soft_loss_and_energy_adjoint_vs_finite_differences():
+    """Term D with its energy adjoint, checked where it is the whole
+    gradient: 3 MeV electrons through eight layers (densities 0.5-2) with
+    every hard channel off and no deflection, the step cap's geometric length
+    held fixed (step_cap; with the algorithm's cap tau_max(E)/rho, a change
+    of energy upstream moves every later step boundary and the difference
+    quotient follows the saw-tooth of the steps that straddle a face).  Every history is then a straight CSDA track
+    whose deposits, at fixed random numbers, are smooth functions of the
+    densities, so common-random-number central differences of the oracle's
+    own dose (h = 1e-4) are the pathwise derivative of the same sample: the
+    estimator's pathwise part (each layer's loss l S(E') at fixed l, minus
+    what the electron lacks downstream through the chain dE'/dE =
+    S(E')/S(E)) plus the mass term must equal them layer by layer.  (The
+    likelihood-ratio part is a mean-zero term of another representation of
+    the same derivative, not part of this sample's pathwise one.)"""
+    n = 50
+    ph, tb, src, c = _csda_layers(n)
+    r = O.run(tb, ph, src, 1, 0, n)
+    d, _ = O.dose(ph, r)
+    g, parts = O.gradient(tb, ph, src, 1, 0, n, c, d)
+    g = g.ravel() - (parts["a"] - parts["qbar"] * parts["b"]) / n  # pathwise + mass terms
+    h = 1e-4
+    fd = np.zeros(8)
+    for j in range(8):
+        vals = []
+        for sg in (1, -1):
+            p2 = dict(ph, rho=ph["rho"].copy())
+            p2["rho"][j] *= 1 + sg * h
+            rr = O.run(tb, p2, src, 1, 0, n)
+            dd, _ = O.dose(p2, rr)
+            vals.append(float((c * dd).sum()))
+        fd[j] = (vals[0] - vals[1]) / (2 * h * ph["rho"][j, 0, 0])
+    err = np.abs(g - fd) / np.abs(fd).max()
+    print("estimator", np.round(g, 3), "fd", np.round(fd, 3), "max rel", err.max())
+    assert err.max() < 1e-4
+    # the pathwise term is what moves: without its downstream part the
+    # estimate would be far off
+    assert np.abs(parts["p"]).max() > 0.1 * np.abs(fd).max() * n
