@@ -61,6 +61,50 @@ def high_dose_deviation(d_mix: np.ndarray, d_64: np.ndarray) -> dict:
                 sum_ratio=float(d_mix.sum() / d_64.sum()))
 
 
+def depth_dose(d: np.ndarray) -> np.ndarray:
+    """Dose summed over each depth plane (z is the first axis)."""
+    return d.reshape(d.shape[0], -1).sum(axis=1)
+
+
+def paired_deviation(d_mix: list, d_64: list) -> dict:
+    """Mixed against FP64 on the same streams, K batches (one per seed):
+    the deviation Delta_b = D_mix,b - D_64,b of each batch splits into a
+    systematic part, the mean over batches, and a statistical part (the few
+    histories whose FP32 rounding took another branch), whose size the
+    batch-to-batch spread measures.  Over the voxels with D_64 >= 50% of the
+    maximum: the mean relative shift with its standard error; the RMS of the
+    per-voxel mean shift and the RMS its noise alone would give; the
+    systematic RMS that remains, sqrt(max(0, rms^2 - noise^2)); the same
+    for the depth-dose curve (dose summed over each plane, planes above half
+    its maximum)."""
+    k = len(d_mix)
+    dm = np.array([a - b for a, b in zip(d_mix, d_64)])
+    d64 = np.mean(d_64, axis=0)
+    hi = d64 >= 0.5 * d64.max()
+    rel = dm[:, hi] / d64[hi]
+    out = dict(batches=k, voxels=int(hi.sum()), per_batch_rms=float(np.sqrt(np.mean(rel ** 2))))
+    if k < 2:
+        return out
+    mean_v = rel.mean(axis=0)
+    se_v = rel.std(axis=0, ddof=1) / np.sqrt(k)
+    shift_b = rel.mean(axis=1)  # each batch's mean relative shift over the set
+    rms = float(np.sqrt(np.mean(mean_v ** 2)))
+    noise = float(np.sqrt(np.mean(se_v ** 2)))
+    pdd = np.array([depth_dose(a) - depth_dose(b) for a, b in zip(d_mix, d_64)])
+    p64 = depth_dose(d64)
+    ph = p64 >= 0.5 * p64.max()
+    prel = pdd[:, ph] / p64[ph]
+    pm, pse = prel.mean(axis=0), prel.std(axis=0, ddof=1) / np.sqrt(k)
+    prms, pnoise = float(np.sqrt(np.mean(pm ** 2))), float(np.sqrt(np.mean(pse ** 2)))
+    out.update(mean_shift=float(shift_b.mean()), mean_shift_se=float(shift_b.std(ddof=1) / np.sqrt(k)),
+               rms_of_mean=rms, rms_noise=noise, systematic_rms=float(np.sqrt(max(0.0, rms ** 2 - noise ** 2))),
+               z_mean=float(np.mean(mean_v / np.where(se_v > 0, se_v, np.inf))),
+               depth_planes=int(ph.sum()), depth_rms_of_mean=prms, depth_rms_noise=pnoise,
+               depth_systematic_rms=float(np.sqrt(max(0.0, prms ** 2 - pnoise ** 2))),
+               depth_max=float(np.max(np.abs(pm))))
+    return out
+
+
 def roofline(st: dict) -> dict:
     """Roofline of the dominant kernel (k_estep, the mixed Class II step) over
     the timed launches.  The step is bound by VALU issue: `achieved` is the
@@ -124,7 +168,9 @@ def target_detector_efficiency(mcx, W, sync, args, n: int = 1_000_000) -> dict:
                 histories=n, analog=res["analog"], forced=res["forced"], efficiency_gain=float(eff))
 
 
-def run_steps(sim, n, seeds, sync):
+def run_steps(sim, n, seeds, sync, doses=None):
+    """One timed run per seed (tallies reset before each); with `doses`, each
+    step's dose is appended to it after the timed region."""
     times = []
     for s in seeds:
         sim.reset()
@@ -133,6 +179,8 @@ def run_steps(sim, n, seeds, sync):
         sim.run(s, 0, n)
         sync()
         times.append(time.perf_counter() - t0)
+        if doses is not None:
+            doses.append(sim.dose()[0])
     return times
 
 
@@ -173,7 +221,7 @@ def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
 
 
 def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: int = 10, n_vox: int = 16,
-                      h: float = 0.01) -> dict:
+                      h: float = 0.01, transport: dict | None = None) -> dict:
     """The replay gradient against common-random-number central differences
     on the same workload: 16 voxels drawn (PCG64 seed 6) among those inside
     the field with D >= 10% of the maximum; each batch b (seed 100 + b,
@@ -182,6 +230,8 @@ def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: i
     and histories; L = sum_v (D_v - T_v)^2 with the target frozen.  Means and
     standard errors over the batches."""
     wl = W.workload("hetero_broad_64", n_batch)
+    if transport is not None:
+        wl["transport"] = transport
     ph = wl["phantom"]
     sim = mcx.Simulator(mcx.FP64, 0).setup(wl)
     sim.run(99, 0, n_batch)
@@ -231,14 +281,11 @@ def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: i
     m, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(batches)
     f, fse = fd.mean(0), fd.std(0, ddof=1) / np.sqrt(batches)
     zz = (m - f) / np.sqrt(se ** 2 + fse ** 2)
-    # one bias figure: the least-squares slope of the replay gradient on the
-    # finite differences (1 = unbiased), with its standard error from the
-    # batch-to-batch spread of both
-    slope = float(np.dot(m, f) / np.dot(f, f))
-    sl_b = [np.dot(est[b], f) / np.dot(f, f) for b in range(batches)]
+
     return dict(voxels=vox, replay=m.tolist(), replay_se=se.tolist(), fd=f.tolist(), fd_se=fse.tolist(),
+                replay_batches=est.tolist(), fd_batches=fd.tolist(),
                 z=zz.tolist(), z_mean=float(zz.mean()), z_rms=float(np.sqrt((zz ** 2).mean())),
-                z_max=float(np.abs(zz).max()), slope=slope, slope_se=float(np.std(sl_b, ddof=1) / np.sqrt(batches)),
+                z_max=float(np.abs(zz).max()), chi2=float((zz ** 2).sum()), dof=n_vox,
                 h=h, batches=batches, histories_per_batch=n_batch, replay_s=t_grad, fd_s=t_fd)
 
 
@@ -301,44 +348,66 @@ def _oracle_shard(args):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(name: str, n_per_proc: int, procs: int) -> dict:
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name: str, n_per_proc: int, procs: int, repeats: int = 3) -> dict:
     """The oracle on the host cores, sharded by history range over `procs`
     processes (independent histories, as the paper's multi-process runs): the
-    rate is the histories over the slowest shard's time (setup excluded)."""
+    rate is the histories over the slowest shard's time (setup excluded),
+    the median of `repeats` repetitions."""
     import concurrent.futures as cf
     import multiprocessing as mp
     jobs = [(name, k * n_per_proc, n_per_proc) for k in range(procs)]
+    rates, singles, slow, work = [], [], [], []
     with cf.ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
-        times = list(ex.map(_oracle_shard, jobs))
-    rate = procs * n_per_proc / max(times)
-    return dict(value=rate, unit="histories/s", cores=procs, kind="oracle",
-                single_core=n_per_proc / (sum(times) / len(times)),
+        for _ in range(repeats):
+            times = list(ex.map(_oracle_shard, jobs))
+            rates.append(procs * n_per_proc / max(times))
+            singles.append(n_per_proc / (sum(times) / len(times)))
+            slow.append(max(times))
+            work.append(sum(times))
+    i = int(np.argsort(rates)[len(rates) // 2])
+    return dict(value=rates[i], unit="histories/s", cores=procs, kind="oracle", host_cpu=host_cpu(),
+                host_logical_cpus=os.cpu_count(), single_core=float(np.median(singles)), repeats=repeats,
                 sample=f"histories [0, {procs * n_per_proc}) of the same workload in {procs} single-thread FP64 "
-                       f"oracle processes of {n_per_proc} histories each ({max(times):.1f} s the slowest, "
-                       f"{sum(times):.0f} s of CPU work)")
+                       f"oracle processes of {n_per_proc} histories each, median of {repeats} repetitions "
+                       f"({slow[i]:.1f} s the slowest shard, {work[i]:.0f} s of CPU work)")
 
 
-def electron_comparison(mcx, W, sync, n: int = 1_000_000) -> dict:
+def electron_comparison(mcx, W, sync, n: int = 1_000_000, batches: int = 4) -> dict:
     """20 MeV electron pencil on a 200^3 x 1 mm water cube: mixed and FP64 on
-    the same streams."""
+    the same streams, `batches` runs of n histories each.  A pencil's dose
+    has few voxels near its maximum, so the high-dose sets are the voxels
+    with D >= 10% of the maximum and the depth-dose planes above half the
+    depth-dose maximum."""
     wl = W.workload("electron_200", n)
     out = {}
     doses = {}
+    seeds = [1 + i for i in range(batches)]
     for name, prec in (("mixed", mcx.MIXED), ("fp64", mcx.FP64)):
         sim = mcx.Simulator(prec, 0).setup(wl)
         sim.run(777, 0, min(n, 100_000))
-        sim.reset()
-        sync()
-        t0 = time.perf_counter()
-        sim.run(1, 0, n)
-        sync()
-        dt = time.perf_counter() - t0
-        doses[name], _ = sim.dose()
+        doses[name] = []
+        t = run_steps(sim, n, seeds, sync, doses[name])
         sim.close()
-        out[name] = dict(value=n / dt, ms=1e3 * dt)
+        out[name] = dict(value=n * len(t) / sum(t), ms=1e3 * sum(t) / len(t))
     out["mixed_over_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    out["high_dose_deviation"] = high_dose_deviation(doses["mixed"], doses["fp64"])
-    out["workload"] = "electron_200: 20 MeV e- pencil, 200^3 x 1 mm water, 1e6 histories"
+    pd = paired_deviation(doses["mixed"], doses["fp64"])
+    dm, d6 = np.mean(doses["mixed"], axis=0), np.mean(doses["fp64"], axis=0)
+    hi = d6 >= 0.1 * d6.max()
+    rel = (dm[hi] - d6[hi]) / d6[hi]
+    out["deviation"] = dict(depth_dose=pd, voxels_above_10pct=int(hi.sum()),
+                            voxel_rms_above_10pct=float(np.sqrt(np.mean(rel ** 2))),
+                            sum_ratio=float(dm.sum() / d6.sum()))
+    out["workload"] = f"electron_200: 20 MeV e- pencil, 200^3 x 1 mm water, {batches} x {n} histories"
     return out
 
 
@@ -350,7 +419,7 @@ def main():
     ap.add_argument("--hist", type=int, default=10_000_000, help="histories per step")
     ap.add_argument("--cpu-sample", type=int, default=6_000, help="oracle histories per host process")
     ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes (host cores used)")
-    ap.add_argument("--electron", action="store_true", help="also time the 20 MeV electron workload")
+    ap.add_argument("--no-electron", action="store_true", help="skip the 20 MeV electron workload")
     ap.add_argument("--straggling", action="store_true",
                     help="also time the mixed step with soft energy-loss straggling on")
     ap.add_argument("--materials", action="store_true",
@@ -368,8 +437,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--no-fd-check", action="store_true", help="skip the finite-difference check of the gradient")
-    ap.add_argument("--beamlets", type=int, default=0, metavar="TOTAL",
-                    help="also time 512 beamlets with TOTAL histories batched vs one run each")
+    ap.add_argument("--beamlets", type=int, default=50_000_000, metavar="TOTAL",
+                    help="512 beamlets with TOTAL histories batched vs one run each (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -406,7 +475,8 @@ def main():
     mix.set_launch(args.bank, 256, 128)
     run_steps(mix, n, warm_seeds, sync)
     mix.set_timing(True)
-    t_mix = run_steps(mix, n, seeds, sync)
+    doses_mix = []
+    t_mix = run_steps(mix, n, seeds, sync, doses_mix)
     st = mix.stats()
     d_mix, s_mix = mix.dose()
     mix.close()
@@ -416,11 +486,15 @@ def main():
         f64 = mcx.Simulator(mcx.FP64, 0).setup(wl)
         f64.set_launch(args.bank, 256, 128)
         run_steps(f64, n, warm_seeds, sync)
-        t_64 = run_steps(f64, n, seeds, sync)
+        doses_64 = []
+        t_64 = run_steps(f64, n, seeds, sync, doses_64)
         d_64, _ = f64.dose()
         f64.close()
         result_64 = dict(value=n * len(t_64) / sum(t_64), ms_per_step=1e3 * sum(t_64) / len(t_64))
         dev = high_dose_deviation(d_mix, d_64)
+        # the timed steps as paired batches: systematic part and noise floor
+        dev["paired_batches"] = paired_deviation(doses_mix, doses_64)
+        del doses_mix, doses_64
 
     value = n * len(t_mix) / sum(t_mix)
     ms = {"k_source": st["ms_source"], "k_flight": st["ms_flight"], "k_knock": st["ms_knock"],
@@ -512,9 +586,10 @@ def main():
         if not args.no_fd_check:
             out["gradient"]["fd_check"] = gradient_fd_check(mcx, W, sync, target)
     if args.beamlets:
-        out["beamlets"] = beamlet_comparison(mcx, W, sync, args.beamlets,
-                                             os.path.join(ROOT, "gpurun_out", "autotune_cache.jsonl"))
-    if args.electron:
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            out["beamlets"] = beamlet_comparison(mcx, W, sync, args.beamlets, os.path.join(td, "autotune.jsonl"))
+    if not args.no_electron:
         out["electron"] = electron_comparison(mcx, W, sync)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline("hetero_broad_128", args.cpu_sample, args.cpu_procs)

@@ -31,16 +31,17 @@ __device__ __forceinline__ uint32_t source_of(const SourceDev* src, int nsrc, ui
 
 // the chunk flush of k_flush (Sum q^2, run statistics, test ledger, slots
 // cleared), and each score also added to the (source, voxel) table
-__global__ void k_flush_influence(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q2, Counters* cnt,
+__global__ void k_flush_influence(TSlot* tab, uint64_t nslot, double* sum_q2, Counters* cnt,
                                   int test_mode, double* hist_led, uint64_t n_run, const SourceDev* src, int nsrc,
                                   uint64_t* ikeys, double* iq, double* iq2, uint64_t imask, uint32_t* iovf) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   uint32_t occ = 0;
   double dep = 0.0;
   for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
-    const uint64_t k = keys[s];
+    const TSlot t = tab[s];
+    const uint64_t k = t.key;
     if (k == kEmptyKey) continue;
-    const double q = vals[s];
+    const double q = t.q;
     dep += q;
     const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
     unsafeAtomicAdd(&sum_q2[v], q * q);
@@ -62,8 +63,7 @@ __global__ void k_flush_influence(uint64_t* keys, double* vals, uint64_t nslot, 
       slot = (slot + 1) & imask;
     }
     if (probe == 4096) atomicOr(iovf, 1u);
-    keys[s] = kEmptyKey;
-    vals[s] = 0.0;
+    tab[s] = TSlot{kEmptyKey, 0.0};
     ++occ;
   }
   occ = wave_sum(occ);
@@ -93,11 +93,11 @@ __global__ void k_influence_compact(const uint64_t* ikeys, const double* iq, con
 
 }  // namespace
 
-hipError_t launch_flush_influence(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q2, Counters* cnt,
+hipError_t launch_flush_influence(TSlot* tab, uint64_t nslot, double* sum_q2, Counters* cnt,
                                   int test_mode, double* hist_led, uint64_t n_run, const SourceDev* src, int nsrc,
                                   uint64_t* ikeys, double* iq, double* iq2, uint64_t imask, uint32_t* iovf,
                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_flush_influence, dim3(8192), dim3(256), 0, s, keys, vals, nslot, sum_q2, cnt, test_mode,
+  hipLaunchKernelGGL(k_flush_influence, dim3(8192), dim3(256), 0, s, tab, nslot, sum_q2, cnt, test_mode,
                      hist_led, n_run, src, nsrc, ikeys, iq, iq2, imask, iovf);
   return hipGetLastError();
 }

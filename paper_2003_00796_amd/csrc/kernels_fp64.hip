@@ -60,9 +60,15 @@ hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   return hipGetLastError();
 }
 
-hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
+hipError_t launch_clear_table(TSlot* tab, uint64_t nslot, hipStream_t s) {
+  const unsigned g = unsigned(std::min<uint64_t>((nslot + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_clear_table<double>, dim3(g), dim3(256), 0, s, tab, nslot);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(TSlot* tab, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
                         int test_mode, double* hist_led, uint64_t n_run, hipStream_t s) {
-  hipLaunchKernelGGL(k_flush<double>, dim3(8192), dim3(256), 0, s, keys, vals, nslot, sum_q, sum_q2, cnt, test_mode,
+  hipLaunchKernelGGL(k_flush<double>, dim3(8192), dim3(256), 0, s, tab, nslot, sum_q, sum_q2, cnt, test_mode,
                      hist_led, n_run);
   return hipGetLastError();
 }

@@ -17,7 +17,9 @@ hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int
                             hipEvent_t* ev);
 hipError_t launch_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t run_first, uint32_t adm,
                              hipStream_t s);
-hipError_t launch_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
+// the chunk flush of the tally table, and the clearing of a table
+hipError_t launch_clear_table(TSlot* tab, uint64_t nslot, hipStream_t s);
+hipError_t launch_flush(TSlot* tab, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
                         int test_mode, double* hist_led, uint64_t n_run, hipStream_t s);
 hipError_t launch_dose(const double* sum_q, const double* sum_q2, const double* rho, uint64_t nvox, double vol,
                        double nhist, double* dose, double* sigma, hipStream_t s);
@@ -37,7 +39,7 @@ hipError_t launch_adjoint_finalize(const double* grad_acc, const double* dl_ddos
 hipError_t launch_sum(const double* q, uint64_t n, double* out, hipStream_t s);
 // per-source dose influence: the chunk flush that also adds every score to
 // the (source, voxel) table, and the table's compaction into arrays
-hipError_t launch_flush_influence(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q2, Counters* cnt,
+hipError_t launch_flush_influence(TSlot* tab, uint64_t nslot, double* sum_q2, Counters* cnt,
                                   int test_mode, double* hist_led, uint64_t n_run, const SourceDev* src, int nsrc,
                                   uint64_t* ikeys, double* iq, double* iq2, uint64_t imask, uint32_t* iovf,
                                   hipStream_t s);

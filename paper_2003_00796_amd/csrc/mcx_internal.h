@@ -8,9 +8,10 @@
 //  - particle queues: Q_NQ structure-of-arrays banks of `cap` records each
 //    (positions f64 x3, direction T x3, energy T, uid u64, history u32, draw
 //    counter u32, packed voxel u32, type/child-count u32, event hash u64);
-//  - tally: open-addressing table of (history, voxel) keys with an FP64 score
-//    each, flushed per chunk into Sum q / Sum q^2 (FP64, one per voxel) --
-//    the per-history estimator of Eq. (1)-(3) of the paper.
+//  - tally: open-addressing table of 16-byte slots, a (history, voxel) key
+//    and its FP64 score on one line, flushed per chunk into Sum q / Sum q^2
+//    (FP64, one per voxel) -- the per-history estimator of Eq. (1)-(3) of
+//    the paper.
 #pragma once
 
 #include <stdint.h>
@@ -129,6 +130,13 @@ constexpr int rec_chunks() {
   return sizeof(T) == 8 ? 5 : 4;
 }
 
+// one slot of the (history, voxel) tally table: the key and its score share
+// a 16-byte line segment, so an insertion dirties one cache line
+struct alignas(16) TSlot {
+  uint64_t key;
+  double q;
+};
+
 template <typename T>
 struct Bank {
   Chunk* c[kMaxChunks];
@@ -205,8 +213,7 @@ struct KArgs {
   const SourceDev* src;
   int nsrc;
   // tally hash table, key = history id << 32 | voxel index
-  uint64_t* hkeys;
-  double* hvals;
+  TSlot* htab;
   uint64_t hmask;
   double* sum_q;
   double* sum_q2;

@@ -77,7 +77,7 @@ struct mcx_ctx {
   Counters* h_cnt = nullptr;  // pinned
   // tally table
   uint64_t hslots = 1ull << MCX_TALLY_LOG2;  // keys and scores, 16 B a slot
-  DevBuf d_hkeys, d_hvals;
+  DevBuf d_htab;  // TSlot[hslots]
   double pairs_per_hist = 0.0;
   bool table_dirty = false;  // a failed run may have left entries behind
   // caller-owned workspace (mcx_set_workspace): queues, counters and tally
@@ -219,13 +219,11 @@ int carve_workspace(mcx_ctx* c) {
   char* base = static_cast<char*>(c->ws);
   const size_t qb = align256(queue_bytes(c));
   c->d_queues = DevBuf{base, qb, true};
-  c->d_hkeys = DevBuf{base + fixed, slots * sizeof(uint64_t), true};
-  c->d_hvals = DevBuf{base + fixed + slots * sizeof(uint64_t), slots * sizeof(double), true};
+  c->d_htab = DevBuf{base + fixed, slots * kSlotBytes, true};
   c->hslots = slots;
   c->queue_cap_built = c->cap;
   c->ws_cap = c->cap;
-  hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, slots * sizeof(uint64_t), c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, slots * sizeof(double), c->stream);
+  hipError_t e = launch_clear_table(static_cast<TSlot*>(c->d_htab.p), slots, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "clear workspace");
   c->table_dirty = false;
@@ -244,11 +242,9 @@ int ensure_workspace(mcx_ctx* c) {
   // fresh allocations are cleared on the context's stream (non-blocking, so
   // it does not order against the null stream) and waited for: reused device
   // memory may still hold an earlier context's entries
-  if (!c->d_hkeys.p) {
-    if ((rc = dalloc(c, c->d_hkeys, c->hslots * sizeof(uint64_t), "tally keys"))) return rc;
-    if ((rc = dalloc(c, c->d_hvals, c->hslots * sizeof(double), "tally values"))) return rc;
-    hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, c->hslots * sizeof(double), c->stream);
+  if (!c->d_htab.p) {
+    if ((rc = dalloc(c, c->d_htab, c->hslots * kSlotBytes, "tally table"))) return rc;
+    hipError_t e = launch_clear_table(static_cast<TSlot*>(c->d_htab.p), c->hslots, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "clear tally table");
   }
@@ -305,8 +301,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.seed = seed;
   a.src = static_cast<const SourceDev*>(c->d_src.p);
   a.nsrc = int(c->src.size());
-  a.hkeys = static_cast<uint64_t*>(c->d_hkeys.p);
-  a.hvals = static_cast<double*>(c->d_hvals.p);
+  a.htab = static_cast<TSlot*>(c->d_htab.p);
   a.hmask = c->hslots - 1;
   a.sum_q = static_cast<double*>(c->d_sumq.p);
   a.sum_q2 = static_cast<double*>(c->d_sumq2.p);
@@ -478,12 +473,12 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
     auto tf = std::chrono::steady_clock::now();
     uint32_t iovf = 0;
     if (c->influence) {
-      e = launch_flush_influence(a.hkeys, a.hvals, slots, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, a.src, a.nsrc,
+      e = launch_flush_influence(a.htab, slots, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, a.src, a.nsrc,
                                  static_cast<uint64_t*>(c->d_ikeys.p), static_cast<double*>(c->d_iq.p),
                                  static_cast<double*>(c->d_iq2.p), c->islots - 1, static_cast<uint32_t*>(c->d_iovf.p), s);
       if (e == hipSuccess) e = hipMemcpyAsync(&iovf, c->d_iovf.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     } else {
-      e = launch_flush(a.hkeys, a.hvals, slots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
+      e = launch_flush(a.htab, slots, a.sum_q, a.sum_q2, a.cnt, c->test_mode, a.hist_led, n, s);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, a.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -554,19 +549,6 @@ void* static_scratch(int dev, hipError_t* rc) {
   }
   *rc = g_scratch_rc[dev];
   return g_scratch[dev];
-}
-
-// fill n 64-bit words (a kernel, not a memset: a caller may capture the work
-// of a static run into a graph)
-__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
-}
-
-hipError_t fill_u64(void* p, uint64_t n, uint64_t v, hipStream_t s) {
-  const unsigned g = unsigned(std::min<uint64_t>((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, s, static_cast<uint64_t*>(p), n, v);
-  return hipGetLastError();
 }
 
 // checks shared by mcx_run and mcx_run_static
@@ -641,8 +623,8 @@ void mcx_destroy(mcx_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
-  for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_cube, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_hkeys,
-                    &c->d_hvals, &c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf, &c->d_vmat, &c->d_adj_w, &c->d_adj_q,
+  for (DevBuf* b : {&c->d_tab, &c->d_rho, &c->d_cube, &c->d_src, &c->d_sumq, &c->d_sumq2, &c->d_queues, &c->d_cnt, &c->d_htab,
+                    &c->d_ikeys, &c->d_iq, &c->d_iq2, &c->d_iovf, &c->d_vmat, &c->d_adj_w, &c->d_adj_q,
                     &c->d_adj_grad,
                     &c->d_adj_dl, &c->d_adj_out,
                     &c->d_adj_sum, &c->d_hhash, &c->d_hled})
@@ -1038,8 +1020,7 @@ int mcx_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* stream)
   if (n == 0) return MCX_OK;
   if ((rc = ensure_workspace(c))) return rc;
   if (c->table_dirty) {
-    hipError_t e = hipMemsetAsync(c->d_hkeys.p, 0xFF, c->hslots * sizeof(uint64_t), s);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_hvals.p, 0, c->hslots * sizeof(double), s);
+    hipError_t e = launch_clear_table(static_cast<TSlot*>(c->d_htab.p), c->hslots, s);
     if (e != hipSuccess) return hip_fail(c, e, "clear tally table");
   }
   c->table_dirty = true;
@@ -1077,18 +1058,17 @@ int mcx_run_static(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* 
   struct Saved {
     mcx_ctx* c;
     uint32_t cap;
-    DevBuf q, k, v;
+    DevBuf q, t;
     uint64_t hslots;
     size_t built;
     ~Saved() {
       c->cap = cap;
       c->d_queues = q;
-      c->d_hkeys = k;
-      c->d_hvals = v;
+      c->d_htab = t;
       c->hslots = hslots;
       c->queue_cap_built = built;
     }
-  } saved{c, c->cap, c->d_queues, c->d_hkeys, c->d_hvals, c->hslots, c->queue_cap_built};
+  } saved{c, c->cap, c->d_queues, c->d_htab, c->hslots, c->queue_cap_built};
   c->cap = std::min(c->cap, kStaticBank);
   const size_t qb = align256(queue_bytes(c));
   uint64_t slots = kTableSlots;
@@ -1097,13 +1077,12 @@ int mcx_run_static(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n, void* 
     return fail(c, MCX_E_RANGE, "static scratch of %zu bytes holds no bank of %u records with a table of 2^20 slots",
                 size_t(MCX_STATIC_SCRATCH_BYTES), c->cap);
   c->d_queues = DevBuf{base, qb, true};
-  c->d_hkeys = DevBuf{base + qb, slots * sizeof(uint64_t), true};
-  c->d_hvals = DevBuf{base + qb + slots * sizeof(uint64_t), slots * sizeof(double), true};
+  c->d_htab = DevBuf{base + qb, slots * kSlotBytes, true};
   c->hslots = slots;
   c->queue_cap_built = c->cap;
-  // the array keeps the last call's contents: an empty table to start
-  e = fill_u64(c->d_hkeys.p, slots, kEmptyKey, s);
-  if (e == hipSuccess) e = fill_u64(c->d_hvals.p, slots, 0ull, s);
+  // the array keeps the last call's contents: an empty table to start (a
+  // kernel, not a memset: a caller may capture the work of a static run)
+  e = launch_clear_table(static_cast<TSlot*>(c->d_htab.p), slots, s);
   if (e != hipSuccess) return hip_fail(c, e, "clear static tally table");
   uint64_t completed = 0;
   // no graph: instantiating one allocates
@@ -1525,7 +1504,7 @@ int mcx_set_workspace(mcx_ctx* c, void* dev, size_t bytes) {
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "synchronize before the workspace change");
   // the loop and statistics counters are the context's own and stay
-  for (DevBuf* b : {&c->d_queues, &c->d_hkeys, &c->d_hvals}) dfree(*b);
+  for (DevBuf* b : {&c->d_queues, &c->d_htab}) dfree(*b);
   c->queue_cap_built = 0;
   c->ws = dev;
   c->ws_bytes = dev ? bytes : 0;
@@ -1533,7 +1512,7 @@ int mcx_set_workspace(mcx_ctx* c, void* dev, size_t bytes) {
   c->hslots = kTableSlots;
   int rc = dev ? carve_workspace(c) : MCX_OK;
   if (rc) {  // too small: back to library-owned memory
-    for (DevBuf* b : {&c->d_queues, &c->d_hkeys, &c->d_hvals}) dfree(*b);
+    for (DevBuf* b : {&c->d_queues, &c->d_htab}) dfree(*b);
     c->ws = nullptr;
     c->ws_bytes = 0;
   }

@@ -440,11 +440,11 @@ template <typename T>
 __device__ __forceinline__ void tally_probe(const KArgs<T>& a, uint64_t key, double q, uint64_t slot, uint64_t k) {
   for (int probe = 0; probe < 4096; ++probe) {
     if (k == kEmptyKey || k == key) {
-      unsafeAtomicAdd(&a.hvals[slot], q);
+      unsafeAtomicAdd(&a.htab[slot].q, q);
       return;
     }
     slot = (slot + 1) & a.hmask;
-    k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey, (unsigned long long)key);
+    k = atomicCAS((unsigned long long*)&a.htab[slot].key, (unsigned long long)kEmptyKey, (unsigned long long)key);
   }
   atomicOr(&a.cnt->overflow, uint32_t(OVF_TALLY));
 }
@@ -459,7 +459,7 @@ __device__ __forceinline__ void tally_insert(const KArgs<T>& a, uint64_t key, do
   ls.inserts++;
   unsafeAtomicAdd(&a.sum_q[uint32_t(key & 0xFFFFFFFFull)], q);
   const uint64_t slot = tally_slot(a, key);
-  const uint64_t k = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
+  const uint64_t k = atomicCAS((unsigned long long*)&a.htab[slot].key, (unsigned long long)kEmptyKey,
                                (unsigned long long)key);
   tally_probe(a, key, q, slot, k);
 }
@@ -521,7 +521,7 @@ __device__ __forceinline__ void dep_flush_pending(const KArgs<T>& a, DepAcc& acc
   unsafeAtomicAdd(&a.sum_q[uint32_t(acc.pkey & 0xFFFFFFFFull)], acc.pq);
   const uint64_t slot = tally_slot(a, acc.pkey);
   acc.fslot = uint32_t(slot);
-  acc.fres = atomicCAS((unsigned long long*)&a.hkeys[slot], (unsigned long long)kEmptyKey,
+  acc.fres = atomicCAS((unsigned long long*)&a.htab[slot].key, (unsigned long long)kEmptyKey,
                        (unsigned long long)acc.pkey);
 }
 

@@ -1366,15 +1366,16 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
 // slots are cleared for the next chunk
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
-                        int test_mode, double* hist_led, uint64_t n_run) {
+__global__ void k_flush(TSlot* tab, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt, int test_mode,
+                        double* hist_led, uint64_t n_run) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   uint32_t occ = 0;
   double dep = 0.0;  // deposited energy, for the run statistics
   for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
-    const uint64_t k = keys[s];
+    const TSlot t = tab[s];
+    const uint64_t k = t.key;
     if (k == kEmptyKey) continue;
-    const double q = vals[s];
+    const double q = t.q;
     dep += q;
     const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
     unsafeAtomicAdd(&sum_q2[v], q * q);  // Sum q was formed at insertion
@@ -1382,14 +1383,20 @@ __global__ void k_flush(uint64_t* keys, double* vals, uint64_t nslot, double* su
       const uint64_t h = (k >> 32) - cnt->run_first;
       if (h < n_run) unsafeAtomicAdd(&hist_led[3 * h], q);
     }
-    keys[s] = kEmptyKey;
-    vals[s] = 0.0;
+    tab[s] = TSlot{kEmptyKey, 0.0};
     ++occ;
   }
   occ = wave_sum(occ);
   dep = wave_sum(dep);
   if (__lane_id() == 0 && occ) atomicAdd((unsigned long long*)&cnt->occupied, (unsigned long long)occ);
   if (__lane_id() == 0 && dep != 0.0) unsafeAtomicAdd(&cnt->e_dep, dep);
+}
+
+// an empty table: every key empty, every score 0
+template <typename T>
+__global__ void k_clear_table(TSlot* tab, uint64_t nslot) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) tab[s] = TSlot{kEmptyKey, 0.0};
 }
 
 // density gradient helpers: loss weights per MeV, mean of Q_h, final terms
