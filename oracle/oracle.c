@@ -24,7 +24,11 @@
  *     matches the soft transport cross section, hard events by the delta
  *     method with a majorant over the step's energy interval (the log-log
  *     chord of the node sums of the hard cross sections, an upper bound of
- *     their sum); every voxel face ends a step;
+ *     their sum); every voxel face ends a step, and the soft loss is charged
+ *     where the step ends, over the geometric length travelled (a face
+ *     before or after the hinge, or the whole step), so that the energy
+ *     along a track is the CSDA energy of the path travelled whatever the
+ *     voxel size;
  *  R5 positrons annihilate at rest only;
  *  R6 per-particle counter-based random streams (Philox4x32-10, Salmon et
  *     al. SC'11) keyed by (seed, history) with counter (draw pair, uid), so
@@ -602,6 +606,9 @@ typedef struct {
   uint32_t nchild;
   uint64_t hash;
   double w;  /* statistical weight (R11) */
+  /* e+-: the majorant optical depth left before the next hard or delta event
+   * (R4); 0 when none is pending (a new particle, or right after an event) */
+  double clk;
 } part;
 
 typedef struct {
@@ -747,8 +754,8 @@ double orc_soft_score(double a, double mu, double mbar, double len, double t1s) 
 }
 
 /* Pathwise term of the soft energy loss.  A step of the current e+- particle
- * in voxel v loses E - E1 over the mass path rho l (l geometric: the face
- * distance, or the whole step at the hinge).  At fixed l, d(E - E1)/d rho =
+ * in voxel v loses E - E1 over the mass path rho l (l geometric: the length
+ * travelled to the face that ends the step, or the whole step).  At fixed l, d(E - E1)/d rho =
  * l S(E1) (the range is R(E1) = R(E) - rho l, R' = 1/S), and E1 = E - loss
  * moves every later step of the particle: dE1/dE = S(E1)/S(E) = r.  The
  * derivative of the particle's weighted deposits from the start of step k
@@ -1281,8 +1288,10 @@ static void electron_track(ctx* c, part* p) {
      * end of the step's energy interval bounds it over the step */
     int annih = ti == 1 && (t->flags & ORC_ANNIH_FLIGHT);
     if (annih) smaj += orc_sigma_annih(tb, elo);
-    double u1 = draw(&p->rng);
-    double tau_h = smaj > 0.0 ? -log(u1) / smaj : INF_D;
+    /* the hard-event clock: a pending free path runs on across steps, so
+     * where faces cut a track does not change where its hard events fall */
+    if (!(p->clk > 0.0)) p->clk = -log(draw(&p->rng));
+    double tau_h = smaj > 0.0 ? p->clk / smaj : INF_D;
     int capped;
     double len;
     if (cap) {
@@ -1293,77 +1302,71 @@ static void electron_track(ctx* c, part* p) {
       double tau_s = capped ? tau_max : tau_h;
       len = tau_s / rho;
     }
-    /* A25 term A: the geometric free path of the majorant process has the
-     * density rho smaj exp(-rho smaj s) below the cap and the tail
-     * exp(-rho smaj len) at it: d ln p / d rho = -smaj len (+ 1/rho below) */
-    if (c->w) score(c, v, -smaj * len + (capped ? 0.0 : 1.0 / rho));
     double th = draw(&p->rng) * len;
     int a;
     double db = face(c, p, &a);
-    if (db <= th) {
-      /* the face comes before the hinge: soft loss over db, cross, new step */
-      double e1 = orc_range_inverse(tb, ti, r0 - rho * db);
-      if (!(e1 < e)) e1 = e;
-      if (t->flags & ORC_STRAGGLING) {
-        e1 = e - straggle(&p->rng, e - e1, rho * db * orc_soft_omega2(tb, ti, e));
-        if (!(e1 > 0.0)) e1 = 0.0;
-      }
-      deposit(c, p, e - e1);
-      c->led[ORC_LED_PATH] += rho * db;
-      if (c->w) {
-        double s1 = interp(tb, tb->el[ti][CH_S], 0.0, e1);
-        elog_push(c, v, db * s1, s1 / ss, p->w * c->w[v]);
-      }
-      p->e = e1;
+    /* Reading A6': the step ends at the first face on its path or at its full
+     * length; the hinge, if reached, deflects the particle by the soft
+     * angular law of the whole step.  The soft loss is charged where the step
+     * ends, over the geometric length s actually travelled: the CSDA energy
+     * after s is R^-1(R(E) - rho s). */
+    int face_end = db <= th;
+    double s = db, after = db;
+    if (!face_end) {
+      move(p, th);
+      double t1s = interp(tb, tb->el[ti][CH_T1S], 0.0, e);
+      double mbar = 0.5 * (1.0 - exp(-rho * len * t1s));
+      double aa = orc_soft_a(mbar);
+      double u3 = draw(&p->rng);
+      double mu = aa * u3 / (1.0 + aa - u3);
+      /* A25 term C */
+      if (c->w) score(c, v, orc_soft_score(aa, mu, mbar, len, t1s));
+      double phi = 2.0 * PI * draw(&p->rng);
+      rotate(p->d, 1.0 - 2.0 * mu, phi);
+      double rem = len - th;
+      double db2 = face(c, p, &a);
+      face_end = db2 <= rem;
+      after = face_end ? db2 : rem;
+      s = face_end ? th + db2 : len;
+    }
+    /* the clock runs down by the majorant optical depth of the path; a step
+     * that ends uncapped at its full length ends at an event (below) */
+    int event_end = !face_end && !capped;
+    p->clk = event_end ? 0.0 : p->clk - smaj * (rho * s);
+    /* A25 term A: the candidate events of the majorant process along the
+     * path form a Poisson process of rate rho smaj per unit length:
+     * d ln L / d rho = -smaj s over each path segment, +1/rho at an event */
+    if (c->w) score(c, v, -smaj * s + (event_end ? 1.0 / rho : 0.0));
+    double e1 = orc_range_inverse(tb, ti, r0 - rho * s);
+    if (!(e1 < e)) e1 = e;
+    if (t->flags & ORC_STRAGGLING) {
+      e1 = e - straggle(&p->rng, e - e1, rho * s * orc_soft_omega2(tb, ti, e));
+      if (!(e1 > 0.0)) e1 = 0.0;
+    }
+    deposit(c, p, e - e1);
+    c->led[ORC_LED_PATH] += rho * s;
+    if (c->w) {
+      double s1 = interp(tb, tb->el[ti][CH_S], 0.0, e1);
+      elog_push(c, v, s * s1, s1 / ss, p->w * c->w[v]);
+    }
+    p->e = e1;
+    if (face_end) {
+      /* cross; an energy at or below Eabs is absorbed at the next step's
+       * start, in the voxel entered */
       event(c, p, EV_CROSS, v);
-      if (cross(c, p, db, a)) {
+      if (cross(c, p, after, a)) {
         if (c->w) elog_close(c, 0.0);
         e_escape(c, p, v);
         return;
       }
       continue;
     }
-    /* hinge: the soft loss of the whole step is charged here */
-    move(p, th);
-    double e1 = orc_range_inverse(tb, ti, r0 - rho * len);
-    if (!(e1 < e)) e1 = e;
-    if (t->flags & ORC_STRAGGLING) {
-      e1 = e - straggle(&p->rng, e - e1, rho * len * orc_soft_omega2(tb, ti, e));
-      if (!(e1 > 0.0)) e1 = 0.0;
-    }
-    deposit(c, p, e - e1);
-    c->led[ORC_LED_PATH] += rho * len;
-    if (c->w) {
-      double s1 = interp(tb, tb->el[ti][CH_S], 0.0, e1);
-      elog_push(c, v, len * s1, s1 / ss, p->w * c->w[v]);
-    }
-    p->e = e1;
+    move(p, after);
     if (!(e1 > eabs)) {
       if (c->w) elog_close(c, p->w * c->w[v]);
       e_absorb(c, p);
       return;
     }
-    double t1s = interp(tb, tb->el[ti][CH_T1S], 0.0, e);
-    double mbar = 0.5 * (1.0 - exp(-rho * len * t1s));
-    double aa = orc_soft_a(mbar);
-    double u3 = draw(&p->rng);
-    double mu = aa * u3 / (1.0 + aa - u3);
-    /* A25 term C */
-    if (c->w) score(c, v, orc_soft_score(aa, mu, mbar, len, t1s));
-    double phi = 2.0 * PI * draw(&p->rng);
-    rotate(p->d, 1.0 - 2.0 * mu, phi);
-    double rem = len - th;
-    double db2 = face(c, p, &a);
-    if (db2 <= rem) {
-      event(c, p, EV_CROSS, v);
-      if (cross(c, p, db2, a)) {
-        if (c->w) elog_close(c, 0.0);
-        e_escape(c, p, v);
-        return;
-      }
-      continue;
-    }
-    move(p, rem);
     if (capped) {
       event(c, p, EV_STEP, v);
       continue;

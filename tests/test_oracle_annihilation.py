@@ -92,23 +92,24 @@ def test_annihilation_photon_fraction_and_kinematics(e):
     assert np.allclose(pb2, kb ** 2, rtol=1e-9)
 
 
-def test_in_flight_fraction_of_slowing_down_positrons():
+@pytest.mark.parametrize("nvox", [1, 8])
+def test_in_flight_fraction_of_slowing_down_positrons(nvox):
     """Hard channels off: the positron loses energy continuously (CSDA) and
     annihilates in flight at the rate Sigma_an(E) per g/cm^2 along its path,
     so it does so before reaching Eabs with probability
     1 - exp(-int_Eabs^E0 Sigma_an(E) / S(E) dE).  Photons are absorbed where
     they are made, so the only charged particles are the positrons: in-flight
-    annihilations = annihilations - absorptions.  One 40 cm voxel: a face
-    that ends a step after its hinge would cut the path short of the soft
-    loss already charged for the whole step (every face interrupts a step),
-    which with 5 cm voxels around a corner start lowers the in-flight share
-    by 3%."""
+    annihilations = annihilations - absorptions.  One 40 cm voxel, and 5 cm
+    voxels around a corner start, where faces interrupt many steps: the soft
+    loss is charged over the length travelled, so the share is the same
+    (charging a whole step's loss at a hinge that a face then cut short
+    lowered it by 3% there)."""
     e0, eabs = 5.0, 0.1
     hard_off = O.NO_HARD_ELASTIC | O.NO_HARD_INELASTIC | O.NO_HARD_BREMS
     t = W.transport(100.0, 250, flags=hard_off | O.ANNIH_FLIGHT, eabs=(1e9, eabs, eabs))
     tb = O.Tables(W.WATER, t)
     n = 40_000
-    ph = W.water_cube(1, 40.0)
+    ph = W.water_cube(nvox, 40.0)
     r = O.run(tb, ph, [W.pencil(2, e0, (20.0, 20.0, 20.0), n)], 5, 0, n, ledger=True)
     st = r.stats.as_dict()
     assert st["escaped"] == 0

@@ -10,9 +10,10 @@ the deterministic CSDA value).
   against scipy's truncated normal and uniform laws, the point mass of the
   two-mode law by a binomial test, and the first two moments;
 - the whole step: 10 MeV electrons through one thin slab voxel with the hard
-  channels off lose exactly one straggled soft loss, charged over the face
-  distance (face before the hinge) or over the whole step (hinge first), so
-  the mean and second moment of the deposited energy follow from the range
+  channels off lose exactly one straggled soft loss, charged over the length
+  travelled to the far face (the face distance when the face comes before
+  the hinge, a little more when the hinge deflects the track first), so the
+  mean and second moment of the deposited energy follow from the range
   tables and the hinge law;
 - per-history energy conservation with straggling on.
 """
@@ -122,13 +123,16 @@ def test_straggling_two_mode_regime():
 @pytest.mark.parametrize("straggle", [False, True])
 def test_thin_slab_loss_is_one_straggled_step(straggle):
     """10 MeV electrons enter a 1 mm water slab (one voxel) with the hard
-    channels off: the step is capped at len = C2 E / S_s, its hinge lies at a
-    uniform fraction u of it, and (but for the rare track that the hinge turns
-    back) the electron leaves after one soft loss: over the face distance d if
-    u >= d/len, else over the whole step (charged at the hinge).  The mass
-    path the history charged (d or len) tells the two apart.  Without
-    straggling the deposited energy is the CSDA loss over that path; with
-    straggling a loss of that mean and of variance path * Omega^2(E0)."""
+    channels off: the step is capped at len = C2 E / S_s > d, its hinge lies at
+    a uniform fraction u of it, and (but for the rare track that the hinge
+    turns back) the electron leaves after one step, charged over the length
+    it travelled to the far face: exactly d when u >= d/len (the face comes
+    first), else the distance to the hinge plus the deflected path from it to
+    the face, a little more than d.  The mass path the history charged tells
+    the two apart.  Without straggling the deposited energy is the CSDA loss
+    over that path; with straggling a loss of that mean and of variance
+    path * Omega^2(E0): the face-first set by its exact two-mode law, the
+    hinge-first set (a different path per history) by its first two moments."""
     e0, d = 10.0, 0.1
     flags = O.NO_HARD_ELASTIC | O.NO_HARD_INELASTIC | O.NO_HARD_BREMS | (O.STRAGGLING if straggle else 0)
     t = W.transport(100.0, 250, flags=flags)
@@ -143,30 +147,37 @@ def test_thin_slab_loss_is_one_straggled_step(straggle):
     length = 0.05 * e0 / ss
     assert length > d
     r0 = tb.eval(O.ech(0, 1), e0)
-    face = np.isclose(path, d, rtol=1e-12)
-    step = np.isclose(path, length, rtol=1e-12)
-    assert (face | step).mean() > 0.995
-    p_face = 1.0 - d / length
-    nf = face.sum() + step.sum()
-    assert abs(face.sum() / nf - p_face) < 5 * math.sqrt(p_face * (1 - p_face) / nf)
     om2 = tb.soft_omega2(0, e0)
-    for sel, ell in ((face, d), (step, length)):
-        m = e0 - tb.range_inverse(0, r0 - ell)
-        x = dep[sel]
-        if not straggle:
-            assert np.allclose(x, m, rtol=1e-12)
-            continue
-        # the two-mode regime: its law has exactly the target mean and
-        # variance
-        v = ell * om2
-        assert m * m < 3 * v
-        k = x.size
-        assert abs(x.mean() - m) < 5 * x.std() / math.sqrt(k)
-        assert abs((x ** 2).mean() - (v + m * m)) < 5 * (x ** 2).std() / math.sqrt(k)
-        s2 = v + m * m
-        a = 1 - 4 * m * m / (3 * s2)
-        assert abs((x == 0).mean() - a) < 5 * math.sqrt(a * (1 - a) / k)
-        assert stats.kstest(x[x > 0], stats.uniform(0.0, 1.5 * s2 / m).cdf).pvalue > 1e-3
+    face = np.isclose(path, d, rtol=1e-12)
+    hinge = (path > d * (1 + 1e-12)) & (path < 1.2 * d) & (r.ledger[:, O.LED_ESC] > 0)
+    assert (face | hinge).mean() > 0.995
+    p_face = 1.0 - d / length
+    nf = face.sum() + hinge.sum()
+    assert abs(face.sum() / nf - p_face) < 5 * math.sqrt(p_face * (1 - p_face) / nf)
+    # the CSDA loss over each history's charged path
+    m_path = e0 - np.array([tb.range_inverse(0, r0 - x) for x in path])
+    if not straggle:
+        assert np.allclose(dep[face | hinge], m_path[face | hinge], rtol=1e-12)
+        return
+    # face first: one path d, the two-mode regime, whose law has exactly the
+    # target mean and variance
+    m, v, x = m_path[face][0], d * om2, dep[face]
+    assert m * m < 3 * v
+    k = x.size
+    assert abs(x.mean() - m) < 5 * x.std() / math.sqrt(k)
+    assert abs((x ** 2).mean() - (v + m * m)) < 5 * (x ** 2).std() / math.sqrt(k)
+    s2 = v + m * m
+    a = 1 - 4 * m * m / (3 * s2)
+    assert abs((x == 0).mean() - a) < 5 * math.sqrt(a * (1 - a) / k)
+    assert stats.kstest(x[x > 0], stats.uniform(0.0, 1.5 * s2 / m).cdf).pvalue > 1e-3
+    # hinge first: per history the loss has mean m(path) and second moment
+    # path * Omega^2 + m(path)^2
+    x, m, v = dep[hinge], m_path[hinge], path[hinge] * om2
+    k = x.size
+    assert k > 500
+    r1, r2 = x - m, x ** 2 - (v + m * m)
+    assert abs(r1.mean()) < 5 * r1.std() / math.sqrt(k)
+    assert abs(r2.mean()) < 5 * r2.std() / math.sqrt(k)
 
 
 def test_energy_conservation_with_straggling():

@@ -113,6 +113,56 @@ def test_voxelisation_invariance_photons():
     assert a.stats.compton == b.stats.compton and a.stats.flights == b.stats.flights
 
 
+def test_voxelisation_invariance_electrons():
+    """Depth voxels of 1 mm and of 2 cm must give the same depth dose of a
+    10 MeV electron pencil: the soft loss of a Class II step is charged over
+    the geometric length travelled up to the face or the step end that ends
+    it, so the energy along a track does not depend on where faces interrupt
+    steps.  (Charging the whole step's loss at a hinge that a later face cuts
+    short moved 14% of the first 2 cm's dose and 76% of the third's.)
+    Eight batches of 500 histories per geometry; z-test per 2 cm bin."""
+    tb = O.Tables(W.WATER, W.transport(100.0, 250))
+    n, nb = 500, 8
+    src = [W.pencil(1, 10.0, (10.0, 10.0, 0.0), n * nb)]
+    means, ses = [], []
+    for dz, nz in ((0.1, 100), (2.0, 5)):
+        ph = W.slab_phantom(nz, dz, np.ones(nz), 1, 20.0)
+        q = np.array([O.run(tb, ph, src, 3, b * n, n).sum_q.reshape(5, -1).sum(axis=1) / n for b in range(nb)])
+        means.append(q.mean(axis=0))
+        ses.append(q.std(axis=0, ddof=1) / math.sqrt(nb))
+    keep = means[1] > 0.01 * means[1].sum()
+    z = (means[0] - means[1])[keep] / np.hypot(ses[0], ses[1])[keep]
+    assert keep.sum() >= 3
+    assert np.all(np.abs(z) < 4.0), z
+
+
+def test_voxelisation_invariance_electrons_on_a_voxel_corner():
+    """A 20 MeV electron pencil along a line where four columns of 1 mm voxels
+    meet (the pencil of the electron workload sits on such a line) must give
+    the depth dose of the same beam in 1 mm depth layers of one 2 cm column:
+    the first hinge deflection sends the primary across a face at zero
+    distance, so faces cut its steps right after their hinges.  The pending
+    free path of the majorant process runs on across those cuts; redrawing
+    it at each cut (a cut tied to the hinge, a fixed fraction of the sampled
+    free path, is not a stopping time of that process) postponed the hard
+    collisions and lowered the first layer's dose by 6%.  Sixteen batches of
+    400 histories, the same histories in both geometries; z-test of the
+    paired batch differences per 1 mm layer over the first 5 mm and per 5 mm
+    over the 2 cm."""
+    tb = O.Tables(W.WATER, W.transport(100.0, 250))
+    n, nb = 400, 16
+    src = [W.pencil(1, 20.0, (1.0, 1.0, 0.0), n * nb)]
+    out = []
+    for ph in (W.water_cube(20, 2.0), W.slab_phantom(20, 0.1, np.ones(20), 1, 2.0)):
+        out.append(np.array([O.run(tb, ph, src, 4, b * n, n).sum_q.reshape(20, -1).sum(axis=1) / n
+                             for b in range(nb)]))
+    for w, m in ((1, 5), (5, 4)):
+        a, b = (x.reshape(nb, -1, w).sum(axis=2)[:, :m] for x in out)
+        dd = a - b
+        z = dd.mean(0) / (dd.std(0, ddof=1) / math.sqrt(nb))
+        assert np.all(np.abs(z) < 4.0), (w, z)
+
+
 def test_estimator_per_history_grouping_single_voxel():
     """With one voxel, the per-history score is the history's total deposit:
     Sum q and Sum q^2 must equal the sums over the independent per-history
