@@ -25,6 +25,7 @@ NO_COMPTON, NO_PHOTO, NO_RAYLEIGH, NO_PAIR = 1, 2, 4, 8
 NO_HARD_ELASTIC, NO_HARD_INELASTIC, NO_HARD_BREMS = 16, 32, 64
 STRAGGLING = 128
 ANNIH_FLIGHT = 256
+GRAD_DEFLECTION_ENERGY = 512
 
 # orc_eval channels
 MU_COMPTON, MU_PHOTO, MU_RAYLEIGH, MU_PAIR = 0, 1, 2, 3

@@ -640,7 +640,7 @@ typedef struct {
   double* p_acc;
   /* the current e+- particle's steps, for the backward sweep of its energy
    * adjoint when it ends (gradient mode) */
-  struct elog_rec { int64_t v; double coef, r, d; }* elog;
+  struct elog_rec { int64_t v; double coef, r, d, se; }* elog;
   int n_elog, cap_elog;
 } ctx;
 
@@ -766,8 +766,18 @@ double orc_soft_score(double a, double mu, double mbar, double len, double t1s) 
  * escapes or annihilates in flight.  Each step adds l S(E1) (d_k - lam_{k+1})
  * to voxel v: the loss it deposits there minus what the particle then lacks
  * downstream.  The steps are logged and swept backward at the particle's
- * end. */
-static void elog_push(ctx* c, int64_t v, double coef, double r, double d) {
+ * end.
+ *
+ * Term E (ORC_GRAD_DEFLECTION_ENERGY): the soft deflection drawn at the hinge
+ * of step k has a law that depends on the particle's energy E_k there
+ * (through the soft transport coefficient t1s(E_k)), and E_k moves with the
+ * density of every earlier step: dE_k/d rho_j = -l_j S(E1_j) times the chain
+ * factors r of the steps between.  Its likelihood-ratio score is
+ * se_k = d ln p(mu_k)/dE_k = (term C of the step) rho (d ln t1s/dE)(E_k), and
+ * psi_j = se_{j+1} + r_{j+1} psi_{j+1} (0 after the last step) collects the
+ * later hinges; step j adds -l_j S(E1_j) psi_j to the history's score of its
+ * voxel. */
+static void elog_push(ctx* c, int64_t v, double coef, double r, double d, double se) {
   if (c->n_elog == c->cap_elog) {
     c->cap_elog = c->cap_elog ? 2 * c->cap_elog : 256;
     c->elog = (struct elog_rec*)realloc(c->elog, sizeof(*c->elog) * (size_t)c->cap_elog);
@@ -776,15 +786,18 @@ static void elog_push(ctx* c, int64_t v, double coef, double r, double d) {
   c->elog[c->n_elog].coef = coef;
   c->elog[c->n_elog].r = r;
   c->elog[c->n_elog].d = d;
+  c->elog[c->n_elog].se = se;
   c->n_elog++;
 }
 
 static void elog_close(ctx* c, double lam_end) {
-  double lam = lam_end;
+  double lam = lam_end, psi = 0.0;
   for (int k = c->n_elog - 1; k >= 0; --k) {
     const struct elog_rec* e = &c->elog[k];
     c->p_acc[e->v] += e->coef * (e->d - lam);
+    if (psi != 0.0) score(c, e->v, -e->coef * psi);
     lam = e->d * (1.0 - e->r) + e->r * lam;
+    psi = e->se + e->r * psi;
   }
   c->n_elog = 0;
 }
@@ -1311,7 +1324,7 @@ static void electron_track(ctx* c, part* p) {
      * ends, over the geometric length s actually travelled: the CSDA energy
      * after s is R^-1(R(E) - rho s). */
     int face_end = db <= th;
-    double s = db, after = db;
+    double s = db, after = db, hinge_se = 0.0;
     if (!face_end) {
       move(p, th);
       double t1s = interp(tb, tb->el[ti][CH_T1S], 0.0, e);
@@ -1319,8 +1332,18 @@ static void electron_track(ctx* c, part* p) {
       double aa = orc_soft_a(mbar);
       double u3 = draw(&p->rng);
       double mu = aa * u3 / (1.0 + aa - u3);
-      /* A25 term C */
-      if (c->w) score(c, v, orc_soft_score(aa, mu, mbar, len, t1s));
+      /* A25 term C, and the same law's score with respect to the energy
+       * (term E): <mu> moves with E through t1s, a power law between nodes */
+      if (c->w) {
+        double sc = orc_soft_score(aa, mu, mbar, len, t1s);
+        score(c, v, sc);
+        if (t->flags & ORC_GRAD_DEFLECTION_ENERGY) {
+          double f;
+          int gi = grid_pos(tb, e, &f);
+          const double* yt = tb->el[ti][CH_T1S];
+          if (yt[gi] > 0.0 && yt[gi + 1] > 0.0) hinge_se = sc * rho * log(yt[gi + 1] / yt[gi]) / (tb->dl * e);
+        }
+      }
       double phi = 2.0 * PI * draw(&p->rng);
       rotate(p->d, 1.0 - 2.0 * mu, phi);
       double rem = len - th;
@@ -1347,7 +1370,7 @@ static void electron_track(ctx* c, part* p) {
     c->led[ORC_LED_PATH] += rho * s;
     if (c->w) {
       double s1 = interp(tb, tb->el[ti][CH_S], 0.0, e1);
-      elog_push(c, v, s * s1, s1 / ss, p->w * c->w[v]);
+      elog_push(c, v, s * s1, s1 / ss, p->w * c->w[v], hinge_se);
     }
     p->e = e1;
     if (face_end) {

@@ -52,7 +52,11 @@ enum {
   ORC_NO_HARD_INELASTIC = 1u << 5,
   ORC_NO_HARD_BREMS = 1u << 6,
   ORC_STRAGGLING = 1u << 7,
-  ORC_ANNIH_FLIGHT = 1u << 8  /* two-photon annihilation of positrons in flight */
+  ORC_ANNIH_FLIGHT = 1u << 8, /* two-photon annihilation of positrons in flight */
+  /* gradient only (orc_run_gradient): also score each soft deflection's
+   * dependence on the particle's energy, chained to the densities of the
+   * steps before it (term E) */
+  ORC_GRAD_DEFLECTION_ENERGY = 1u << 9
 };
 
 typedef struct {
@@ -205,17 +209,23 @@ int orc_run(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
  *           variables whose laws depend on rho_j:
  *           photon free flights: -mu l_j per voxel crossed, +1/rho_k where the
  *           flight ends in an interaction (term A, photons);
- *           e+- steps in voxel j: the geometric free path of the hard-event
- *           majorant process, -smaj len, +1/rho_j when it ends below the step
- *           cap (term A, e+-), and the soft deflection of the hinge (term C);
+ *           e+- steps in voxel j: the candidate events of the hard-event
+ *           majorant process along the path, -smaj s over the step's length
+ *           s, +1/rho_j where the step ends at an event (term A, e+-), and the
+ *           soft deflection of the hinge (term C); with
+ *           ORC_GRAD_DEFLECTION_ENERGY also -s S(E1) psi for each step (term
+ *           E), psi the sum over the particle's later hinges of their
+ *           deflection's d ln p / dE times the CSDA chain dE/dE1 back to
+ *           this step's end;
  *   P_hj  = pathwise soft-loss terms of the e+- steps in voxel j at fixed
  *           geometric step lengths: l S(E1) (weight w_j - lam), lam the
  *           particle's CSDA energy adjoint after the step (term D);
  * Accumulated: A_j += Q_h S_hj, B_j += S_hj, P_j += P_hj, *sum_q_h += Q_h.
  * The gradient is (A_j - Qbar B_j + P_j)/N - (dL/dD_j) D_j / rho_j (term B),
  * Qbar = sum_q_h / N.  Exact when electrons deposit where they are created;
- * with Class II transport the step cap's geometric length, the majorant and
- * the energy dependence of the later sampling laws are held fixed. */
+ * with Class II transport the step cap's geometric length and the majorant
+ * are held fixed, and so is the energy dependence of the later sampling laws
+ * (hard-event rates and laws, and, without term E, the soft deflection). */
 int orc_run_gradient(const orc_tables* tb, const orc_transport* t, const orc_phantom* ph,
                      const orc_source* src, int n_src, uint32_t seed, uint64_t first,
                      uint64_t n, const double* w, double* a_acc, double* b_acc,
