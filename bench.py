@@ -168,6 +168,11 @@ def target_detector_efficiency(mcx, W, sync, args, n: int = 1_000_000) -> dict:
                 histories=n, analog=res["analog"], forced=res["forced"], efficiency_gain=float(eff))
 
 
+def progress(msg: str) -> None:
+    """One line per finished leg on stderr (the JSON line stays on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def run_steps(sim, n, seeds, sync, doses=None):
     """One timed run per seed (tallies reset before each); with `doses`, each
     step's dose is appended to it after the timed region."""
@@ -210,6 +215,7 @@ def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
     d, _ = sim.dose()
     sync()
     t1 = time.perf_counter()
+    esteps = sim.stats()["esteps"]
     target = smooth_target(d)
     g = sim.dose_backward(2.0 * (d - target))
     sync()
@@ -217,7 +223,7 @@ def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
     sim.close()
     return dict(workload="hetero_broad_64: 6 MeV 10x10 field, 64^3 x 4 mm, FP64", histories=n,
                 forward_s=t1 - t0, backward_s=t2 - t1, fwd_bwd_s=t2 - t0, grad_abs_max=float(np.abs(g).max()),
-                target=target)
+                esteps_forward=esteps, target=target)
 
 
 def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: int = 10, n_vox: int = 16,
@@ -228,7 +234,9 @@ def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: i
     histories [0, n_batch)) gives one replay gradient and, for each voxel,
     (L(rho + h rho_j) - L(rho - h rho_j)) / (2 h rho_j) with the same seed
     and histories; L = sum_v (D_v - T_v)^2 with the target frozen.  Means and
-    standard errors over the batches."""
+    standard errors over the batches.  Both estimators of the replay are
+    taken from the same runs: the default one and the one with the soft
+    deflection's energy term (term E)."""
     wl = W.workload("hetero_broad_64", n_batch)
     if transport is not None:
         wl["transport"] = transport
@@ -249,14 +257,24 @@ def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: i
     pick = elig[np.random.Generator(np.random.PCG64(6)).choice(len(elig), size=n_vox, replace=False)]
     vox = [tuple(int(c) for c in v) for v in pick]
     est = np.zeros((batches, n_vox))
+    est_e = np.zeros((batches, n_vox))
     t0 = time.perf_counter()
+    t_e = 0.0
     for b in range(batches):
         sim.reset()
         sim.run(100 + b, 0, n_batch)
         d, _ = sim.dose()
+        sim.set_gradient(0)
         g = sim.dose_backward(2.0 * (d - target))
         est[b] = [g[v] for v in vox]
-    t_grad = time.perf_counter() - t0
+        sync()
+        t1 = time.perf_counter()
+        sim.set_gradient(mcx.GRAD_DEFLECTION_ENERGY)
+        g = sim.dose_backward(2.0 * (d - target))
+        est_e[b] = [g[v] for v in vox]
+        sync()
+        t_e += time.perf_counter() - t1
+    t_grad = time.perf_counter() - t0 - t_e
     fd = np.zeros((batches, n_vox))
     t0 = time.perf_counter()
     for k, v in enumerate(vox):
@@ -275,18 +293,24 @@ def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: i
             fd[b, k] = (vals[1] - vals[-1]) / (2.0 * h * ph["rho"][v])
         for sm in sims.values():
             sm.close()
+        progress(f"finite differences: voxel {k + 1} of {n_vox}")
     t_fd = time.perf_counter() - t0
     sim.close()
     sync()
-    m, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(batches)
     f, fse = fd.mean(0), fd.std(0, ddof=1) / np.sqrt(batches)
-    zz = (m - f) / np.sqrt(se ** 2 + fse ** 2)
 
-    return dict(voxels=vox, replay=m.tolist(), replay_se=se.tolist(), fd=f.tolist(), fd_se=fse.tolist(),
-                replay_batches=est.tolist(), fd_batches=fd.tolist(),
-                z=zz.tolist(), z_mean=float(zz.mean()), z_rms=float(np.sqrt((zz ** 2).mean())),
-                z_max=float(np.abs(zz).max()), chi2=float((zz ** 2).sum()), dof=n_vox,
-                h=h, batches=batches, histories_per_batch=n_batch, replay_s=t_grad, fd_s=t_fd)
+    def versus_fd(e):
+        m, se = e.mean(0), e.std(0, ddof=1) / np.sqrt(batches)
+        zz = (m - f) / np.sqrt(se ** 2 + fse ** 2)
+        return dict(replay=m.tolist(), replay_se=se.tolist(), replay_batches=e.tolist(), z=zz.tolist(),
+                    z_mean=float(zz.mean()), z_rms=float(np.sqrt((zz ** 2).mean())), z_max=float(np.abs(zz).max()),
+                    chi2=float((zz ** 2).sum()), median_rel_se=float(np.median(se / np.abs(m))))
+
+    out = dict(voxels=vox, fd=f.tolist(), fd_se=fse.tolist(), fd_batches=fd.tolist(), dof=n_vox,
+               h=h, batches=batches, histories_per_batch=n_batch, replay_s=t_grad, replay_term_e_s=t_e, fd_s=t_fd)
+    out.update(versus_fd(est))
+    out["with_deflection_energy_term"] = versus_fd(est_e)
+    return out
 
 
 def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
@@ -358,14 +382,16 @@ def host_cpu() -> str:
     return "unknown"
 
 
-def cpu_baseline(name: str, n_per_proc: int, procs: int, repeats: int = 3) -> dict:
+def cpu_baseline(name: str, n_per_proc: int, procs: int, repeats: int = 3, stride: int | None = None) -> dict:
     """The oracle on the host cores, sharded by history range over `procs`
     processes (independent histories, as the paper's multi-process runs): the
     rate is the histories over the slowest shard's time (setup excluded),
-    the median of `repeats` repetitions."""
+    the median of `repeats` repetitions.  Shard k starts at history
+    k * stride (default: contiguous shards)."""
     import concurrent.futures as cf
     import multiprocessing as mp
-    jobs = [(name, k * n_per_proc, n_per_proc) for k in range(procs)]
+    step = stride or n_per_proc
+    jobs = [(name, k * step, n_per_proc) for k in range(procs)]
     rates, singles, slow, work = [], [], [], []
     with cf.ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
         for _ in range(repeats):
@@ -377,9 +403,44 @@ def cpu_baseline(name: str, n_per_proc: int, procs: int, repeats: int = 3) -> di
     i = int(np.argsort(rates)[len(rates) // 2])
     return dict(value=rates[i], unit="histories/s", cores=procs, kind="oracle", host_cpu=host_cpu(),
                 host_logical_cpus=os.cpu_count(), single_core=float(np.median(singles)), repeats=repeats,
-                sample=f"histories [0, {procs * n_per_proc}) of the same workload in {procs} single-thread FP64 "
+                sample=(f"histories [0, {procs * n_per_proc})" if step == n_per_proc else
+                        f"{procs} ranges of {n_per_proc} histories spaced {step} apart") +
+                       f" of the same workload in {procs} single-thread FP64 "
                        f"oracle processes of {n_per_proc} histories each, median of {repeats} repetitions "
                        f"({slow[i]:.1f} s the slowest shard, {work[i]:.0f} s of CPU work)")
+
+
+def cpu_baseline_configs(procs: int) -> dict:
+    """The oracle on the other workloads, the same way: the 1 MeV photon
+    pencil in full (1e5 histories), and bounded samples of the 20 MeV
+    electron pencil, the 512 beamlets (ranges spread over all 5e7 history
+    ids, so beamlets enter by their history counts) and the 64^3 gradient
+    field."""
+    import workloads as W
+    out = {}
+    n_beam = sum(s["n_hist"] for s in W.beamlet_sources())
+    for name, n, stride in (("water_pencil_32", 100_000 // procs, None), ("electron_200", 600, None),
+                            ("beamlets_256", 3000, n_beam // procs), ("hetero_broad_64", 6000, None)):
+        r = cpu_baseline(name, n, procs, stride=stride)
+        out[name] = {k: r[k] for k in ("value", "single_core", "sample")}
+        progress(f"oracle on {name}: {r['value']:.4g} histories/s on {procs} processes")
+    return out
+
+
+def small_config_rates(mcx, W, sync, steps: int = 5) -> dict:
+    """GPU rates of the 1 MeV photon pencil (1e5 histories, 32^3): FP64 and
+    mixed, `steps` timed runs after one warm-up."""
+    wl = W.workload("water_pencil_32")
+    n = wl["sources"][0]["n_hist"]
+    out = {}
+    for key, prec in (("fp64", mcx.FP64), ("mixed", mcx.MIXED)):
+        sim = mcx.Simulator(prec, 0).setup(wl)
+        run_steps(sim, n, [500], sync)
+        t = run_steps(sim, n, list(range(1, steps + 1)), sync)
+        sim.close()
+        out[key] = dict(value=n * len(t) / sum(t), ms=1e3 * sum(t) / len(t))
+    out["workload"] = "water_pencil_32: 1 MeV photon pencil, 32^3 x 6.25 mm water, 1e5 histories"
+    return out
 
 
 def electron_comparison(mcx, W, sync, n: int = 1_000_000, batches: int = 4) -> dict:
@@ -418,7 +479,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hist", type=int, default=10_000_000, help="histories per step")
     ap.add_argument("--cpu-sample", type=int, default=6_000, help="oracle histories per host process")
+    # a GPU machine's share of host cores is 16, whatever os.cpu_count() reports there
     ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes (host cores used)")
+    ap.add_argument("--no-cpu-configs", action="store_true", help="time the oracle on the benchmark workload only")
     ap.add_argument("--no-electron", action="store_true", help="skip the 20 MeV electron workload")
     ap.add_argument("--straggling", action="store_true",
                     help="also time the mixed step with soft energy-loss straggling on")
@@ -480,6 +543,7 @@ def main():
     st = mix.stats()
     d_mix, s_mix = mix.dose()
     mix.close()
+    progress(f"mixed: {len(t_mix)} steps, {n * len(t_mix) / sum(t_mix):.4g} histories/s")
 
     result_64 = None
     if not args.no_fp64:
@@ -489,12 +553,15 @@ def main():
         doses_64 = []
         t_64 = run_steps(f64, n, seeds, sync, doses_64)
         d_64, _ = f64.dose()
+        st_64 = f64.stats()
         f64.close()
-        result_64 = dict(value=n * len(t_64) / sum(t_64), ms_per_step=1e3 * sum(t_64) / len(t_64))
+        result_64 = dict(value=n * len(t_64) / sum(t_64), ms_per_step=1e3 * sum(t_64) / len(t_64),
+                         esteps_per_history=st_64["esteps"] / n)
         dev = high_dose_deviation(d_mix, d_64)
         # the timed steps as paired batches: systematic part and noise floor
         dev["paired_batches"] = paired_deviation(doses_mix, doses_64)
         del doses_mix, doses_64
+        progress(f"fp64: {len(t_64)} steps, {result_64['value']:.4g} histories/s")
 
     value = n * len(t_mix) / sum(t_mix)
     ms = {"k_source": st["ms_source"], "k_flight": st["ms_flight"], "k_knock": st["ms_knock"],
@@ -583,16 +650,24 @@ def main():
     if not args.no_gradient:
         out["gradient"] = gradient_timing(mcx, W, sync)
         target = out["gradient"].pop("target")
+        progress(f"gradient: forward + backward {out['gradient']['fwd_bwd_s']:.3f} s")
         if not args.no_fd_check:
             out["gradient"]["fd_check"] = gradient_fd_check(mcx, W, sync, target)
+            progress(f"gradient finite-difference check: z_rms {out['gradient']['fd_check']['z_rms']:.3f}")
     if args.beamlets:
         import tempfile
         with tempfile.TemporaryDirectory() as td:
             out["beamlets"] = beamlet_comparison(mcx, W, sync, args.beamlets, os.path.join(td, "autotune.jsonl"))
+        progress(f"beamlets: batched {out['beamlets']['batched_s']:.3f} s, one run each {out['beamlets']['per_beamlet_s']:.3f} s")
     if not args.no_electron:
         out["electron"] = electron_comparison(mcx, W, sync)
+        progress(f"electrons: mixed {out['electron']['mixed']['value']:.4g}, fp64 {out['electron']['fp64']['value']:.4g} histories/s")
+    out["water_pencil"] = small_config_rates(mcx, W, sync)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline("hetero_broad_128", args.cpu_sample, args.cpu_procs)
+        progress(f"oracle on hetero_broad_128: {out['cpu_baseline']['value']:.4g} histories/s")
+        if not args.no_cpu_configs:
+            out["cpu_baseline"]["other_workloads"] = cpu_baseline_configs(args.cpu_procs)
     print(json.dumps(out))
 
 

@@ -255,26 +255,42 @@ int mcx_set_test_mode(mcx_ctx* ctx, int on);
  * mcx_stats.next_history complete and tallied, when it honours mcx_cancel. */
 int mcx_run(mcx_ctx* ctx, uint64_t seed, uint64_t first_hist, uint64_t n_hist, void* stream);
 
-/* Gradient of a dose loss with respect to every voxel density.  dl_ddose
+/* Gradient of a dose loss with respect to every voxel density (the density
+ * derivative of the estimator of Sec. 4.3, Eq. (1)).  dl_ddose
  * holds dL/dD_v (D in eV/g per history, as from mcx_get_dose); dl_drho
  * receives dL/drho_v (nx*ny*nz doubles each; device arrays if on_device,
  * else host).  The histories of the last mcx_run are replayed twice from
  * their random-number counters (no tracks are stored): the first replay forms
  * each history's weighted score Q_h = sum_v w_v q_hv with
- * w_v = dL/dD_v * 1e6 / (rho_v V) and the local derivative of the soft energy
- * loss of electron/positron steps stopped by a voxel face; the second adds
- * (Q_h - mean Q) times the likelihood-ratio score of every photon free flight
- * (-mu l_j per traversed voxel with mu of the voxel's material, +1/rho at
- * the interaction).  The explicit
- * mass term -dL/dD_v D_v / rho_v completes the gradient.  Unbiased when
- * electrons are absorbed where they are created; with Class II transport the
- * downstream effect of density on electron tracks is not included.  Requires
+ * w_v = dL/dD_v * 1e6 / (rho_v V); the second adds (Q_h - mean Q) times the
+ * likelihood-ratio scores of the history's sampled variables (every photon
+ * free flight: -mu l_j per traversed voxel with mu of the voxel's material,
+ * +1/rho at the interaction; every e+- step: -smaj s of its hard-event
+ * majorant process over its length s, +1/rho where it ends at an event, and
+ * the score of its soft deflection), and the pathwise derivative of each
+ * e+- step's soft loss at fixed geometric length, s S(E1) times its voxel's
+ * weight minus the particle's CSDA energy adjoint after the step.  The
+ * explicit mass term -dL/dD_v D_v / rho_v completes the gradient.  Unbiased
+ * when electrons are absorbed where they are created; with Class II
+ * transport the step control (cap, hinge) is held at its geometric value and
+ * the energy dependence of later sampling laws is held fixed, except the soft
+ * deflection's under MCX_GRAD_DEFLECTION_ENERGY (mcx_set_gradient).  Requires
  * that the tallies hold exactly one mcx_run since the last reset
  * (MCX_E_STATE otherwise).  Runs with straggling are refused
  * (MCX_E_UNSUPPORTED: the estimator has no term for a straggled loss);
  * annihilation in flight (an unscored e+ hard event like the others),
  * several-material phantoms, forcing and splitting are supported.  The tallies and statistics are unchanged. */
 int mcx_dose_backward(mcx_ctx* ctx, const double* dl_ddose, double* dl_drho, int on_device, void* stream);
+
+/* Options of mcx_dose_backward.  MCX_GRAD_DEFLECTION_ENERGY also scores each
+ * soft deflection's dependence on the particle's energy (through the soft
+ * transport coefficient), chained to the density of every earlier step of
+ * the particle through the CSDA energy chain: it removes the estimator's
+ * bias on electron tracks (where the energy sets the angular spread) at the
+ * price of a larger variance.  Default 0.  Changing it keeps the last run's
+ * replays valid.  MCX_E_INVALID for unknown bits. */
+#define MCX_GRAD_DEFLECTION_ENERGY (1u << 0)
+int mcx_set_gradient(mcx_ctx* ctx, uint32_t flags);
 
 /* Dose (eV/g per history) and its standard error per voxel from the
  * accumulated counters, Eq. (1)-(3).  dose and sigma are caller-owned arrays
@@ -377,7 +393,7 @@ int mcx_workspace_size(mcx_ctx* ctx, size_t* bytes);
 int mcx_set_workspace(mcx_ctx* ctx, void* dev, size_t bytes);
 
 /* Size of the fixed device array of mcx_run_static (per device). */
-#define MCX_STATIC_SCRATCH_BYTES (72ull << 20)
+#define MCX_STATIC_SCRATCH_BYTES (73ull << 20)
 /* mcx_run for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation.  It
  * transports the same histories into the same tallies as mcx_run (the same

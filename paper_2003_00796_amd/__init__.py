@@ -15,8 +15,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# MCX_LIBRARY selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("MCX_LIBRARY") or os.path.join(_HERE, "libmcx.so")
+LIB_PATH = os.path.join(_HERE, "libmcx.so")
 
 FP64, MIXED = 0, 1
 PHOTON, ELECTRON, POSITRON = 0, 1, 2
@@ -25,6 +24,8 @@ NO_COMPTON, NO_PHOTO, NO_RAYLEIGH, NO_PAIR = 1, 2, 4, 8
 NO_HARD_ELASTIC, NO_HARD_INELASTIC, NO_HARD_BREMS = 16, 32, 64
 STRAGGLING = 128
 ANNIH_FLIGHT = 256
+# mcx_set_gradient: score the soft deflection's energy dependence (term E)
+GRAD_DEFLECTION_ENERGY = 1
 
 ERRORS = {0: "MCX_OK", -1: "MCX_E_INVALID", -2: "MCX_E_STATE", -3: "MCX_E_NOMEM", -4: "MCX_E_DEVICE",
           -5: "MCX_E_RANGE", -6: "MCX_E_CANCELLED", -7: "MCX_E_UNSUPPORTED"}
@@ -36,7 +37,7 @@ ABI_SYMBOLS = ("mcx_create", "mcx_destroy", "mcx_last_error", "mcx_set_transport
                "mcx_get_history_results", "mcx_dose_backward", "mcx_set_graph", "mcx_autotune",
                "mcx_synchronize", "mcx_cancel", "mcx_checkpoint", "mcx_restore", "mcx_workspace_size",
                "mcx_set_workspace", "mcx_set_influence", "mcx_get_influence", "mcx_ct_to_phantom",
-               "mcx_run_static")
+               "mcx_run_static", "mcx_set_gradient")
 
 
 class MaterialDesc(C.Structure):
@@ -149,6 +150,7 @@ def lib():
         L.mcx_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
         L.mcx_set_test_mode.argtypes = [vp, C.c_int]
         L.mcx_set_timing.argtypes = [vp, C.c_int]
+        L.mcx_set_gradient.argtypes = [vp, C.c_uint32]
         L.mcx_run.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp]
         L.mcx_run_static.argtypes = [vp, C.c_uint64, C.c_uint64, C.c_uint64, vp]
         L.mcx_get_dose.argtypes = [vp, vp, vp, C.c_int, vp]
@@ -274,6 +276,11 @@ class Simulator:
 
     def set_launch(self, bank: int = 0, block: int = 0, steps: int = 0):
         self._check(self._L.mcx_set_launch(self._h, bank, block, steps), "set_launch")
+
+    def set_gradient(self, flags: int):
+        """Options of the density gradient (GRAD_DEFLECTION_ENERGY)."""
+        self._check(self._L.mcx_set_gradient(self._h, int(flags)), "set_gradient")
+        return self
 
     def set_timing(self, on: bool):
         self._check(self._L.mcx_set_timing(self._h, 1 if on else 0), "set_timing")

@@ -142,6 +142,7 @@ struct Bank {
   Chunk* c[kMaxChunks];
   uint64_t* hash;  // event hash (test mode)
   double* w;       // statistical weight (interaction forcing)
+  T* clk;          // e+- queues only: majorant optical depth left before the next hard event
 };
 
 struct SourceDev {
@@ -226,6 +227,7 @@ struct KArgs {
   // 2: replay B scatters (Q_h - Qbar) times the photon free-flight scores)
   int mode;
   int straggle;          // soft energy-loss straggling on (selects the kernel flavour)
+  int grad_e;            // replay B: score the soft deflection's energy dependence (term E)
   int annih;             // positron annihilation in flight on (selects the kernel flavour)
   int mm;                // several materials (selects the kernel flavour)
   int vr;                // interaction forcing: weighted particles (selects the kernel flavour)

@@ -49,6 +49,7 @@ struct mcx_ctx {
   hipStream_t stream = nullptr;
   bool have_transport = false, have_material = false, have_phantom = false, have_sources = false;
   mcx_transport tr{};
+  uint32_t grad_flags = 0;  // mcx_set_gradient
   mcx_material_desc mat{};
   BuiltTables tabs;
   DevBuf d_tab;
@@ -188,14 +189,15 @@ void carve_banks(mcx_ctx* c, KArgs<T>& a) {
       b.c[k] = k < rec_chunks<T>() ? reinterpret_cast<Chunk*>(take(n * sizeof(Chunk))) : nullptr;
     b.hash = reinterpret_cast<uint64_t*>(take(n * sizeof(uint64_t)));
     b.w = reinterpret_cast<double*>(take(n * sizeof(double)));
+    b.clk = q == Q_E0 || q == Q_E1 ? reinterpret_cast<T*>(take(n * sizeof(T))) : nullptr;
   }
 }
 
 size_t queue_bytes(const mcx_ctx* c) {
   const size_t n = c->cap;
-  // records, event hashes, weights
+  // records, event hashes, weights; the hard-event clocks of the two e+- queues
   const size_t per = ((n * sizeof(Chunk) + 255) / 256 * 256) * (fp64(c) ? 5 : 4) + 2 * ((n * 8 + 255) / 256 * 256);
-  return per * Q_NQ;
+  return per * Q_NQ + 2 * ((n * tsize(c) + 255) / 256 * 256);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -314,6 +316,7 @@ void fill_args(mcx_ctx* c, KArgs<T>& a, uint32_t seed, int mode = 0, double qbar
   a.steps = c->steps;
   a.mode = mode;
   a.straggle = (c->tr.flags & MCX_STRAGGLING) ? 1 : 0;
+  a.grad_e = (c->grad_flags & MCX_GRAD_DEFLECTION_ENERGY) ? 1 : 0;
   a.annih = (c->tr.flags & MCX_ANNIH_FLIGHT) ? 1 : 0;
   a.mm = c->d_vmat.p ? 1 : 0;
   a.vr = weighted_run(c->tr) ? 1 : 0;
@@ -885,6 +888,13 @@ int mcx_set_launch(mcx_ctx* c, uint32_t bank, uint32_t block, uint32_t steps) {
     if (steps > 4096) return fail(c, MCX_E_INVALID, "steps must be <= 4096");
     c->steps = steps;
   }
+  return MCX_OK;
+}
+
+int mcx_set_gradient(mcx_ctx* c, uint32_t flags) {
+  if (!c) return MCX_E_INVALID;
+  if (flags & ~uint32_t(MCX_GRAD_DEFLECTION_ENERGY)) return fail(c, MCX_E_INVALID, "unknown gradient flags 0x%x", flags);
+  c->grad_flags = flags;
   return MCX_OK;
 }
 

@@ -247,6 +247,7 @@ struct Part {
   uint64_t uid;
   uint64_t hash;
   double w;  // statistical weight (1 without interaction forcing)
+  T clk;     // e+-: majorant optical depth left before the next hard or delta event, 0 if none pending
   Rng<T> rng;
 };
 
@@ -270,7 +271,7 @@ __device__ __forceinline__ uint32_t pack_vox(const int ix[3]) {
 template <typename T>
 __device__ __forceinline__ void store_record(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
                                              const T d[3], T e, uint64_t uid, uint32_t ctr, uint32_t flags,
-                                             uint64_t hash, double w) {
+                                             uint64_t hash, double w, T clk) {
   Chunk c0, c1, cm;
   split_f64(p.x[0], c0.x, c0.y);
   split_f64(p.x[1], c0.z, c0.w);
@@ -302,6 +303,7 @@ __device__ __forceinline__ void store_record(const KArgs<T>& a, const Bank<T>& b
   }
   if (a.test_mode) b.hash[i] = hash;
   if (a.vr) b.w[i] = w;
+  if (b.clk) b.clk[i] = clk;  // the e+- queues
 }
 
 template <typename T>
@@ -333,12 +335,13 @@ __device__ __forceinline__ void load_part(const KArgs<T>& a, const Bank<T>& b, u
   p.nchild = cm.w >> 2;
   p.hash = a.test_mode ? b.hash[i] : 0ull;
   p.w = a.vr ? b.w[i] : 1.0;
+  p.clk = b.clk ? b.clk[i] : T(0);
   rng_init(p.rng, a.seed, p.hist, p.uid, cm.y);
 }
 
 template <typename T>
 __device__ __forceinline__ void store_part(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p) {
-  store_record(a, b, i, p, p.d, p.e, p.uid, p.rng.ctr, p.type | (p.nchild << 2), p.hash, p.w);
+  store_record(a, b, i, p, p.d, p.e, p.uid, p.rng.ctr, p.type | (p.nchild << 2), p.hash, p.w, p.clk);
 }
 
 // a secondary waiting to be appended: shares position/voxel/history with its parent
@@ -355,7 +358,7 @@ struct Child {
 template <typename T>
 __device__ __forceinline__ void store_child(const KArgs<T>& a, const Bank<T>& b, uint32_t i, const Part<T>& p,
                                             const Child<T>& c) {
-  store_record(a, b, i, p, c.d, c.e, c.uid, 0u, c.type, 0ull, c.w);
+  store_record(a, b, i, p, c.d, c.e, c.uid, 0u, c.type, 0ull, c.w, T(0));
 }
 
 // ---------------------------------------------------------------------------

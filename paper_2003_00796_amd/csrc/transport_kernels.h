@@ -182,6 +182,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_source(KArgs<T> a, int par) {
       p.nchild = 0u;
       p.hash = 0ull;
       p.w = 1.0;
+      p.clk = T(0);
       rng_init(p.rng, a.seed, p.hist, 1ull, 0u);
       p.x[0] = s.pos[0]; p.x[1] = s.pos[1]; p.x[2] = s.pos[2];
       p.d[0] = T(s.dir[0]); p.d[1] = T(s.dir[1]); p.d[2] = T(s.dir[2]);
@@ -829,6 +830,7 @@ __device__ __forceinline__ T sigma_annih(const Tab<T>& tb, T e) {
 struct EGrad {
   uint32_t v;
   double score, coef, r, d, lam_end;
+  double se;  // d ln p(mu) / dE of the hinge's soft deflection (term E), 0 without a hinge
   bool end;
 };
 
@@ -863,6 +865,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     eg.r = 1.0;
     eg.d = a.adj_w[eg.v] * (a.vr ? p.w : 1.0);
     eg.lam_end = 0.0;
+    eg.se = 0.0;
     eg.end = false;
   }
   if (!(p.e > eabs)) {
@@ -902,14 +905,13 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     // value at the interval's low end bounds it over the step
     if (a.annih && lep) smaj += sigma_annih(tb, elo);
   }
-  const T u1 = uni<T>(p.rng);
-  const T tau_h = smaj > T(0) ? -M<T>::log(u1) / smaj : M<T>::inf();
+  // the hard-event clock: a pending free path runs on across steps, so where
+  // faces cut a track does not change where its hard events fall
+  if (!(p.clk > T(0))) p.clk = -M<T>::log(uni<T>(p.rng));
+  const T tau_h = smaj > T(0) ? p.clk / smaj : M<T>::inf();
   const bool capped = !(tau_h <= tau_max);
   const T tau_s = capped ? tau_max : tau_h;
   const double len = double(tau_s / rho);
-  // gradient: score of the majorant process's geometric free path, density
-  // rho smaj exp(-rho smaj s) below the cap and tail exp(-rho smaj len) at it
-  if constexpr (G != 0) eg.score = -double(smaj) * len + (capped ? 0.0 : 1.0 / double(rho));
   const double th = double(uni<T>(p.rng)) * len;
   int ax;
   const double db = face_dist(a, p, &ax);
@@ -918,38 +920,82 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     if constexpr (G != 0) eg.end = true;
     return false;
   }
-  // soft loss over the geometric length travelled: db when the face comes
-  // before the hinge (then the step ends at the face), else the whole step
-  // charged at the hinge; one range inversion serves both cases
-  const bool face_first = db <= th;
-  const double mass_path = double(rho) * (face_first ? db : len);
+  // the step ends at the first face on its path or at its full length; a
+  // reached hinge deflects the particle by the soft angular law of the whole
+  // step.  The soft loss is charged where the step ends, over the geometric
+  // length s travelled, so the energy along a track is the CSDA energy of
+  // the path travelled whatever the voxel size.
+  bool face_end = db <= th;
+  double s = db, after = db;
+  if (!face_end) {
+    move(p, th);
+    const T t1s = interp(tab, nt, base + O_LT1S, g, e, T(0));
+    const T mbar = T(0.5) * (T(1) - M<T>::exp(-T(double(rho) * len) * t1s));
+    const T A = soft_a(mbar, soft);
+    const T u3 = uni<T>(p.rng);
+    const T mu = A * u3 / (T(1) + A - u3);
+    if constexpr (G != 0) {
+      const double sc = soft_score(double(A), double(mu), double(mbar), len, double(t1s));
+      eg.score += sc;
+      if (a.grad_e) {
+        // the same law's score with respect to the energy: <mu> moves with E
+        // through t1s, a power law between nodes (stored as logarithms)
+        const T l0 = tab[(base + O_LT1S) * nt + g.i], l1 = tab[(base + O_LT1S) * nt + g.i + 1];
+        if (l0 > -M<T>::inf() && l1 > -M<T>::inf())
+          eg.se = sc * double(rho) * double(l1 - l0) * double(tb.inv_dl) / double(e);
+      }
+    }
+    const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+    rotate(p.d, T(1) - T(2) * mu, phi);
+    const double rem = len - th;
+    const double db2 = face_dist(a, p, &ax);
+    if (ax < 0) {
+      atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+      if constexpr (G != 0) eg.end = true;
+      return false;
+    }
+    face_end = db2 <= rem;
+    after = face_end ? db2 : rem;
+    s = face_end ? th + db2 : len;
+  }
+  const double mass_path = double(rho) * s;
+  // the clock runs down by the majorant optical depth of the path; a step
+  // that ends uncapped at its full length ends at an event (below)
+  const bool event_end = !face_end && !capped;
+  p.clk = event_end ? T(0) : p.clk - smaj * T(mass_path);
+  // gradient: the candidate events of the majorant process along the path
+  // are a Poisson process of rate rho smaj per unit length: -smaj s over the
+  // path, +1/rho at an event
+  if constexpr (G != 0) eg.score += -double(smaj) * s + (event_end ? 1.0 / double(rho) : 0.0);
   T e1 = range_inv(tab, nt, base, T(r0 - T(mass_path)), g.i);
   if (!(e1 < e)) e1 = e;
   if (EXT && a.straggle) {
     // the loss keeps its CSDA mean and fluctuates about it (drawn after the
-    // hinge position, before the soft deflection)
+    // soft deflection)
     e1 = e - soft_straggle(tb, lep, e, e - e1, mass_path, p.rng);
     if (!(e1 > T(0))) e1 = T(0);
   }
   if (!DRY) deposit(a, acc, ls, p, e - e1);
   p.e = e1;
   if constexpr (G != 0) {
-    // d(loss)/d rho at fixed geometric length l = l S(E1); dE1/dE = S(E1)/S(E)
+    // d(loss)/d rho at fixed geometric length s = s S(E1); dE1/dE = S(E1)/S(E)
     const Grid<T> g1 = grid_at(tb, M<T>::log(e1));
     const double s1 = double(interp(tab, nt, base + O_LS, g1, e1, T(0)));
-    eg.coef = (face_first ? db : len) * s1;
+    eg.coef = s * s1;
     eg.r = s1 / double(ss);
   }
-  if (face_first) {
+  if (face_end) {
+    // an energy at or below Eabs is absorbed at the next step's start, in
+    // the voxel entered
     if (!DRY) event(a, p, EV_CROSS, v);
-    if (cross(a, p, db, ax, ls)) {
+    if (cross(a, p, after, ax, ls)) {
       if constexpr (G != 0) eg.end = true;
       if (!DRY) e_escape(a, p, v, bs);
       return false;
     }
     return true;
   }
-  move(p, th);
+  move(p, after);
   if (!(e1 > eabs)) {
     if constexpr (G != 0) {
       eg.end = true;
@@ -958,31 +1004,6 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     if (!DRY) e_absorb(a, p, c1, c2, acc, ls, bs);
     return false;
   }
-  const T t1s = interp(tab, nt, base + O_LT1S, g, e, T(0));
-  const T mbar = T(0.5) * (T(1) - M<T>::exp(-T(double(rho) * len) * t1s));
-  const T A = soft_a(mbar, soft);
-  const T u3 = uni<T>(p.rng);
-  const T mu = A * u3 / (T(1) + A - u3);
-  if constexpr (G != 0) eg.score += soft_score(double(A), double(mu), double(mbar), len, double(t1s));
-  const T phi = T(2.0 * kPi) * uni<T>(p.rng);
-  rotate(p.d, T(1) - T(2) * mu, phi);
-  const double rem = len - th;
-  const double db2 = face_dist(a, p, &ax);
-  if (ax < 0) {
-    atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
-    if constexpr (G != 0) eg.end = true;
-    return false;
-  }
-  if (db2 <= rem) {
-    if (!DRY) event(a, p, EV_CROSS, v);
-    if (cross(a, p, db2, ax, ls)) {
-      if constexpr (G != 0) eg.end = true;
-      if (!DRY) e_escape(a, p, v, bs);
-      return false;
-    }
-    return true;
-  }
-  move(p, rem);
   if (capped) {
     if (!DRY) event(a, p, EV_STEP, v);
     return true;
@@ -1196,6 +1217,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
   bool ahead = false;
   uint32_t rec = 0;
   double lam_tot = 0.0, lam_pre = 0.0, lam_p = 1.0;
+  double psi_tot = 0.0, psi_pre = 0.0;  // term E: the same sums of the hinges' energy scores
   uint32_t used = 0, dry = 0;
   uint32_t rbase = 0, rleft = 0;  // the wavefront's reserved input records [rbase, rbase + rleft)
   for (;;) {
@@ -1230,6 +1252,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
           ahead = true;
           rec = striped_record(sums, idx, cs);
           lam_tot = 0.0;
+          psi_tot = 0.0;
           lam_p = 1.0;
         }
       }
@@ -1259,6 +1282,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
           // the chain factors before step k: every later step's energy
           // adjoint follows from it and the sums before that step
           lam_tot += eg.d * (1.0 - eg.r) * lam_p;
+          psi_tot += eg.se * lam_p;
           lam_p *= eg.r;
           if (!alive) {
             lam_tot += eg.lam_end * lam_p;
@@ -1266,16 +1290,21 @@ __global__ __launch_bounds__(kMaxBlock, MCX_ESTEP_WAVES) void k_estep(KArgs<T> a
             alive = true;
             ahead = false;
             lam_pre = 0.0;
+            psi_pre = 0.0;
             lam_p = 1.0;
           }
         } else {
           // the history's centred score times the step's scores, and the soft
           // loss it deposits here minus what the particle then lacks downstream
           lam_pre += eg.d * (1.0 - eg.r) * lam_p;
+          psi_pre += eg.se * lam_p;
           lam_p *= eg.r;
           const double lam_after = eg.end ? eg.lam_end : (lam_tot - lam_pre) / lam_p;
+          // term E: the later hinges' energy scores, chained back to this
+          // step's end, times d(E1)/d rho = -s S(E1)
+          const double psi_after = eg.end ? 0.0 : (psi_tot - psi_pre) / lam_p;
           const double cq = a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar;
-          const double gv = cq * eg.score + eg.coef * (eg.d - lam_after);
+          const double gv = cq * (eg.score - eg.coef * psi_after) + eg.coef * (eg.d - lam_after);
           if (gv != 0.0) unsafeAtomicAdd(&a.adj_grad[eg.v], gv);
         }
       }

@@ -140,7 +140,7 @@ def test_forced_gradient_matches_oracle():
         go, _ = O.gradient(tb, wl["phantom"], wl["sources"], wl["seed"], 0, n, c, do)
         rel = np.abs(g - go) / np.abs(go).max()
         print("forced gradient: max deviation", rel.max())
-        assert rel.max() < 1e-9
+        assert rel.max() < 1e-8  # Class II bound, see test_gpu_gradient.CLASS2_TOL
 
 
 def test_forcing_refusals():

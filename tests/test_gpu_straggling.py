@@ -2,8 +2,8 @@
 against the FP64 oracle with the same option, through the C ABI.
 
 The straggled loss keeps the CSDA value as its mean and draws its
-fluctuation from the particle's own random stream right after the hinge
-position, so the FP64 GPU path must reproduce the oracle's event sequences
+fluctuation from the particle's own random stream where the step ends (after
+the hinge's deflection, if the hinge is reached), so the FP64 GPU path must reproduce the oracle's event sequences
 (>= 99.9% of the 1 MeV photon pencil histories, >= 99% on the other cases)
 and per-history ledgers, conserve energy per history, and give doses within
 3 combined standard errors.  The thin-slab case (hard channels off, one
@@ -107,7 +107,8 @@ def test_straggling_particle_types_parity(case):
 def test_straggling_thin_slab_per_history_losses():
     """One straggled soft loss per history (hard channels off, 1 mm slab):
     the GPU deposits the oracle's energy history by history, and without
-    straggling the losses take only the two CSDA values."""
+    straggling every history whose face came before its hinge (1 - d/len,
+    about half) loses the one CSDA value over the slab's thickness."""
     e0 = 10.0
     hard_off = O.NO_HARD_ELASTIC | O.NO_HARD_INELASTIC | O.NO_HARD_BREMS
     base = dict(W.workload("electron_200"), phantom=W.slab_phantom(1, 0.1, [1.0]),
@@ -122,7 +123,8 @@ def test_straggling_thin_slab_per_history_losses():
     # straggled: a spread of losses, not two values
     assert np.unique(np.round(g["led"][:, 0], 9)).size > n // 4
     g0 = gpu_run(base, n)
-    assert np.unique(np.round(g0["led"][:, 0], 9)).size < 20
+    _, counts = np.unique(np.round(g0["led"][:, 0], 9), return_counts=True)
+    assert counts.max() > 0.4 * n
     # the mean loss is the CSDA mean in both (the same hinge law)
     se = np.sqrt(g["led"][:, 0].var() / n + g0["led"][:, 0].var() / n)
     assert abs(g["led"][:, 0].mean() - g0["led"][:, 0].mean()) < 5 * se
