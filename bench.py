@@ -66,12 +66,12 @@ def depth_dose(d: np.ndarray) -> np.ndarray:
     return d.reshape(d.shape[0], -1).sum(axis=1)
 
 
-def paired_deviation(d_mix: list, d_64: list) -> dict:
+def paired_deviation(d_mix: list, d_64: list, frac: float = 0.5) -> dict:
     """Mixed against FP64 on the same streams, K batches (one per seed):
     the deviation Delta_b = D_mix,b - D_64,b of each batch splits into a
     systematic part, the mean over batches, and a statistical part (the few
     histories whose FP32 rounding took another branch), whose size the
-    batch-to-batch spread measures.  Over the voxels with D_64 >= 50% of the
+    batch-to-batch spread measures.  Over the voxels with D_64 >= frac of the
     maximum: the mean relative shift with its standard error; the RMS of the
     per-voxel mean shift and the RMS its noise alone would give; the
     systematic RMS that remains, sqrt(max(0, rms^2 - noise^2)); the same
@@ -80,9 +80,9 @@ def paired_deviation(d_mix: list, d_64: list) -> dict:
     k = len(d_mix)
     dm = np.array([a - b for a, b in zip(d_mix, d_64)])
     d64 = np.mean(d_64, axis=0)
-    hi = d64 >= 0.5 * d64.max()
+    hi = d64 >= frac * d64.max()
     rel = dm[:, hi] / d64[hi]
-    out = dict(batches=k, voxels=int(hi.sum()), per_batch_rms=float(np.sqrt(np.mean(rel ** 2))))
+    out = dict(batches=k, voxel_threshold=frac, voxels=int(hi.sum()), per_batch_rms=float(np.sqrt(np.mean(rel ** 2))))
     if k < 2:
         return out
     mean_v = rel.mean(axis=0)
@@ -461,11 +461,11 @@ def electron_comparison(mcx, W, sync, n: int = 1_000_000, batches: int = 4) -> d
         sim.close()
         out[name] = dict(value=n * len(t) / sum(t), ms=1e3 * sum(t) / len(t))
     out["mixed_over_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    pd = paired_deviation(doses["mixed"], doses["fp64"])
+    pd = paired_deviation(doses["mixed"], doses["fp64"], frac=0.1)
     dm, d6 = np.mean(doses["mixed"], axis=0), np.mean(doses["fp64"], axis=0)
     hi = d6 >= 0.1 * d6.max()
     rel = (dm[hi] - d6[hi]) / d6[hi]
-    out["deviation"] = dict(depth_dose=pd, voxels_above_10pct=int(hi.sum()),
+    out["deviation"] = dict(paired=pd, voxels_above_10pct=int(hi.sum()),
                             voxel_rms_above_10pct=float(np.sqrt(np.mean(rel ** 2))),
                             sum_ratio=float(dm.sum() / d6.sum()))
     out["workload"] = f"electron_200: 20 MeV e- pencil, 200^3 x 1 mm water, {batches} x {n} histories"

@@ -124,8 +124,8 @@ typedef struct {
    * primary (energy loss, deflection) with probability 1/F, so that every
    * expectation is unchanged while F times more secondaries are produced.
    * 0 or 1 = analog; otherwise F in [1, 1e5] (MCX_E_INVALID if not).
-   * Runs on one-material phantoms (mcx_run returns MCX_E_UNSUPPORTED with a
-   * material index array); mcx_dose_backward weights the deposits and
+   * Each material's tables carry the forced cross sections (several-material
+   * phantoms included); mcx_dose_backward weights the deposits and
    * soft-loss terms (the photon-flight scores are the analog ones). */
   double force_in, force_br;
   /* Bremsstrahlung splitting (the same example splits emitted photons by 2):

@@ -39,6 +39,11 @@ static hipError_t launch_flavor(const KArgs<float>& a, int par, uint32_t target,
 hipError_t launch_iteration(const KArgs<float>& a, int par, uint32_t target, int grid, int block, hipStream_t s,
                             hipEvent_t* ev) {
   // replays never write the test outputs
+  if (a.mode == 1 && a.mm && a.vr) return launch_flavor<FL_MMVR_ADJ_A>(a, par, target, grid, block, s, ev);
+  if (a.mode == 2 && a.mm && a.vr) return launch_flavor<FL_MMVR_ADJ_B>(a, par, target, grid, block, s, ev);
+  if (a.mode == 0 && a.mm && a.vr)
+    return a.test_mode ? launch_flavor<FL_MMVR_TEST>(a, par, target, grid, block, s, ev)
+                       : launch_flavor<FL_MMVR>(a, par, target, grid, block, s, ev);
   if (a.mode == 1)
     return a.mm ? launch_flavor<FL_MM_ADJ_A>(a, par, target, grid, block, s, ev)
                 : (a.vr ? launch_flavor<FL_VR_ADJ_A>(a, par, target, grid, block, s, ev)
@@ -92,7 +97,11 @@ hipError_t configure_kernels(int n_grid, bool fp64) {
                              reinterpret_cast<const void*>(&k_estep<float, FL_VR_ADJ_A>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_VR_ADJ_B>),
                              reinterpret_cast<const void*>(&k_estep<float, FL_EXT_ADJ_A>),
-                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_ADJ_B>)};
+                             reinterpret_cast<const void*>(&k_estep<float, FL_EXT_ADJ_B>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MMVR>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MMVR_TEST>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MMVR_ADJ_A>),
+                             reinterpret_cast<const void*>(&k_estep<float, FL_MMVR_ADJ_B>)};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

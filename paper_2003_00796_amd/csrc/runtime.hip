@@ -110,6 +110,10 @@ struct mcx_ctx {
   double ms_transport = 0.0, ms_flush = 0.0;
   // replay batches of iterations as one captured HIP graph (timing off only)
   int use_graph = 1;
+  // the instantiated batch graph of the last run of each mode (forward,
+  // replay A, replay B): a later run with the same kernels only updates its
+  // arguments (hipGraphExecUpdate) instead of instantiating a new one
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
   // per-kernel timing with HIP events on the run's stream
   int timing = 0;
   std::vector<hipEvent_t> events;  // kBatch iterations x (kTimedKernels + 1)
@@ -392,24 +396,37 @@ int run_impl(mcx_ctx* c, uint32_t seed, uint64_t first, uint64_t n, hipStream_t 
   hipGraphExec_t gexec = nullptr;
   const bool use_graph = allow_graph && c->use_graph && !c->timing;
   if (use_graph) {
+    // capture this run's batch (its kernels and arguments); the context keeps
+    // the instantiated graph of the mode's last run and updates it in place
+    // when the kernels are the same (only arguments changed), which is much
+    // cheaper than instantiating
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < kBatch && e == hipSuccess; ++k) e = launch_iteration(a, k & 1, target, grid, int(c->block), s, nullptr);
     hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    hipGraphExec_t& cached = c->gexec[mode];
+    if (e == hipSuccess && cached) {
+      hipGraphNode_t bad = nullptr;
+      hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+      if (hipGraphExecUpdate(cached, graph, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+        gexec = cached;
+      } else {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(cached);
+        cached = nullptr;
+      }
+    }
+    if (e == hipSuccess && !gexec) {
+      e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      if (e == hipSuccess) cached = gexec;
+    }
     if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return hip_fail(c, e, "capture of the iteration graph");
     }
   }
-  struct GraphGuard {
-    hipGraphExec_t g;
-    ~GraphGuard() {
-      if (g) (void)hipGraphExecDestroy(g);
-    }
-  } guard{gexec};
   bool cancelled = false;
   while (done < n && !cancelled) {
     uint64_t chunk;
@@ -561,8 +578,6 @@ int check_run(mcx_ctx* c, uint64_t seed, uint64_t first, uint64_t n) {
   if (seed > 0xFFFFFFFFull) return fail(c, MCX_E_INVALID, "seed must be < 2^32");
   for (int k = 0; k <= c->vmat_max; ++k)
     if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
-  if (weighted_run(c->tr) && c->d_vmat.p)
-    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing and splitting run on one-material phantoms");
   if (first + n > c->total_hist || first + n < first) return fail(c, MCX_E_RANGE, "history range exceeds the sources");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");
   return MCX_OK;
@@ -633,6 +648,8 @@ void mcx_destroy(mcx_ctx* c) {
                     &c->d_adj_sum, &c->d_hhash, &c->d_hled})
     dfree(*b);
   if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+  for (hipGraphExec_t& g : c->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1111,8 +1128,6 @@ int mcx_dose_backward(mcx_ctx* c, const double* dl_ddose, double* dl_drho, int o
     return fail(c, MCX_E_STATE, "the tallies must hold exactly one run since the last reset, with its setup unchanged");
   for (int k = 0; k <= c->vmat_max; ++k)
     if (!c->have_mat[k]) return fail(c, MCX_E_STATE, "the phantom uses material %d, which is not loaded", k);
-  if (weighted_run(c->tr) && c->d_vmat.p)
-    return fail(c, MCX_E_UNSUPPORTED, "interaction forcing and splitting run on one-material phantoms");
   if (c->tr.flags & MCX_STRAGGLING)
     return fail(c, MCX_E_UNSUPPORTED, "the gradient has no term for a straggled soft loss");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MCX_E_DEVICE, "hipSetDevice");

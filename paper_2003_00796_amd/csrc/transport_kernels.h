@@ -52,26 +52,36 @@ enum Flavor : int {
   FL_VR_ADJ_A = 12,   // the density-gradient replays with weighted particles
   FL_VR_ADJ_B = 13,
   FL_EXT_ADJ_A = 14,  // the density-gradient replays with annihilation in flight
-  FL_EXT_ADJ_B = 15
+  FL_EXT_ADJ_B = 15,
+  FL_MMVR = 16,       // several materials and weighted particles, with the optional physics
+  FL_MMVR_TEST = 17,  // the same with the per-history test outputs
+  FL_MMVR_ADJ_A = 18, // the density-gradient replays on several materials with weights
+  FL_MMVR_ADJ_B = 19
 };
-constexpr int kFlavors = 16;
+constexpr int kFlavors = 20;
 
 // the optional physics changes the e+- step only: the other kernels of an
 // extended flavour are those of the flavour without it; several materials
 // change the photon flight and interactions too
 constexpr int base_flavor(int f) {
-  return (f == FL_EXT || f == FL_MM || f == FL_VR)
+  return (f == FL_EXT || f == FL_MM || f == FL_VR || f == FL_MMVR)
              ? FL_FWD
-             : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST)
+             : ((f == FL_EXT_TEST || f == FL_MM_TEST || f == FL_VR_TEST || f == FL_MMVR_TEST)
                     ? FL_TEST
-                    : ((f == FL_MM_ADJ_A || f == FL_VR_ADJ_A || f == FL_EXT_ADJ_A)
+                    : ((f == FL_MM_ADJ_A || f == FL_VR_ADJ_A || f == FL_EXT_ADJ_A || f == FL_MMVR_ADJ_A)
                            ? FL_ADJ_A
-                           : ((f == FL_MM_ADJ_B || f == FL_VR_ADJ_B || f == FL_EXT_ADJ_B) ? FL_ADJ_B : f)));
+                           : ((f == FL_MM_ADJ_B || f == FL_VR_ADJ_B || f == FL_EXT_ADJ_B || f == FL_MMVR_ADJ_B)
+                                  ? FL_ADJ_B
+                                  : f)));
 }
 constexpr bool extended(int f) { return f >= FL_EXT; }
-constexpr bool several(int f) { return f == FL_MM || f == FL_MM_TEST || f == FL_MM_ADJ_A || f == FL_MM_ADJ_B; }
+constexpr bool several(int f) {
+  return f == FL_MM || f == FL_MM_TEST || f == FL_MM_ADJ_A || f == FL_MM_ADJ_B || f >= FL_MMVR;
+}
 // weighted particles: every kernel carries the weights
-constexpr bool weighted(int f) { return f == FL_VR || f == FL_VR_TEST || f == FL_VR_ADJ_A || f == FL_VR_ADJ_B; }
+constexpr bool weighted(int f) {
+  return f == FL_VR || f == FL_VR_TEST || f == FL_VR_ADJ_A || f == FL_VR_ADJ_B || f >= FL_MMVR;
+}
 constexpr int photon_flavor(int f) { return several(f) || weighted(f) ? f : base_flavor(f); }
 constexpr int source_flavor(int f) { return weighted(f) ? f : base_flavor(f); }
 
@@ -1397,23 +1407,36 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
 template <typename T>
 __global__ void k_flush(TSlot* tab, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt, int test_mode,
                         double* hist_led, uint64_t n_run) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  // the table is a stream of 16-byte slots: each thread loads kFlushUnroll
+  // of them (a wavefront's loads coalesce) before it examines any, so that
+  // several loads are in flight per thread; occupied slots add q^2 and are
+  // emptied
+  constexpr int kFlushUnroll = 4;
+  const uint64_t lanes = uint64_t(gridDim.x) * blockDim.x;
   uint32_t occ = 0;
   double dep = 0.0;  // deposited energy, for the run statistics
-  for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
-    const TSlot t = tab[s];
-    const uint64_t k = t.key;
-    if (k == kEmptyKey) continue;
-    const double q = t.q;
-    dep += q;
-    const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
-    unsafeAtomicAdd(&sum_q2[v], q * q);  // Sum q was formed at insertion
-    if (test_mode) {
-      const uint64_t h = (k >> 32) - cnt->run_first;
-      if (h < n_run) unsafeAtomicAdd(&hist_led[3 * h], q);
+  for (uint64_t s0 = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s0 < nslot; s0 += kFlushUnroll * lanes) {
+    TSlot t[kFlushUnroll];
+#pragma unroll
+    for (int j = 0; j < kFlushUnroll; ++j) {
+      const uint64_t s = s0 + uint64_t(j) * lanes;
+      t[j] = s < nslot ? tab[s] : TSlot{kEmptyKey, 0.0};
     }
-    tab[s] = TSlot{kEmptyKey, 0.0};
-    ++occ;
+#pragma unroll
+    for (int j = 0; j < kFlushUnroll; ++j) {
+      const uint64_t k = t[j].key;
+      if (k == kEmptyKey) continue;
+      const double q = t[j].q;
+      dep += q;
+      const uint32_t v = uint32_t(k & 0xFFFFFFFFull);
+      unsafeAtomicAdd(&sum_q2[v], q * q);  // Sum q was formed at insertion
+      if (test_mode) {
+        const uint64_t h = (k >> 32) - cnt->run_first;
+        if (h < n_run) unsafeAtomicAdd(&hist_led[3 * h], q);
+      }
+      tab[s0 + uint64_t(j) * lanes] = TSlot{kEmptyKey, 0.0};
+      ++occ;
+    }
   }
   occ = wave_sum(occ);
   dep = wave_sum(dep);

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tally_checks import check_tally_parity
+from tally_checks import check_tally_parity, check_gradient_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -127,4 +127,4 @@ def test_annihilation_mixed_precision_and_gradient():
     go, _ = O.gradient(tb, wl["phantom"], wl["sources"], wl["seed"], 0, 1000, c, d)
     rel = np.abs(g - go) / np.abs(go).max()
     print("gradient with annihilation in flight: max deviation", rel.max())
-    assert rel.max() < 1e-8  # Class II bound, see test_gpu_gradient.CLASS2_TOL
+    check_gradient_parity(g, go, class2=True)

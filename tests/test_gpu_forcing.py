@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tally_checks import check_tally_parity
+from tally_checks import check_tally_parity, check_gradient_parity
 
 pytestmark = pytest.mark.gpu
 MC2 = W.MC2
@@ -34,8 +34,11 @@ def gpu_run(wl, n, precision=0, test=True):
 
 
 def oracle_run(wl, n):
-    r = O.run(O.Tables(wl["material"], wl["transport"]), wl["phantom"], wl["sources"], wl["seed"], 0, n,
-              hashes=True, ledger=True)
+    if wl.get("phantom", {}).get("mat") is not None:
+        tbs = [O.Tables(m, wl["transport"]) for m in wl["materials"]]
+    else:
+        tbs = O.Tables(wl["material"], wl["transport"])
+    r = O.run(tbs, wl["phantom"], wl["sources"], wl["seed"], 0, n, hashes=True, ledger=True)
     d, s = O.dose(wl["phantom"], r)
     return dict(hash=r.hashes, led=r.ledger, dose=d, sigma=s, q=r.sum_q, q2=r.sum_q2, stats=r.stats.as_dict())
 
@@ -140,7 +143,7 @@ def test_forced_gradient_matches_oracle():
         go, _ = O.gradient(tb, wl["phantom"], wl["sources"], wl["seed"], 0, n, c, do)
         rel = np.abs(g - go) / np.abs(go).max()
         print("forced gradient: max deviation", rel.max())
-        assert rel.max() < 1e-8  # Class II bound, see test_gpu_gradient.CLASS2_TOL
+        check_gradient_parity(g, go, class2=True)
 
 
 def test_forcing_refusals():
@@ -154,12 +157,57 @@ def test_forcing_refusals():
     with pytest.raises(mcx.MCXError, match="INVALID"):
         sim.set_transport(dict(wl["transport"], split_br=3))
     sim.close()
-    mm = dict(W.workload("hetero_mm_64", 100))
-    mm["transport"] = dict(mm["transport"], force_br=10.0)
-    sim = mcx.Simulator(0, 0).setup(mm)
-    with pytest.raises(mcx.MCXError, match="UNSUPPORTED"):
-        sim.run(mm["seed"], 0, 100)
+
+
+def _three_material_layers(particle, e0, n, **force):
+    """Water, bone and lung layers (1 cm) of the several-material workload's
+    materials, with forcing."""
+    rho = np.array([1.0, 1.85, 0.26, 1.0, 1.85, 0.3, 1.0, 0.26] * 2)
+    mat = np.array([0, 1, 2, 0, 1, 2, 0, 2] * 2, dtype=np.uint8)
+    ph = W.slab_phantom(len(rho), 1.0, rho)
+    ph["mat"] = np.broadcast_to(mat[:, None, None], ph["rho"].shape).copy()
+    base = W.workload("hetero_mm_64")
+    t = dict(W.transport(100.0, 250), **force)
+    return dict(base, phantom=ph, transport=t, sources=[W.pencil(particle, e0, (50.0, 50.0, 0.0), n)])
+
+
+@pytest.mark.parametrize("case", ["electrons_forced_split", "photons_forced"])
+def test_forcing_on_several_materials_parity(case):
+    """Forcing and splitting on a phantom of water, bone and lung: the
+    several-material weighted kernels reproduce the oracle's event sequences
+    and weighted ledgers, and the doses agree within 3 combined standard
+    errors."""
+    if case == "electrons_forced_split":
+        wl = _three_material_layers(1, 10.0, 800, force_in=4.0, force_br=20.0, split_br=2)
+    else:
+        wl = _three_material_layers(0, 6.0, 3000, force_in=4.0, force_br=20.0)
+    n = wl["sources"][0]["n_hist"]
+    g, o = gpu_run(wl, n), oracle_run(wl, n)
+    same = g["hash"] == o["hash"]
+    print(case, "identical hashes", same.mean())
+    assert same.mean() >= 0.99
+    assert np.allclose(g["led"][same], o["led"][same][:, [0, 1, 2]], rtol=0, atol=1e-8)
+    check_dose_3sigma(g, o)
+
+
+def test_forced_gradient_on_several_materials_matches_oracle():
+    """The replays with weights on a three-material phantom against the
+    oracle's several-material gradient on the same histories."""
+    mcx = _mcx()
+    wl = _three_material_layers(1, 10.0, 400, force_in=4.0, force_br=20.0, split_br=2)
+    n = wl["sources"][0]["n_hist"]
+    c = np.random.default_rng(8).uniform(-1.0, 1.0, size=wl["phantom"]["rho"].shape)
+    sim = mcx.Simulator(0, 0).setup(wl)
+    sim.run(wl["seed"], 0, n)
+    g = sim.dose_backward(c)
     sim.close()
+    tbs = [O.Tables(m, wl["transport"]) for m in wl["materials"]]
+    r = O.run(tbs, wl["phantom"], wl["sources"], wl["seed"], 0, n)
+    do, _ = O.dose(wl["phantom"], r)
+    go, _ = O.gradient(tbs, wl["phantom"], wl["sources"], wl["seed"], 0, n, c, do)
+    rel = np.abs(g - go) / np.abs(go).max()
+    print("forced several-material gradient: max deviation", rel.max())
+    check_gradient_parity(g, go, class2=True)
 
 
 def test_full_size_sampled_histories_forced_and_split():

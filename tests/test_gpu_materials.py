@@ -54,7 +54,7 @@ def check_dose_3sigma(g, o, frac=0.01):
 
 def layered():
     rho = np.array([1.0, 1.85, 0.3, 1.85, 1.0, 0.26, 1.85, 1.0] * 2)
-    mat = np.array([0, 1, 0, 1, 0, 0, 1, 0] * 2, dtype=np.uint8)
+    mat = np.array([0, 1, 2, 1, 0, 2, 1, 0] * 2, dtype=np.uint8)  # water, bone, lung
     ph = W.slab_phantom(len(rho), 1.0, rho)
     ph["mat"] = np.broadcast_to(mat[:, None, None], ph["rho"].shape).copy()
     return dict(W.workload("hetero_mm_64"), phantom=ph, sources=[W.pencil(0, 1.0, (50.0, 50.0, 0.0), 4000)])
@@ -62,11 +62,12 @@ def layered():
 
 def ct_case():
     """A CT-like volume through a calibration (density by linear
-    interpolation, bone at and above 300 HU), converted here with numpy so
-    that the oracle's input does not come from the library."""
+    interpolation, bone at and above 300 HU, lung below -400 HU), converted
+    here with numpy so that the oracle's input does not come from the
+    library."""
     hu = W.ct_hu_volume(32)
     rho = np.interp(hu.astype(np.float64), [-1000.0, -700.0, 0.0, 100.0, 1500.0], [0.0012, 0.3, 1.0, 1.07, 1.9])
-    mat = (hu >= 300).astype(np.uint8)
+    mat = np.where(hu >= 300, 1, np.where(hu < -400, 2, 0)).astype(np.uint8)
     ph = dict(shape=hu.shape, voxel=(0.5, 0.5, 0.5), origin=(0.0, 0.0, 0.0), rho=rho, mat=mat)
     return dict(W.workload("hetero_mm_64"), phantom=ph, sources=[W.rect_field(0, 6.0, (8.0, 8.0, 0.0), (6.0, 6.0), 3000)])
 
@@ -133,6 +134,9 @@ def test_several_materials_mixed_precision_and_refusals():
     with pytest.raises(mcx.MCXError, match="STATE"):
         sim.run(wl["seed"], 0, 100)  # bone (1) not loaded
     sim.load_material(W.BONE, 1)
+    with pytest.raises(mcx.MCXError, match="STATE"):
+        sim.run(wl["seed"], 0, 100)  # lung (2) not loaded
+    sim.load_material(W.LUNG, 2)
     sim.run(wl["seed"], 0, 100)
     g = sim.dose_backward(np.zeros(sim.shape))  # the replays run on several materials too
     assert g.shape == tuple(sim.shape) and np.all(g == 0.0)

@@ -5,7 +5,8 @@ variance-reduction extension of the main path).
 - forcing multiplies the hard-event rate by F: in a thin slab the number of
   hard bremsstrahlung events per electron is Poisson with mean
   F sigma_br(E0) rho t (E0 barely changes across the slab), while the
-  weighted count keeps the analog mean sigma_br rho t;
+  weighted count keeps the analog mean sigma_br rho t; the same in a bone
+  slab through the several-material path, with bone's sigma_br;
 - forcing leaves every expectation unchanged: the weighted energy balance
   has mean E0 per history, and the depth-dose curve and the escaped energy
   agree with the analog run's within their combined standard errors, at
@@ -35,19 +36,27 @@ def test_unit_forcing_is_the_analog_run():
     assert np.array_equal(a.ledger, b.ledger)
 
 
-def test_forced_bremsstrahlung_rate_in_a_thin_slab():
+@pytest.mark.parametrize("slab", ["water", "bone_several_materials"])
+def test_forced_bremsstrahlung_rate_in_a_thin_slab(slab):
     e0, dz, n, f = 10.0, 0.05, 4000, 25.0
-    ph = W.slab_phantom(1, dz, np.array([1.0]))
+    rho = 1.0 if slab == "water" else 1.85
+    ph = W.slab_phantom(1, dz, np.array([rho]))
     base = W.transport(100.0, 250, flags=O.NO_HARD_ELASTIC | O.NO_HARD_INELASTIC | O.NO_COMPTON | O.NO_PHOTO
                        | O.NO_RAYLEIGH | O.NO_PAIR)
     src = [W.pencil(1, e0, (50.0, 50.0, 0.0), n)]
-    sig = O.Tables(W.WATER, base).eval(EL_BR, e0)
-    mean = sig * 1.0 * dz
+    m = W.WATER if slab == "water" else W.BONE
+    if slab == "water":
+        tables = lambda t: O.Tables(W.WATER, t)
+    else:
+        ph["mat"] = np.ones(ph["rho"].shape, dtype=np.uint8)
+        tables = lambda t: [O.Tables(W.WATER, t), O.Tables(W.BONE, t), O.Tables(W.LUNG, t)]
+    sig = O.Tables(m, base).eval(EL_BR, e0)
+    mean = sig * rho * dz
     assert 1e-3 < mean < 0.1
-    a = O.run(O.Tables(W.WATER, base), ph, src, 2, 0, n, ledger=True)
+    a = O.run(tables(base), ph, src, 2, 0, n, ledger=True)
     tf = dict(base, force_br=f)
-    assert O.Tables(W.WATER, tf).eval(EL_BR, e0) == pytest.approx(f * sig, rel=1e-14)
-    b = O.run(O.Tables(W.WATER, tf), ph, src, 2, 0, n, ledger=True)
+    assert O.Tables(m, tf).eval(EL_BR, e0) == pytest.approx(f * sig, rel=1e-14)
+    b = O.run(tables(tf), ph, src, 2, 0, n, ledger=True)
     # the step's energy falls by at most a few per cent over 0.05 cm: allow 5 sd plus 3 %
     for st, m in ((a.stats, mean * n), (b.stats, f * mean * n)):
         assert abs(st.hard_br - m) <= 5 * np.sqrt(m) + 0.03 * m, (st.hard_br, m)

@@ -50,6 +50,20 @@ BONE = dict(
 )
 
 
+# Synthetic lung-tissue-like material (model parameters, not data): per
+# formula unit 10 electrons and 18.2 g/mol (Z/A = 0.549), Z(Z+1) sum for an
+# effective Z of 7.6 (its small fractions of P, S, Cl, K raise it above
+# water's), I = 75.3 eV; photoelectric coefficient raised by (7.6/7.42)^3,
+# pair and bremsstrahlung coefficients by 7.6/7.42.
+LUNG = dict(
+    z_mol=10.0, a_mol=18.2, zz1_mol=80.0, z_screen=7.6, i_exc=75.3e-6,
+    pe_coef=5.31, pe_eref=0.01, pe_exp=3.0,
+    pp_coef=1.024e-3,
+    ray_f0=10.0, ray_a=4.6,
+    brems_b=0.0164,
+)
+
+
 def transport(e_max: float = 10.0, n_grid: int = 200, flags: int = 0, **kw) -> dict:
     t = dict(n_grid=n_grid, e_min=1.0e-3, e_max=e_max, eabs=(0.01, 0.1, 0.1),
              c1=0.05, c2=0.05, wcc=0.01, wcr=0.01, flags=flags)
@@ -116,9 +130,13 @@ def hetero_phantom(n: int, size: float = 25.6, seed: int = 2) -> dict:
 
 def hetero_mm_phantom(n: int, size: float = 25.6, seed: int = 2) -> dict:
     """The heterogeneous phantom with materials: water (0) for the
-    background and the lung slab, bone (1) for the spheres."""
+    background, bone (1) for the spheres, lung (2) for the slab outside
+    them."""
     ph = hetero_phantom(n, size, seed)
-    ph["mat"] = (ph["rho"] == 1.85).astype(np.uint8)
+    mat = np.zeros(ph["rho"].shape, dtype=np.uint8)
+    mat[ph["rho"] == 1.85] = 1
+    mat[ph["rho"] == 0.26] = 2
+    ph["mat"] = mat
     return ph
 
 
@@ -216,7 +234,7 @@ def workload(name: str, n_hist: int | None = None) -> dict:
         n = n_hist or 10_000_000
         return dict(name=name, phantom=hetero_mm_phantom(nn),
                     sources=[rect_field(0, 6.0, (12.8, 12.8, 0.0), (10.0, 10.0), n)],
-                    transport=transport(10.0, 200), seed=1, material=WATER, materials=[WATER, BONE])
+                    transport=transport(10.0, 200), seed=1, material=WATER, materials=[WATER, BONE, LUNG])
     if name == "target_detector":
         # 2 MeV electrons stopped in a 1.5 cm water target, a 10 cm air gap,
         # a 2 cm water detector that only bremsstrahlung photons reach
