@@ -380,3 +380,51 @@ def test_full_size_sampled_histories():
     g32 = gpu_run(wl, n, precision=1, launch=launch)
     check_balance(g32["led"], 6.0, 2e-5)
     assert g32["stats"]["histories"] == n
+
+
+def _sampled_parity(wl, g, n, e0_of, k=200, seed=13):
+    """k histories drawn over [0, n) re-run one by one by the oracle: >= 99%
+    identical event sequences, ledgers of those within 1e-8 MeV."""
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(n, size=k, replace=False))
+    tb = O.Tables(wl["material"], wl["transport"])
+    same = 0
+    for h in sample:
+        r = O.run(tb, wl["phantom"], wl["sources"], wl["seed"], int(h), 1, hashes=True, ledger=True)
+        if r.hashes[0] == g["hash"][h]:
+            same += 1
+            assert np.allclose(g["led"][h], r.ledger[0][[0, 1, 2]], rtol=0, atol=1e-8), int(h)
+    print("sampled identical hashes", same, "of", len(sample))
+    assert same >= 0.99 * len(sample)
+    bal = g["led"][:, 0] + g["led"][:, 1] + 2 * MC2 * g["led"][:, 2]
+    e0 = e0_of(np.arange(n))
+    assert np.max(np.abs(bal - e0) / e0) <= 1e-12
+    assert g["stats"]["histories"] == n
+
+
+def test_full_size_sampled_histories_electron_pencil():
+    """The 20 MeV electron pencil at full size (1e6 histories, 200^3 voxels of
+    1 mm), FP64, in the launch the benchmark's electron leg uses (the
+    library's default): sampled histories against the oracle one by one, and
+    every history's energy balance."""
+    wl = W.workload("electron_200")
+    n = wl["sources"][0]["n_hist"]
+    assert n == 1_000_000
+    g = gpu_run(wl, n, precision=0)
+    _sampled_parity(wl, g, n, lambda h: np.full(h.shape, 20.0))
+
+
+def test_full_size_sampled_histories_beamlets():
+    """The 512 beamlets at full size (5e7 histories, 4-15 MeV, 256^3 noise
+    phantom), FP64, in the launch the benchmark's autotuner picks (2^26
+    records per queue, blocks of 256, 32 steps per visit): sampled histories
+    (beamlets enter by their history counts) against the oracle one by one,
+    and every history's energy balance against its own beamlet's energy."""
+    wl = W.workload("beamlets_256")
+    counts = np.array([s["n_hist"] for s in wl["sources"]])
+    energies = np.array([s["energy"] for s in wl["sources"]])
+    n = int(counts.sum())
+    assert n == 50_000_000
+    ends = np.cumsum(counts)
+    g = gpu_run(wl, n, precision=0, launch=(1 << 26, 256, 32))
+    _sampled_parity(wl, g, n, lambda h: energies[np.searchsorted(ends, h, side="right")])
