@@ -10,9 +10,10 @@ flights and interactions, Class II electron/positron steps, tally flush);
 inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line with the metric, the mixed-vs-FP64 comparison (speed-up
-and high-dose deviation), the roofline of the dominant kernel (measured live
-with HIP events recorded around each launch on the run's stream) and the
-oracle timed on a bounded sample on the host CPU.
+and high-dose deviation), the roofline of the dominant kernel, the Class II
+step, for the mixed path, the FP64 path and the gradient's replays (each
+measured live with HIP events recorded around each launch on the run's
+stream), and the oracle timed on a bounded sample on the host CPU.
 """
 from __future__ import annotations
 
@@ -105,42 +106,67 @@ def paired_deviation(d_mix: list, d_64: list, frac: float = 0.5) -> dict:
     return out
 
 
-def roofline(st: dict) -> dict:
-    """Roofline of the dominant kernel (k_estep, the mixed Class II step) over
-    the timed launches.  The step is bound by VALU issue: `achieved` is the
-    VALU wave-instructions per e+- step counted by the hardware counters for
-    this kernel source, times the steps of a launch (counted live), over the
-    launch time measured with HIP events.  The HBM view beside it uses the
-    algorithmic bytes and the counted traffic."""
+def load_counters():
+    """The counters file, if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as fh:
+        prof = json.load(fh)
+    return prof if prof.get("kernel_source_digest") == kernel_source_digest() else None
+
+
+def roofline(st: dict, fp64: bool = False) -> dict:
+    """Roofline of the Class II step kernel k_estep (the dominant kernel) over
+    the timed launches, mixed (FP32 physics) or FP64.  The step is bound by
+    VALU issue: `achieved` is the VALU wave-instructions per e+- step counted
+    by the hardware counters for this kernel source, times the steps of a
+    launch (counted live), over the launch time measured with HIP events.
+    The HBM view beside it uses the algorithmic bytes and the counted
+    traffic."""
     launches = st["timed_iterations"]
     if not launches:
         return None
     avg_s = st["ms_estep"] / launches * 1e-3
     esteps = st["esteps"] / launches
-    alg = estep_algorithmic_bytes(st, fp64=False) / launches
+    alg = estep_algorithmic_bytes(st, fp64=fp64) / launches
     hbm = {"algorithmic_bytes_per_launch": alg, "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS}
-    prof = None
-    if os.path.exists(COUNTERS):
-        with open(COUNTERS) as fh:
-            prof = json.load(fh)
-        if prof.get("kernel_source_digest") != kernel_source_digest():
-            prof = None
-    out = {"kernel": "k_estep<float>", "avg_launch_ms": avg_s * 1e3, "launches": launches, "esteps_per_launch": esteps}
+    prof = load_counters()
+    out = {"kernel": "k_estep<double>" if fp64 else "k_estep<float>", "avg_launch_ms": avg_s * 1e3,
+           "launches": launches, "esteps_per_launch": esteps}
     if prof is None:  # counters taken on another kernel source: the HBM view alone
         out.update(bound="hbm", achieved=hbm["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm["frac"],
                    traffic=None)
         return out
-    wi = prof["valu_wave_instr_per_estep"] * esteps
-    traffic = prof["hbm_bytes_per_estep"] * esteps
+    kp = prof["fp64_k_estep"] if fp64 else prof
+    wi = kp["valu_wave_instr_per_estep"] * esteps
+    traffic = kp["hbm_bytes_per_estep"] * esteps
     hbm["traffic_GBs"] = traffic / avg_s / 1e9
     out.update(bound="alu", achieved=wi / avg_s / 1e9, peak=VALU_ISSUE_PEAK, unit="G VALU wave-instr/s",
                frac=wi / avg_s / 1e9 / VALU_ISSUE_PEAK, traffic=traffic,
-               valu_wave_instr_per_estep=prof["valu_wave_instr_per_estep"],
-               valu_lane_utilisation=prof["valu_lane_utilisation"], hbm=hbm,
-               valu_lane_utilisation_per_kernel={k: v["lane_utilisation"] for k, v in
-                                                 prof.get("valu_lane_utilisation_per_kernel", {}).items()})
+               valu_wave_instr_per_estep=kp["valu_wave_instr_per_estep"],
+               valu_lane_utilisation=kp["valu_lane_utilisation"], hbm=hbm)
+    if not fp64:
+        out["valu_lane_utilisation_per_kernel"] = {k: v["lane_utilisation"] for k, v in
+                                                   prof.get("valu_lane_utilisation_per_kernel", {}).items()}
     return out
+
+
+def replay_roofline(ms_estep: float, launches: int, esteps_forward: int) -> dict:
+    """Roofline of the gradient's two replays of k_estep (FP64): the VALU
+    wave-instructions the counters give per forward e+- step for replay A and
+    for replay B (look-ahead and pass), times the forward steps, over the
+    replays' k_estep time measured with HIP events."""
+    prof = load_counters()
+    if prof is None or not launches or not ms_estep > 0.0:
+        return None
+    rp = prof["gradient_replays"]
+    per_step = sum(v["valu_wave_instr_per_forward_step"] for k, v in rp.items() if k.startswith("replay"))
+    achieved = per_step * esteps_forward / (ms_estep * 1e-3) / 1e9
+    return {"kernel": "k_estep<double> replays A + B", "bound": "alu", "k_estep_ms": ms_estep,
+            "launches": launches, "valu_wave_instr_per_forward_step": per_step, "achieved": achieved,
+            "peak": VALU_ISSUE_PEAK, "unit": "G VALU wave-instr/s", "frac": achieved / VALU_ISSUE_PEAK,
+            "valu_lane_utilisation": {k: v["valu_lane_utilisation"] for k, v in rp.items()}}
 
 
 def target_detector_efficiency(mcx, W, sync, args, n: int = 1_000_000) -> dict:
@@ -209,21 +235,28 @@ def gradient_timing(mcx, W, sync, n: int = 10_000_000) -> dict:
     sim.run(777, 0, min(n, 200_000))  # warm-up
     sim.dose_backward(np.zeros(wl["phantom"]["shape"]))
     sim.reset()
+    sim.set_timing(True)  # per-kernel HIP events (the launches are not graph-replayed)
     sync()
     t0 = time.perf_counter()
     sim.run(1, 0, n)
     d, _ = sim.dose()
     sync()
     t1 = time.perf_counter()
-    esteps = sim.stats()["esteps"]
+    st0 = sim.stats()
     target = smooth_target(d)
     g = sim.dose_backward(2.0 * (d - target))
     sync()
     t2 = time.perf_counter()
+    st1 = sim.stats()  # the forward run's statistics; the kernel times add up over the replays
     sim.close()
+    esteps = st0["esteps"]
     return dict(workload="hetero_broad_64: 6 MeV 10x10 field, 64^3 x 4 mm, FP64", histories=n,
                 forward_s=t1 - t0, backward_s=t2 - t1, fwd_bwd_s=t2 - t0, grad_abs_max=float(np.abs(g).max()),
-                esteps_forward=esteps, target=target)
+                esteps_forward=esteps, forward_k_estep_ms=st0["ms_estep"],
+                replay_k_estep_ms=st1["ms_estep"] - st0["ms_estep"],
+                roofline=replay_roofline(st1["ms_estep"] - st0["ms_estep"],
+                                         st1["timed_iterations"] - st0["timed_iterations"], esteps),
+                target=target)
 
 
 def gradient_fd_check(mcx, W, sync, target, n_batch: int = 1_000_000, batches: int = 10, n_vox: int = 16,
@@ -550,13 +583,14 @@ def main():
         f64 = mcx.Simulator(mcx.FP64, 0).setup(wl)
         f64.set_launch(args.bank, 256, 128)
         run_steps(f64, n, warm_seeds, sync)
+        f64.set_timing(True)
         doses_64 = []
         t_64 = run_steps(f64, n, seeds, sync, doses_64)
         d_64, _ = f64.dose()
         st_64 = f64.stats()
         f64.close()
         result_64 = dict(value=n * len(t_64) / sum(t_64), ms_per_step=1e3 * sum(t_64) / len(t_64),
-                         esteps_per_history=st_64["esteps"] / n)
+                         esteps_per_history=st_64["esteps"] / n, roofline=roofline(st_64, fp64=True))
         dev = high_dose_deviation(d_mix, d_64)
         # the timed steps as paired batches: systematic part and noise floor
         dev["paired_batches"] = paired_deviation(doses_mix, doses_64)
