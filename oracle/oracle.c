@@ -1100,16 +1100,24 @@ static void e_escape(ctx* c, part* p, int64_t v) {
   finish(c, p);
 }
 
+/* Moller energy transfer k in [kc, 1/2] from the bracket over k^2.  With
+ * r = k/(1-k), k^2 times the bracket is f(k) = 1 + r^2 - (1-a) r + a k^2,
+ * and f(k) <= 1 + 5 a k^2 on (0, 1/2] (the difference r^2 - r + a (r - 4k^2)
+ * is linear in a and <= 0 at a = 0 and a = 1 because r <= 1 and
+ * r <= 2k there; equality at k = 1/2).  The proposal is therefore
+ * (1 + 5 a k^2)/k^2 = 1/k^2 + 5a, a mixture of 1/k^2 (weight 1/kc - 2,
+ * sampled by inversion) and a uniform part (weight 5a (1/2 - kc)); one
+ * uniform picks the part and, rescaled, samples it; the acceptance is
+ * f(k)/(1 + 5 a k^2), above 0.97 from 1 MeV up */
 static double sample_moller(stream* s, double e, double wcc) {
   double kc = wcc / e;
   inel_coef cf = inel_coefficients(e);
+  double w1 = 1.0 / kc - 2.0, w2 = 5.0 * cf.a * (0.5 - kc);
   for (;;) {
-    double u = draw(s), ua = draw(s);
-    double k = kc / (1.0 - u * (1.0 - 2.0 * kc));
-    /* k^2 times the bracket 1/k^2 + 1/(1-k)^2 + a - (1-a)/(k(1-k)), written
-     * with r = k/(1-k); it rises to its maximum 1 + 5a/4 at k = 1/2 */
+    double u = draw(s) * (w1 + w2), ua = draw(s);
+    double k = u < w1 ? kc / (1.0 - (u / w1) * (1.0 - 2.0 * kc)) : kc + (u - w1) / w2 * (0.5 - kc);
     double r = k / (1.0 - k);
-    if (ua * (1.0 + 1.25 * cf.a) <= 1.0 + r * r + cf.a * k * k - (1.0 - cf.a) * r) return k;
+    if (ua * (1.0 + 5.0 * cf.a * k * k) <= 1.0 + r * r + cf.a * k * k - (1.0 - cf.a) * r) return k;
   }
 }
 

@@ -89,6 +89,33 @@ def test_moller(tb, e):
     assert chi2_pvalue(k, lambda x: _moller(x, g), kc, 0.5, edges=edges) > 1e-4
 
 
+@pytest.mark.parametrize("e", [0.3, 15.0])
+def test_moller_upper_half(tb, e):
+    """The share of Moller transfers with k > 1/4 (where the bracket over k^2
+    is largest relative to 1/k^2) against the DCS integrated by quadrature:
+    a proposal that dropped or mis-weighted its flat part, or an acceptance
+    bound that the bracket exceeds, moves this share by tens of percent."""
+    from scipy.integrate import quad
+    n = 1_000_000
+    k, _ = tb.sample("moller", e, n, seed=11)
+    kc = 0.01 / e
+    g = 1 + e / MC2
+    tot = quad(lambda x: _moller(x, g), kc, 0.5, limit=200, points=[2 * kc, 10 * kc])[0]
+    upper = quad(lambda x: _moller(x, g), 0.25, 0.5)[0] / tot
+    m = np.count_nonzero(k > 0.25)
+    assert abs(m - n * upper) < 5.0 * np.sqrt(n * upper * (1 - upper)) + 1.0
+
+
+def test_moller_envelope_bound():
+    """k^2 times the Moller bracket stays below 1 + 5 a k^2 on (0, 1/2], with
+    equality at 1/2, for every a in [0, 1] (the sampler's acceptance bound)."""
+    kk = np.linspace(1e-4, 0.5, 20001)
+    for a in np.linspace(0.0, 1.0, 41):
+        f = kk**2 * (1 / kk**2 + 1 / (1 - kk) ** 2 + a - (1 - a) / (kk * (1 - kk)))
+        assert np.all(f <= 1 + 5 * a * kk**2 + 1e-12)
+        assert abs(f[-1] - (1 + 1.25 * a)) < 1e-12
+
+
 @pytest.mark.parametrize("e", [0.08, 1.0, 15.0])
 def test_bhabha(tb, e):
     k, _ = tb.sample("bhabha", e, N)
