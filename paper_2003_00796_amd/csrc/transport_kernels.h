@@ -1111,17 +1111,22 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
       b4 = aa * (gm - T(1)) * (gm - T(1)) / (gp * gp);
     }
     const T span = lep == 0 ? T(1) - T(2) * kc : T(1) - kc;
+    // e-: k^2 times the bracket, f = 1 + r^2 + a k^2 - (1 - a) r with
+    // r = k/(1-k), is at most 1 + 5 a k^2 on (0, 1/2]: the proposal is
+    // 1/k^2 (weight w1 = 1/kc - 2, by inversion) plus a flat part (weight
+    // w2 = 5a (1/2 - kc)), one uniform choosing the part and sampling it
+    const T w1 = T(1) / kc - T(2), w2 = T(5) * aa * (T(0.5) - kc);
+    const T wt = lep == 0 ? w1 + w2 : T(1);
     T k = kc;
     for (int tries = 0; tries < kMaxTries; ++tries) {
-      const T uu = uni<T>(p.rng), ua = uni<T>(p.rng);
-      k = kc / (T(1) - uu * span);
+      const T uu = uni<T>(p.rng) * wt, ua = uni<T>(p.rng);
       bool ok;
       if (lep == 0) {
-        // k^2 times the bracket, 1 + r^2 + a k^2 - (1 - a) r with r = k/(1-k),
-        // is at most its value 1 + 5a/4 at k = 1/2
+        k = uu < w1 ? kc / (T(1) - (uu / w1) * span) : kc + (uu - w1) / w2 * (T(0.5) - kc);
         const T r = k / (T(1) - k);
-        ok = ua * (T(1) + T(1.25) * aa) <= T(1) + r * r + aa * k * k - (T(1) - aa) * r;
+        ok = ua * (T(1) + T(5) * aa * k * k) <= T(1) + r * r + aa * k * k - (T(1) - aa) * r;
       } else {
+        k = kc / (T(1) - uu * span);
         const T gg = T(1) - b1 * k + b2 * k * k - b3 * k * k * k + b4 * k * k * k * k;
         ok = ua <= gg;
       }
@@ -1136,6 +1141,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
     cos_c = leading_angle(beta_of(e1), uni<T>(p.rng));
   }
   const T ph = T(2.0 * kPi) * uni<T>(p.rng);
+  bool turn = kind == 1;
   if (kind != 1) {
     // the secondary leaves from the direction before the event: the knock-on
     // electron on the opposite azimuth, the photon on the drawn one
@@ -1164,10 +1170,7 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
       if (!DRY) rotate(d2, c2c, ph2);
       fw *= 2.0;
     }
-    if (apply) {
-      if (kind == 2) rotate(p.d, cos_p, ph);
-      p.e = e1 - w;
-    }
+    if (apply) p.e = e1 - w;
     if (!DRY) {
       const double w0 = p.w;
       p.w = w0 / fw;
@@ -1175,9 +1178,11 @@ __device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const 
       if (split) make_child(a, p, c2, PHOTON, w, d2, acc, ls, bs);
       p.w = w0;
     }
-  } else {
-    rotate(p.d, cos_p, ph);
+    turn = kind == 2 && apply;
   }
+  // one rotation of the primary serves the elastic and the inelastic events
+  // (the children above take the direction before the event)
+  if (turn) rotate(p.d, cos_p, ph);
   if (!DRY) event(a, p, kind == 1 ? EV_HARD_EL : (kind == 2 ? EV_HARD_IN : EV_HARD_BR), v);
   return true;
 }
