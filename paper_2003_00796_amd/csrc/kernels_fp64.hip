@@ -1,6 +1,12 @@
 // kernels_fp64.hip -- FP64 instantiation of the transport kernels.  Built with
 // -ffp-contract=off: no multiply-add fusion, so the arithmetic follows the
 // order of the source expressions.
+// the FP64 step kernel needs up to 256 registers: bound it to 2 waves per
+// SIMD, so that no flavour's register count (with the accumulation registers
+// it may borrow) drops it to one
+#ifndef MCX_ESTEP_WAVES
+#define MCX_ESTEP_WAVES 2
+#endif
 #include <algorithm>
 
 #include "transport_kernels.h"

@@ -861,7 +861,7 @@ __device__ __forceinline__ double soft_score(double A, double mu, double mbar, d
 // with `look` set it moves the particle without any other effect (no deposit,
 // secondary, statistic or event): the look-ahead pass of the second replay.
 template <typename T, bool EXT, int G = 0>
-__device__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const T* soft, Part<T>& p, Child<T>& c1,
+__device__ __forceinline__ bool e_step(const KArgs<T>& a, const Tab<T>& tb, const T* tab, const T* soft, Part<T>& p, Child<T>& c1,
                        Child<T>& c2, DepAcc& acc, LaneStats& ls, BlockStats* bs, EGrad& eg, bool look = false) {
   const bool DRY = G != 0 && look;
   const int nt = tb.n;
