@@ -25,7 +25,7 @@ static hipError_t launch_flavor(const KArgs<double>& a, int par, uint32_t target
   constexpr int PF = photon_flavor(F);
   hipLaunchKernelGGL((k_flight<double, PF>), dim3(grid), dim3(block), several(F) ? sm_f * size_t(a.tb.nmat) : sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL((k_knock<double, PF>), dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_knock<double, PF>), dim3(grid), dim3(block), several(F) ? sm_f * size_t(a.tb.nmat) : sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[3], s);
   hipLaunchKernelGGL((k_estep<double, F>), dim3(grid), dim3(block), several(F) ? size_t(kSoftN) * sizeof(double) : sm_e, s,
                      a, par);

@@ -27,7 +27,7 @@ static hipError_t launch_flavor(const KArgs<float>& a, int par, uint32_t target,
   constexpr int PF = photon_flavor(F);
   hipLaunchKernelGGL((k_flight<float, PF>), dim3(grid), dim3(block), several(F) ? sm_f * size_t(a.tb.nmat) : sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL((k_knock<float, PF>), dim3(grid), dim3(block), 0, s, a, par);
+  hipLaunchKernelGGL((k_knock<float, PF>), dim3(grid), dim3(block), several(F) ? sm_f * size_t(a.tb.nmat) : sm_f, s, a, par);
   if (ev) (void)hipEventRecord(ev[3], s);
   hipLaunchKernelGGL((k_estep<float, F>), dim3(grid), dim3(block), several(F) ? size_t(kSoftN) * sizeof(float) : sm_e, s,
                      a, par);

@@ -12,6 +12,11 @@
 #ifndef MCX_ESTEP_WAVES
 #define MCX_ESTEP_WAVES 1
 #endif
+// photons waiting for an interaction at or below which the interaction
+// kernel follows each photon to its end (see k_knock)
+#ifndef MCX_CHAIN_PHOTONS
+#define MCX_CHAIN_PHOTONS 131072
+#endif
 // tail of the e+- kernel: once the input queue is empty, a wavefront keeps
 // stepping its particles for at least MCX_TAIL_MIN more steps, then writes
 // them all back as soon as fewer than MCX_TAIL_ALIVE of its lanes hold one
@@ -295,6 +300,282 @@ __global__ void k_cube_pass(const uint8_t* in, uint8_t* out, int nx, int ny, int
 #ifndef MCX_FLIGHT_WAVES
 #define MCX_FLIGHT_WAVES 1
 #endif
+// One photon flight (JUMP and STEP through the voxels): from the photon's
+// position to its next interaction, whose channel it returns (0 Compton,
+// 1 photoabsorption, 2 Rayleigh, 3 pair production), or out of the phantom
+// (-1: the escape is recorded and the photon's history record finished).  In
+// the second gradient replay it also scores the flight's density derivatives.
+// `tab` holds the photon channels in LDS (of every material with several).
+template <typename T, int F>
+__device__ __forceinline__ int photon_flight(const KArgs<T>& a, const T* tab, Part<T>& p, LaneStats& ls,
+                                             BlockStats* bs) {
+  constexpr bool MMF = several(F);
+  const int nt = a.tb.n;
+  int ch = -1;
+  const T e = p.e;
+  const Grid<T> g = grid_at(a.tb, M<T>::log(e));
+  T mu[4];
+  T mt = T(0);
+  // several materials: the attenuation rho mu_m(E) of each voxel's
+  // material; the flight is measured in optical depth
+  T mtm[kMaxMat];
+  if constexpr (MMF) {
+#pragma unroll
+    for (int m = 0; m < kMaxMat; ++m) {
+      const T* tm = tab + m * T_PHOTON_END * nt;
+      mtm[m] = m < a.tb.nmat ? interp(tm, nt, T_LMU_C, g, e, T(0)) + interp(tm, nt, T_LMU_PE, g, e, T(0)) +
+                                   interp(tm, nt, T_LMU_R, g, e, T(0)) +
+                                   interp(tm, nt, T_LMU_PP, g, e, a.tb.thr_pp)
+                             : T(0);
+    }
+  } else {
+    mu[0] = interp(tab, nt, T_LMU_C, g, e, T(0));
+    mu[1] = interp(tab, nt, T_LMU_PE, g, e, T(0));
+    mu[2] = interp(tab, nt, T_LMU_R, g, e, T(0));
+    mu[3] = interp(tab, nt, T_LMU_PP, g, e, a.tb.thr_pp);
+    mt = mu[0] + mu[1] + mu[2] + mu[3];
+  }
+  // replay B: mu of voxel vv's material (several materials), else mu
+  auto mu_of = [&](uint32_t vv) -> double {
+    if constexpr (MMF) {
+      const uint32_t m = a.mat[vv];
+      return double(m == 0u ? mtm[0] : (m == 1u ? mtm[1] : (m == 2u ? mtm[2] : mtm[3])));
+    } else {
+      return double(mt);
+    }
+  };
+  auto att = [&](uint32_t vv) -> double {
+    if constexpr (MMF) {
+      const uint32_t m = a.mat[vv];
+      const T mm = m == 0u ? mtm[0] : (m == 1u ? mtm[1] : (m == 2u ? mtm[2] : mtm[3]));
+      return double(a.rho[vv]) * double(mm);
+    } else {
+      return double(a.rho[vv]);
+    }
+  };
+  ls.flights++;
+  double tau = MMF ? double(-M<T>::log(uni<T>(p.rng))) : double(-M<T>::log(uni<T>(p.rng)) / mt);
+  // incremental DDA: tn[k] = distance along the ray to the next face
+  // normal to axis k, advanced by the voxel pitch over |d_k| per crossing
+  const double o[3] = {a.ox, a.oy, a.oz};
+  const double dd[3] = {a.dx, a.dy, a.dz};
+  const int nn[3] = {a.nx, a.ny, a.nz};
+  double tn[3], dt[3];
+  int stp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dk = double(p.d[k]);
+    if (dk > 0.0) {
+      stp[k] = 1;
+      tn[k] = (o[k] + double(p.ix[k] + 1) * dd[k] - p.x[k]) / dk;
+      dt[k] = dd[k] / dk;
+    } else if (dk < 0.0) {
+      stp[k] = -1;
+      tn[k] = (o[k] + double(p.ix[k]) * dd[k] - p.x[k]) / dk;
+      dt[k] = -dd[k] / dk;
+    } else {
+      stp[k] = 0;
+      tn[k] = __builtin_huge_val();
+      dt[k] = 0.0;
+    }
+    if (tn[k] < 0.0) tn[k] = 0.0;
+  }
+  if (!(tn[0] < __builtin_huge_val()) && !(tn[1] < __builtin_huge_val()) &&
+      !(tn[2] < __builtin_huge_val())) {
+    atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
+    tau = 0.0;
+  }
+  double t = 0.0;
+  bool escaped = false;
+  uint32_t v = vlin(a, p.ix);
+  double t0 = tn[0], t1 = tn[1], t2 = tn[2];
+  // faces per unit length along each axis (|d_k| / pitch), for counting
+  // the faces a cube crossing passes
+  const double it[3] = {fabs(double(p.d[0])) * a.idx, fabs(double(p.d[1])) * a.idy, fabs(double(p.d[2])) * a.idz};
+  double rho_v = att(v);
+  uint32_t cube_v = a.cube[v];
+  // replay B: the history's centred weighted score times d ln p / d rho_j
+  // of this free flight (-mu l_j per voxel, +1/rho at the interaction)
+  const double cq = a.mode == 2 ? a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar : 0.0;
+  const double mud = double(mt);
+  // The walk runs kWalk voxels ahead of the mass-thickness sum: the
+  // geometry of the next kWalk segments needs no density, so their
+  // densities are requested together and their latencies overlap.
+  bool ended = false;
+  uint32_t esc_v = v;
+  while (!ended) {
+    if (cube_v >= kCubeMin) {
+      // one step to the first of: the interaction, were the cube's density
+      // to continue, and the cube's boundary; it crosses every face strictly
+      // before that point (at most cube_v per axis, all inside the cube) and
+      // leaves the decision at the point to the walk below
+      const double r = double(cube_v);
+      const double te = fmin(fmin(t0 + r * dt[0], t1 + r * dt[1]), t2 + r * dt[2]);
+      const double tt = fmin(te, t + tau / rho_v);
+      const int lim = int(cube_v);
+      const int n0 = tt > t0 ? min(lim, int(ceil((tt - t0) * it[0]))) : 0;
+      const int n1 = tt > t1 ? min(lim, int(ceil((tt - t1) * it[1]))) : 0;
+      const int n2 = tt > t2 ? min(lim, int(ceil((tt - t2) * it[2]))) : 0;
+      if (n0 + n1 + n2 > 0) {
+        double tl = t;  // the last face crossed
+        if (n0 > 0) tl = fmax(tl, t0 + double(n0 - 1) * dt[0]);
+        if (n1 > 0) tl = fmax(tl, t1 + double(n1 - 1) * dt[1]);
+        if (n2 > 0) tl = fmax(tl, t2 + double(n2 - 1) * dt[2]);
+        if (cq != 0.0) {
+          // replay B: the same faces one by one, for each voxel's length
+          double u0 = t0, u1 = t1, u2 = t2, tc = t;
+          int m0 = n0, m1 = n1, m2 = n2;
+          int jx[3] = {p.ix[0], p.ix[1], p.ix[2]};
+          for (int left = n0 + n1 + n2; left > 0; --left) {
+            // next face among the axes with faces left; ties in x, y, z order
+            const bool a0 = m0 > 0 && (m1 <= 0 || u0 <= u1) && (m2 <= 0 || u0 <= u2);
+            const bool a1 = !a0 && m1 > 0 && (m2 <= 0 || u1 <= u2);
+            const bool a2 = !a0 && !a1;
+            const double uk = a0 ? u0 : (a1 ? u1 : u2);
+            unsafeAtomicAdd(&a.adj_grad[vlin(a, jx)], cq * (-(MMF ? mu_of(v) : mud) * (uk - tc)));
+            tc = uk;
+            u0 = a0 ? u0 + dt[0] : u0;
+            u1 = a1 ? u1 + dt[1] : u1;
+            u2 = a2 ? u2 + dt[2] : u2;
+            jx[0] += a0 ? stp[0] : 0;
+            jx[1] += a1 ? stp[1] : 0;
+            jx[2] += a2 ? stp[2] : 0;
+            m0 -= a0 ? 1 : 0;
+            m1 -= a1 ? 1 : 0;
+            m2 -= a2 ? 1 : 0;
+          }
+        }
+        tau = fmax(tau - rho_v * (tl - t), 0.0);
+        t = tl;
+        p.ix[0] += stp[0] * n0;
+        p.ix[1] += stp[1] * n1;
+        p.ix[2] += stp[2] * n2;
+        t0 += double(n0) * dt[0];
+        t1 += double(n1) * dt[1];
+        t2 += double(n2) * dt[2];
+        ls.crossings += uint32_t(n0 + n1 + n2);
+        v = vlin(a, p.ix);
+      }
+    }
+    // branch-free: the lanes of a wavefront walk different axes
+    double seg[kWalk], tend[kWalk];
+    uint32_t vs[kWalk + 1];
+    int axs[kWalk];
+    bool outs[kWalk];
+    {
+      double u0 = t0, u1 = t1, u2 = t2, tc = t;
+      int j0 = p.ix[0], j1 = p.ix[1], j2 = p.ix[2];
+      uint32_t vc = v;
+      bool gone = false;  // an earlier segment of this batch leaves the phantom
+#pragma unroll
+      for (int j = 0; j < kWalk; ++j) {
+        const bool a0 = (u0 <= u1) & (u0 <= u2);
+        const bool a1 = !a0 & (u1 <= u2);
+        const bool a2 = !a0 & !a1;
+        const double tf = a0 ? u0 : (a1 ? u1 : u2);
+        seg[j] = tf - tc;
+        tend[j] = tf;
+        vs[j] = vc;
+        axs[j] = a0 ? 0 : (a1 ? 1 : 2);
+        j0 += a0 ? stp[0] : 0;
+        j1 += a1 ? stp[1] : 0;
+        j2 += a2 ? stp[2] : 0;
+        u0 = a0 ? u0 + dt[0] : u0;
+        u1 = a1 ? u1 + dt[1] : u1;
+        u2 = a2 ? u2 + dt[2] : u2;
+        const bool out = (j0 < 0) | (j0 >= nn[0]) | (j1 < 0) | (j1 >= nn[1]) | (j2 < 0) | (j2 >= nn[2]);
+        outs[j] = out;
+        gone = gone | out;
+        const int jx[3] = {j0, j1, j2};
+        vc = gone ? vc : vlin(a, jx);
+        tc = tf;
+      }
+      vs[kWalk] = vc;
+    }
+    double rr[kWalk];
+#pragma unroll
+    for (int j = 0; j < kWalk; ++j) rr[j] = att(vs[j]);
+    // the voxel after the last segment: where the next pass starts
+    const double rho_n = att(vs[kWalk]);
+    const uint32_t cube_n = a.cube[vs[kWalk]];
+#pragma unroll
+    for (int j = 0; j < kWalk; ++j) {
+      const double rho = rr[j], sj = seg[j];
+      const bool act = !ended;
+      const bool hit = act & (rho * sj >= tau);
+      const bool pass = act & !hit;
+      if (cq != 0.0 && act) {
+        // several materials: rho here is rho mu_m, tau an optical depth
+        const double muj = MMF ? mu_of(vs[j]) : mud;
+        const double rj = MMF ? double(a.rho[vs[j]]) : rho;
+        unsafeAtomicAdd(&a.adj_grad[vs[j]], hit ? cq * (-muj * (tau / rho) + 1.0 / rj) : cq * (-muj * sj));
+      }
+      t = hit ? t + tau / rho : (pass ? tend[j] : t);
+      tau = pass ? tau - rho * sj : tau;
+      p.ix[0] += (pass & (axs[j] == 0)) ? stp[0] : 0;
+      p.ix[1] += (pass & (axs[j] == 1)) ? stp[1] : 0;
+      p.ix[2] += (pass & (axs[j] == 2)) ? stp[2] : 0;
+      t0 = (pass & (axs[j] == 0)) ? t0 + dt[0] : t0;
+      t1 = (pass & (axs[j] == 1)) ? t1 + dt[1] : t1;
+      t2 = (pass & (axs[j] == 2)) ? t2 + dt[2] : t2;
+      ls.crossings += pass ? 1u : 0u;
+      const bool esc = pass & outs[j];
+      esc_v = esc ? vs[j] : esc_v;
+      escaped = escaped | esc;
+      v = (pass & !outs[j]) ? vs[j + 1] : v;
+      ended = ended | hit | esc;
+    }
+    rho_v = rho_n;
+    cube_v = cube_n;
+  }
+  if (escaped) {
+    ledger_escape(a, bs, p);
+    event(a, p, EV_PH_ESCAPE, esc_v);
+    finish(a, p);
+  }
+  move(p, t);
+  if (!escaped) {
+    if constexpr (MMF) {
+      // the interaction by the tables of the voxel the photon stops in
+      const T* tm = tab + int(a.mat[v]) * T_PHOTON_END * nt;
+      mu[0] = interp(tm, nt, T_LMU_C, g, e, T(0));
+      mu[1] = interp(tm, nt, T_LMU_PE, g, e, T(0));
+      mu[2] = interp(tm, nt, T_LMU_R, g, e, T(0));
+      mu[3] = interp(tm, nt, T_LMU_PP, g, e, a.tb.thr_pp);
+      mt = mu[0] + mu[1] + mu[2] + mu[3];
+    }
+    const T u = uni<T>(p.rng) * mt;
+    T cum = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cum += mu[k];
+      if (ch < 0 && u < cum) ch = k;
+    }
+    if (ch < 0) {
+#pragma unroll
+      for (int k = 3; k >= 0; --k)
+        if (ch < 0 && mu[k] > T(0)) ch = k;
+    }
+  }
+  return ch;
+}
+
+// the photon channels into LDS: those of every material with several
+template <typename T, int F>
+__device__ __forceinline__ void stage_photon(const KArgs<T>& a, T* tab) {
+  const int nt = a.tb.n;
+  if constexpr (several(F)) {
+    // the photon channels of every material, T_PHOTON_END x n each
+    const int per = T_PHOTON_END * nt;
+    for (int k = threadIdx.x; k < per * a.tb.nmat; k += blockDim.x) {
+      const int m = k / per;
+      tab[k] = a.tb.t[mat_block(m, nt) + uint32_t(k - m * per)];
+    }
+  } else {
+    stage(a.tb, tab, T_PHOTON_END);
+  }
+}
+
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T> a, int par) {
   set_flavor<F>(a);
@@ -307,18 +588,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
   __shared__ BlockStats bs;
   LaneStats ls;
   stats_init(&bs, ls);
-  constexpr bool MMF = several(F);
-  const int nt = a.tb.n;
-  if constexpr (MMF) {
-    // the photon channels of every material, T_PHOTON_END x n each
-    const int per = T_PHOTON_END * nt;
-    for (int k = threadIdx.x; k < per * a.tb.nmat; k += blockDim.x) {
-      const int m = k / per;
-      tab[k] = a.tb.t[mat_block(m, nt) + uint32_t(k - m * per)];
-    }
-  } else {
-    stage(a.tb, tab, T_PHOTON_END);
-  }
+  stage_photon<T, F>(a, tab);
   __syncthreads();
   const Bank<T>& in = a.q[q_gin(par)];
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -328,251 +598,7 @@ __global__ __launch_bounds__(kMaxBlock, MCX_FLIGHT_WAVES) void k_flight(KArgs<T>
     Part<T> p;
     if (i < n) {
       load_part(a, in, striped_record(sums, i, cs), p);
-      const T e = p.e;
-      const Grid<T> g = grid_at(a.tb, M<T>::log(e));
-      T mu[4];
-      T mt = T(0);
-      // several materials: the attenuation rho mu_m(E) of each voxel's
-      // material; the flight is measured in optical depth
-      T mtm[kMaxMat];
-      if constexpr (MMF) {
-#pragma unroll
-        for (int m = 0; m < kMaxMat; ++m) {
-          const T* tm = tab + m * T_PHOTON_END * nt;
-          mtm[m] = m < a.tb.nmat ? interp(tm, nt, T_LMU_C, g, e, T(0)) + interp(tm, nt, T_LMU_PE, g, e, T(0)) +
-                                       interp(tm, nt, T_LMU_R, g, e, T(0)) +
-                                       interp(tm, nt, T_LMU_PP, g, e, a.tb.thr_pp)
-                                 : T(0);
-        }
-      } else {
-        mu[0] = interp(tab, nt, T_LMU_C, g, e, T(0));
-        mu[1] = interp(tab, nt, T_LMU_PE, g, e, T(0));
-        mu[2] = interp(tab, nt, T_LMU_R, g, e, T(0));
-        mu[3] = interp(tab, nt, T_LMU_PP, g, e, a.tb.thr_pp);
-        mt = mu[0] + mu[1] + mu[2] + mu[3];
-      }
-      // replay B: mu of voxel vv's material (several materials), else mu
-      auto mu_of = [&](uint32_t vv) -> double {
-        if constexpr (MMF) {
-          const uint32_t m = a.mat[vv];
-          return double(m == 0u ? mtm[0] : (m == 1u ? mtm[1] : (m == 2u ? mtm[2] : mtm[3])));
-        } else {
-          return double(mt);
-        }
-      };
-      auto att = [&](uint32_t vv) -> double {
-        if constexpr (MMF) {
-          const uint32_t m = a.mat[vv];
-          const T mm = m == 0u ? mtm[0] : (m == 1u ? mtm[1] : (m == 2u ? mtm[2] : mtm[3]));
-          return double(a.rho[vv]) * double(mm);
-        } else {
-          return double(a.rho[vv]);
-        }
-      };
-      ls.flights++;
-      double tau = MMF ? double(-M<T>::log(uni<T>(p.rng))) : double(-M<T>::log(uni<T>(p.rng)) / mt);
-      // incremental DDA: tn[k] = distance along the ray to the next face
-      // normal to axis k, advanced by the voxel pitch over |d_k| per crossing
-      const double o[3] = {a.ox, a.oy, a.oz};
-      const double dd[3] = {a.dx, a.dy, a.dz};
-      const int nn[3] = {a.nx, a.ny, a.nz};
-      double tn[3], dt[3];
-      int stp[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double dk = double(p.d[k]);
-        if (dk > 0.0) {
-          stp[k] = 1;
-          tn[k] = (o[k] + double(p.ix[k] + 1) * dd[k] - p.x[k]) / dk;
-          dt[k] = dd[k] / dk;
-        } else if (dk < 0.0) {
-          stp[k] = -1;
-          tn[k] = (o[k] + double(p.ix[k]) * dd[k] - p.x[k]) / dk;
-          dt[k] = -dd[k] / dk;
-        } else {
-          stp[k] = 0;
-          tn[k] = __builtin_huge_val();
-          dt[k] = 0.0;
-        }
-        if (tn[k] < 0.0) tn[k] = 0.0;
-      }
-      if (!(tn[0] < __builtin_huge_val()) && !(tn[1] < __builtin_huge_val()) &&
-          !(tn[2] < __builtin_huge_val())) {
-        atomicOr(&a.cnt->overflow, uint32_t(OVF_LOST));
-        tau = 0.0;
-      }
-      double t = 0.0;
-      bool escaped = false;
-      uint32_t v = vlin(a, p.ix);
-      double t0 = tn[0], t1 = tn[1], t2 = tn[2];
-      // faces per unit length along each axis (|d_k| / pitch), for counting
-      // the faces a cube crossing passes
-      const double it[3] = {fabs(double(p.d[0])) * a.idx, fabs(double(p.d[1])) * a.idy, fabs(double(p.d[2])) * a.idz};
-      double rho_v = att(v);
-      uint32_t cube_v = a.cube[v];
-      // replay B: the history's centred weighted score times d ln p / d rho_j
-      // of this free flight (-mu l_j per voxel, +1/rho at the interaction)
-      const double cq = a.mode == 2 ? a.adj_q[p.hist - a.cnt->run_first] - a.adj_qbar : 0.0;
-      const double mud = double(mt);
-      // The walk runs kWalk voxels ahead of the mass-thickness sum: the
-      // geometry of the next kWalk segments needs no density, so their
-      // densities are requested together and their latencies overlap.
-      bool ended = false;
-      uint32_t esc_v = v;
-      while (!ended) {
-        if (cube_v >= kCubeMin) {
-          // one step to the first of: the interaction, were the cube's density
-          // to continue, and the cube's boundary; it crosses every face strictly
-          // before that point (at most cube_v per axis, all inside the cube) and
-          // leaves the decision at the point to the walk below
-          const double r = double(cube_v);
-          const double te = fmin(fmin(t0 + r * dt[0], t1 + r * dt[1]), t2 + r * dt[2]);
-          const double tt = fmin(te, t + tau / rho_v);
-          const int lim = int(cube_v);
-          const int n0 = tt > t0 ? min(lim, int(ceil((tt - t0) * it[0]))) : 0;
-          const int n1 = tt > t1 ? min(lim, int(ceil((tt - t1) * it[1]))) : 0;
-          const int n2 = tt > t2 ? min(lim, int(ceil((tt - t2) * it[2]))) : 0;
-          if (n0 + n1 + n2 > 0) {
-            double tl = t;  // the last face crossed
-            if (n0 > 0) tl = fmax(tl, t0 + double(n0 - 1) * dt[0]);
-            if (n1 > 0) tl = fmax(tl, t1 + double(n1 - 1) * dt[1]);
-            if (n2 > 0) tl = fmax(tl, t2 + double(n2 - 1) * dt[2]);
-            if (cq != 0.0) {
-              // replay B: the same faces one by one, for each voxel's length
-              double u0 = t0, u1 = t1, u2 = t2, tc = t;
-              int m0 = n0, m1 = n1, m2 = n2;
-              int jx[3] = {p.ix[0], p.ix[1], p.ix[2]};
-              for (int left = n0 + n1 + n2; left > 0; --left) {
-                // next face among the axes with faces left; ties in x, y, z order
-                const bool a0 = m0 > 0 && (m1 <= 0 || u0 <= u1) && (m2 <= 0 || u0 <= u2);
-                const bool a1 = !a0 && m1 > 0 && (m2 <= 0 || u1 <= u2);
-                const bool a2 = !a0 && !a1;
-                const double uk = a0 ? u0 : (a1 ? u1 : u2);
-                unsafeAtomicAdd(&a.adj_grad[vlin(a, jx)], cq * (-(MMF ? mu_of(v) : mud) * (uk - tc)));
-                tc = uk;
-                u0 = a0 ? u0 + dt[0] : u0;
-                u1 = a1 ? u1 + dt[1] : u1;
-                u2 = a2 ? u2 + dt[2] : u2;
-                jx[0] += a0 ? stp[0] : 0;
-                jx[1] += a1 ? stp[1] : 0;
-                jx[2] += a2 ? stp[2] : 0;
-                m0 -= a0 ? 1 : 0;
-                m1 -= a1 ? 1 : 0;
-                m2 -= a2 ? 1 : 0;
-              }
-            }
-            tau = fmax(tau - rho_v * (tl - t), 0.0);
-            t = tl;
-            p.ix[0] += stp[0] * n0;
-            p.ix[1] += stp[1] * n1;
-            p.ix[2] += stp[2] * n2;
-            t0 += double(n0) * dt[0];
-            t1 += double(n1) * dt[1];
-            t2 += double(n2) * dt[2];
-            ls.crossings += uint32_t(n0 + n1 + n2);
-            v = vlin(a, p.ix);
-          }
-        }
-        // branch-free: the lanes of a wavefront walk different axes
-        double seg[kWalk], tend[kWalk];
-        uint32_t vs[kWalk + 1];
-        int axs[kWalk];
-        bool outs[kWalk];
-        {
-          double u0 = t0, u1 = t1, u2 = t2, tc = t;
-          int j0 = p.ix[0], j1 = p.ix[1], j2 = p.ix[2];
-          uint32_t vc = v;
-          bool gone = false;  // an earlier segment of this batch leaves the phantom
-#pragma unroll
-          for (int j = 0; j < kWalk; ++j) {
-            const bool a0 = (u0 <= u1) & (u0 <= u2);
-            const bool a1 = !a0 & (u1 <= u2);
-            const bool a2 = !a0 & !a1;
-            const double tf = a0 ? u0 : (a1 ? u1 : u2);
-            seg[j] = tf - tc;
-            tend[j] = tf;
-            vs[j] = vc;
-            axs[j] = a0 ? 0 : (a1 ? 1 : 2);
-            j0 += a0 ? stp[0] : 0;
-            j1 += a1 ? stp[1] : 0;
-            j2 += a2 ? stp[2] : 0;
-            u0 = a0 ? u0 + dt[0] : u0;
-            u1 = a1 ? u1 + dt[1] : u1;
-            u2 = a2 ? u2 + dt[2] : u2;
-            const bool out = (j0 < 0) | (j0 >= nn[0]) | (j1 < 0) | (j1 >= nn[1]) | (j2 < 0) | (j2 >= nn[2]);
-            outs[j] = out;
-            gone = gone | out;
-            const int jx[3] = {j0, j1, j2};
-            vc = gone ? vc : vlin(a, jx);
-            tc = tf;
-          }
-          vs[kWalk] = vc;
-        }
-        double rr[kWalk];
-#pragma unroll
-        for (int j = 0; j < kWalk; ++j) rr[j] = att(vs[j]);
-        // the voxel after the last segment: where the next pass starts
-        const double rho_n = att(vs[kWalk]);
-        const uint32_t cube_n = a.cube[vs[kWalk]];
-#pragma unroll
-        for (int j = 0; j < kWalk; ++j) {
-          const double rho = rr[j], sj = seg[j];
-          const bool act = !ended;
-          const bool hit = act & (rho * sj >= tau);
-          const bool pass = act & !hit;
-          if (cq != 0.0 && act) {
-            // several materials: rho here is rho mu_m, tau an optical depth
-            const double muj = MMF ? mu_of(vs[j]) : mud;
-            const double rj = MMF ? double(a.rho[vs[j]]) : rho;
-            unsafeAtomicAdd(&a.adj_grad[vs[j]], hit ? cq * (-muj * (tau / rho) + 1.0 / rj) : cq * (-muj * sj));
-          }
-          t = hit ? t + tau / rho : (pass ? tend[j] : t);
-          tau = pass ? tau - rho * sj : tau;
-          p.ix[0] += (pass & (axs[j] == 0)) ? stp[0] : 0;
-          p.ix[1] += (pass & (axs[j] == 1)) ? stp[1] : 0;
-          p.ix[2] += (pass & (axs[j] == 2)) ? stp[2] : 0;
-          t0 = (pass & (axs[j] == 0)) ? t0 + dt[0] : t0;
-          t1 = (pass & (axs[j] == 1)) ? t1 + dt[1] : t1;
-          t2 = (pass & (axs[j] == 2)) ? t2 + dt[2] : t2;
-          ls.crossings += pass ? 1u : 0u;
-          const bool esc = pass & outs[j];
-          esc_v = esc ? vs[j] : esc_v;
-          escaped = escaped | esc;
-          v = (pass & !outs[j]) ? vs[j + 1] : v;
-          ended = ended | hit | esc;
-        }
-        rho_v = rho_n;
-        cube_v = cube_n;
-      }
-      if (escaped) {
-        ledger_escape(a, &bs, p);
-        event(a, p, EV_PH_ESCAPE, esc_v);
-        finish(a, p);
-      }
-      move(p, t);
-      if (!escaped) {
-        if constexpr (MMF) {
-          // the interaction by the tables of the voxel the photon stops in
-          const T* tm = tab + int(a.mat[v]) * T_PHOTON_END * nt;
-          mu[0] = interp(tm, nt, T_LMU_C, g, e, T(0));
-          mu[1] = interp(tm, nt, T_LMU_PE, g, e, T(0));
-          mu[2] = interp(tm, nt, T_LMU_R, g, e, T(0));
-          mu[3] = interp(tm, nt, T_LMU_PP, g, e, a.tb.thr_pp);
-          mt = mu[0] + mu[1] + mu[2] + mu[3];
-        }
-        const T u = uni<T>(p.rng) * mt;
-        T cum = T(0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          cum += mu[k];
-          if (ch < 0 && u < cum) ch = k;
-        }
-        if (ch < 0) {
-#pragma unroll
-          for (int k = 3; k >= 0; --k)
-            if (ch < 0 && mu[k] > T(0)) ch = k;
-        }
-      }
+      ch = photon_flight<T, F>(a, tab, p, ls, &bs);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -642,6 +668,80 @@ __device__ __forceinline__ void make_child(const KArgs<T>& a, Part<T>& p, Child<
   c.uid = child_uid(p.uid, k);
 }
 
+// One photon interaction of channel q at the photon's position (KNOCK):
+// secondaries in c1 (and c2 for pair production); returns whether the photon
+// goes on (Compton above Eabs, Rayleigh), else its history record is finished.
+template <typename T, int F>
+__device__ __forceinline__ bool photon_interact(const KArgs<T>& a, int q, Part<T>& p, Child<T>& c1, Child<T>& c2,
+                                                DepAcc& acc, LaneStats& ls, BlockStats* bs) {
+  bool keep = false;
+  const uint32_t v = vlin(a, p.ix);
+  if (q == 0) {
+    stat_add(bs, S_COMPTON);
+    T cost;
+    const T kap = sample_kn(p.rng, p.e, &cost);
+    const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+    const T d0[3] = {p.d[0], p.d[1], p.d[2]};
+    rotate(p.d, cost, phi);
+    const T ep = kap * p.e;
+    const T te = p.e - ep;
+    T pe[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pe[k] = p.e * d0[k] - ep * p.d[k];
+    const T nn = M<T>::sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
+    if (nn > T(0)) { pe[0] /= nn; pe[1] /= nn; pe[2] /= nn; }
+    else { pe[0] = d0[0]; pe[1] = d0[1]; pe[2] = d0[2]; }
+    make_child(a, p, c1, ELECTRON, te, pe, acc, ls, bs);
+    if (ep > a.eabs[PHOTON]) {
+      p.e = ep;
+      keep = true;
+    } else {
+      deposit(a, acc, ls, p, ep);
+      stat_add(bs, S_ABSORBED);
+    }
+    event(a, p, EV_COMPTON, v);
+  } else if (q == 1) {
+    stat_add(bs, S_PHOTO);
+    make_child(a, p, c1, ELECTRON, p.e, p.d, acc, ls, bs);
+    stat_add(bs, S_ABSORBED);
+    event(a, p, EV_PHOTO, v);
+  } else if (q == 2) {
+    stat_add(bs, S_RAYLEIGH);
+    const T ct = sample_rayleigh(p.rng, p.e, several(F) ? mat_const(a.tb, a.mat[v]).ray_a : a.tb.ray_a);
+    const T phi = T(2.0 * kPi) * uni<T>(p.rng);
+    rotate(p.d, ct, phi);
+    keep = true;
+    event(a, p, EV_RAYLEIGH, v);
+  } else {
+    stat_add(bs, S_PAIR);
+    const T avail = p.e - T(2.0 * kMc2);
+    const T eps = uni<T>(p.rng);
+    const T tm = eps * avail, tp = (T(1) - eps) * avail;
+    T dm[3] = {p.d[0], p.d[1], p.d[2]};
+    T dp[3] = {p.d[0], p.d[1], p.d[2]};
+    const T cm = leading_angle(beta_of(tm), uni<T>(p.rng));
+    const T fm = T(2.0 * kPi) * uni<T>(p.rng);
+    const T cp = leading_angle(beta_of(tp), uni<T>(p.rng));
+    const T fp = T(2.0 * kPi) * uni<T>(p.rng);
+    rotate(dm, cm, fm);
+    rotate(dp, cp, fp);
+    make_child(a, p, c1, ELECTRON, tm, dm, acc, ls, bs);
+    make_child(a, p, c2, POSITRON, tp, dp, acc, ls, bs);
+    stat_add(bs, S_ABSORBED);
+    event(a, p, EV_PAIR, v);
+  }
+  if (!keep) finish(a, p);
+  return keep;
+}
+
+// Photon interactions.  While many photons are in flight, a launch performs
+// one interaction per photon and hands the scattered photon to the next
+// iteration's flight kernel.  Once at most MCX_CHAIN_PHOTONS photons wait for
+// an interaction, each lane follows its photon through every further flight
+// and interaction to its end (the secondaries go to the e+- queue as they are
+// made), so that the last photons of long scattering chains do not each cost
+// an iteration of every kernel.  Each particle draws from its own random
+// stream, so the result does not depend on which kernel runs a flight.
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
   set_flavor<F>(a);
@@ -650,10 +750,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
   const uint32_t n2 = min(C->n[Q_KR].v, a.cap), n3 = min(C->n[Q_KX].v, a.cap);
   const uint32_t e1 = n0 + n1, e2 = e1 + n2, ntot = e2 + n3;
   if (blockIdx.x * blockDim.x >= ntot) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tab = reinterpret_cast<T*>(smem);
   __shared__ BlockStats bs;
   LaneStats ls;
   stats_init(&bs, ls);
+  const bool chain = ntot <= uint32_t(MCX_CHAIN_PHOTONS);  // uniform over the grid
+  if (chain) stage_photon<T, F>(a, tab);
   __syncthreads();
+  const int eo = q_eout(par);
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t base = blockIdx.x * blockDim.x; base < ntot; base += stride) {
     const uint32_t i = base + threadIdx.x;
@@ -664,73 +769,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
     bool keep = false;
     DepAcc acc = dep_init();
     if (i < ntot) {
-      const int q = i < n0 ? 0 : (i < e1 ? 1 : (i < e2 ? 2 : 3));
+      int q = i < n0 ? 0 : (i < e1 ? 1 : (i < e2 ? 2 : 3));
       const uint32_t j = i - (q == 0 ? 0u : (q == 1 ? n0 : (q == 2 ? e1 : e2)));
       load_part(a, a.q[Q_KC + q], j, p);
-      const uint32_t v = vlin(a, p.ix);
-      if (q == 0) {
-        stat_add(&bs, S_COMPTON);
-        T cost;
-        const T kap = sample_kn(p.rng, p.e, &cost);
-        const T phi = T(2.0 * kPi) * uni<T>(p.rng);
-        const T d0[3] = {p.d[0], p.d[1], p.d[2]};
-        rotate(p.d, cost, phi);
-        const T ep = kap * p.e;
-        const T te = p.e - ep;
-        T pe[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pe[k] = p.e * d0[k] - ep * p.d[k];
-        const T nn = M<T>::sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
-        if (nn > T(0)) { pe[0] /= nn; pe[1] /= nn; pe[2] /= nn; }
-        else { pe[0] = d0[0]; pe[1] = d0[1]; pe[2] = d0[2]; }
-        make_child(a, p, c1, ELECTRON, te, pe, acc, ls, &bs);
-        if (ep > a.eabs[PHOTON]) {
-          p.e = ep;
-          keep = true;
-        } else {
-          deposit(a, acc, ls, p, ep);
-          stat_add(&bs, S_ABSORBED);
-        }
-        event(a, p, EV_COMPTON, v);
-      } else if (q == 1) {
-        stat_add(&bs, S_PHOTO);
-        make_child(a, p, c1, ELECTRON, p.e, p.d, acc, ls, &bs);
-        stat_add(&bs, S_ABSORBED);
-        event(a, p, EV_PHOTO, v);
-      } else if (q == 2) {
-        stat_add(&bs, S_RAYLEIGH);
-        const T ct = sample_rayleigh(p.rng, p.e, several(F) ? mat_const(a.tb, a.mat[v]).ray_a : a.tb.ray_a);
-        const T phi = T(2.0 * kPi) * uni<T>(p.rng);
-        rotate(p.d, ct, phi);
-        keep = true;
-        event(a, p, EV_RAYLEIGH, v);
-      } else {
-        stat_add(&bs, S_PAIR);
-        const T avail = p.e - T(2.0 * kMc2);
-        const T eps = uni<T>(p.rng);
-        const T tm = eps * avail, tp = (T(1) - eps) * avail;
-        T dm[3] = {p.d[0], p.d[1], p.d[2]};
-        T dp[3] = {p.d[0], p.d[1], p.d[2]};
-        const T cm = leading_angle(beta_of(tm), uni<T>(p.rng));
-        const T fm = T(2.0 * kPi) * uni<T>(p.rng);
-        const T cp = leading_angle(beta_of(tp), uni<T>(p.rng));
-        const T fp = T(2.0 * kPi) * uni<T>(p.rng);
-        rotate(dm, cm, fm);
-        rotate(dp, cp, fp);
-        make_child(a, p, c1, ELECTRON, tm, dm, acc, ls, &bs);
-        make_child(a, p, c2, POSITRON, tp, dp, acc, ls, &bs);
-        stat_add(&bs, S_ABSORBED);
-        event(a, p, EV_PAIR, v);
+      keep = photon_interact<T, F>(a, q, p, c1, c2, acc, ls, &bs);
+      while (chain && keep) {
+        // this interaction's secondaries (made where the photon is now), then
+        // the photon's next flight and interaction
+        const uint32_t t1 = append(a, eo, c1.on);
+        if (c1.on && t1 != ~0u) store_child(a, a.q[eo], t1, p, c1);
+        const uint32_t t2 = append(a, eo, c2.on);
+        if (c2.on && t2 != ~0u) store_child(a, a.q[eo], t2, p, c2);
+        c1.on = false;
+        c2.on = false;
+        q = photon_flight<T, F>(a, tab, p, ls, &bs);
+        keep = q >= 0 && photon_interact<T, F>(a, q, p, c1, c2, acc, ls, &bs);
       }
-      if (!keep) finish(a, p);
       dep_flush(a, acc, ls);
     }
     const uint32_t sg = append(a, q_gout(par), keep);
     if (keep && sg != ~0u) store_part(a, a.q[q_gout(par)], sg, p);
-    const uint32_t s1 = append(a, q_eout(par), c1.on);
-    if (c1.on && s1 != ~0u) store_child(a, a.q[q_eout(par)], s1, p, c1);
-    const uint32_t s2 = append(a, q_eout(par), c2.on);
-    if (c2.on && s2 != ~0u) store_child(a, a.q[q_eout(par)], s2, p, c2);
+    const uint32_t s1 = append(a, eo, c1.on);
+    if (c1.on && s1 != ~0u) store_child(a, a.q[eo], s1, p, c1);
+    const uint32_t s2 = append(a, eo, c2.on);
+    if (c2.on && s2 != ~0u) store_child(a, a.q[eo], s2, p, c2);
   }
   stats_flush(&bs, ls, a.cnt);
 }
