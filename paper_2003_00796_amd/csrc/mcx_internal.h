@@ -113,6 +113,7 @@ struct Counters {
   uint64_t stat[S_NSTAT];
   double e_dep, e_esc;
   uint64_t occupied;       // tally pairs seen by the last flush
+  uint32_t knock_peak;     // most photons an interaction launch of the chunk took (the photon-chain switch)
 };
 
 // A queue record is 4 (FP32 physics) or 5 (FP64) chunks of 16 bytes; chunk k

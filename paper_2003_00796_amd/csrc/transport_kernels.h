@@ -17,6 +17,9 @@
 #ifndef MCX_CHAIN_PHOTONS
 #define MCX_CHAIN_PHOTONS 131072
 #endif
+#ifndef MCX_CHAIN_DIV
+#define MCX_CHAIN_DIV 8
+#endif
 // tail of the e+- kernel: once the input queue is empty, a wavefront keeps
 // stepping its particles for at least MCX_TAIL_MIN more steps, then writes
 // them all back as soon as fewer than MCX_TAIL_ALIVE of its lanes hold one
@@ -736,11 +739,15 @@ __device__ __forceinline__ bool photon_interact(const KArgs<T>& a, int q, Part<T
 
 // Photon interactions.  While many photons are in flight, a launch performs
 // one interaction per photon and hands the scattered photon to the next
-// iteration's flight kernel.  Once at most MCX_CHAIN_PHOTONS photons wait for
-// an interaction, each lane follows its photon through every further flight
-// and interaction to its end (the secondaries go to the e+- queue as they are
-// made), so that the last photons of long scattering chains do not each cost
-// an iteration of every kernel.  Each particle draws from its own random
+// iteration's flight kernel.  In the tail of a chunk (at most
+// MCX_CHAIN_PHOTONS photons wait for an interaction, and at most
+// 1/MCX_CHAIN_DIV of the chunk's largest interaction launch) each lane
+// follows its photon through every further flight and interaction to its
+// end (the secondaries go to the e+- queue as they are made), so that the
+// last photons of long scattering chains do not each cost an iteration of
+// every kernel.  The relative bound keeps small runs, whose photons would
+// all be chained from the start, on the flight kernel, which walks the
+// voxels at a higher occupancy.  Each particle draws from its own random
 // stream, so the result does not depend on which kernel runs a flight.
 template <typename T, int F>
 __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
@@ -755,7 +762,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
   __shared__ BlockStats bs;
   LaneStats ls;
   stats_init(&bs, ls);
-  const bool chain = ntot <= uint32_t(MCX_CHAIN_PHOTONS);  // uniform over the grid
+  // the peak of earlier launches (this launch raises it only when it takes
+  // more photons than any before, and then chains nothing either way)
+  const uint32_t peak = C->knock_peak;
+  const bool chain = ntot <= uint32_t(MCX_CHAIN_PHOTONS) && uint64_t(ntot) * MCX_CHAIN_DIV <= peak;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && ntot > peak) atomicMax(&C->knock_peak, ntot);
   if (chain) stage_photon<T, F>(a, tab);
   __syncthreads();
   const int eo = q_eout(par);
@@ -1463,6 +1474,7 @@ __global__ void k_chunk_init(Counters* c, uint64_t first, uint64_t end, uint64_t
   c->run_first = run_first;
   c->adm = adm;
   c->occupied = 0ull;
+  c->knock_peak = 0u;
   c->take_e.v = 0u;
 }
 
