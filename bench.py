@@ -512,7 +512,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--hist", type=int, default=10_000_000, help="histories per step")
     ap.add_argument("--cpu-sample", type=int, default=6_000, help="oracle histories per host process")
-    # a GPU machine's share of host cores is 16, whatever os.cpu_count() reports there
+    # the host share of a one-GPU benchmark node is 16 cores, whatever os.cpu_count() reports
     ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes (host cores used)")
     ap.add_argument("--no-cpu-configs", action="store_true", help="time the oracle on the benchmark workload only")
     ap.add_argument("--no-electron", action="store_true", help="skip the 20 MeV electron workload")
