@@ -91,9 +91,10 @@ constexpr bool is_fp64() { return std::is_same<T, double>::value; }
 #define MCX_RNG_PAIRS 4
 #endif
 #ifndef MCX_RNG_PAIRS_FP64
-#define MCX_RNG_PAIRS_FP64 2
+#define MCX_RNG_PAIRS_FP64 4
 #endif
-// calls held per particle: FP64 draw words take twice the registers
+// calls held per particle (eight draws cover a typical hard-event step; the
+// FP64 words take twice the registers, which the FP64 kernels' 256 hold)
 template <typename T>
 constexpr int rng_pairs() { return std::is_same<T, double>::value ? MCX_RNG_PAIRS_FP64 : MCX_RNG_PAIRS; }
 
