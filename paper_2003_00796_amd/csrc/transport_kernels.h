@@ -20,6 +20,11 @@
 #ifndef MCX_CHAIN_DIV
 #define MCX_CHAIN_DIV 8
 #endif
+// the interaction kernel, with the photon flight inlined for the chains,
+// needs about 250 registers in FP64: bound it to 2 waves per SIMD
+#ifndef MCX_KNOCK_WAVES
+#define MCX_KNOCK_WAVES 2
+#endif
 // tail of the e+- kernel: once the input queue is empty, a wavefront keeps
 // stepping its particles for at least MCX_TAIL_MIN more steps, then writes
 // them all back as soon as fewer than MCX_TAIL_ALIVE of its lanes hold one
@@ -750,7 +755,7 @@ __device__ __forceinline__ bool photon_interact(const KArgs<T>& a, int q, Part<T
 // voxels at a higher occupancy.  Each particle draws from its own random
 // stream, so the result does not depend on which kernel runs a flight.
 template <typename T, int F>
-__global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
+__global__ __launch_bounds__(kMaxBlock, MCX_KNOCK_WAVES) void k_knock(KArgs<T> a, int par) {
   set_flavor<F>(a);
   Counters* C = a.cnt;
   const uint32_t n0 = min(C->n[Q_KC].v, a.cap), n1 = min(C->n[Q_KP].v, a.cap);
@@ -770,6 +775,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
   if (chain) stage_photon<T, F>(a, tab);
   __syncthreads();
   const int eo = q_eout(par);
+  const uint32_t cs = stripe_cap(a);
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t base = blockIdx.x * blockDim.x; base < ntot; base += stride) {
     const uint32_t i = base + threadIdx.x;
@@ -786,13 +792,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_knock(KArgs<T> a, int par) {
       keep = photon_interact<T, F>(a, q, p, c1, c2, acc, ls, &bs);
       while (chain && keep) {
         // this interaction's secondaries (made where the photon is now), then
-        // the photon's next flight and interaction
+        // the photon's next flight and interaction; a chain stops (its photon
+        // goes on in the next iteration) once the secondaries fill half of an
+        // e+- queue stripe, so that long chains cannot overflow a small bank
         const uint32_t t1 = append(a, eo, c1.on);
         if (c1.on && t1 != ~0u) store_child(a, a.q[eo], t1, p, c1);
         const uint32_t t2 = append(a, eo, c2.on);
         if (c2.on && t2 != ~0u) store_child(a, a.q[eo], t2, p, c2);
+        const bool half = (c1.on && t1 != ~0u && t1 % cs >= cs / 2) || (c2.on && t2 != ~0u && t2 % cs >= cs / 2);
         c1.on = false;
         c2.on = false;
+        if (half) break;
         q = photon_flight<T, F>(a, tab, p, ls, &bs);
         keep = q >= 0 && photon_interact<T, F>(a, q, p, c1, c2, acc, ls, &bs);
       }
