@@ -558,7 +558,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the transport shards by history range "
-              "and would need one all-reduce of the tallies, which this build does not launch.", file=sys.stderr)
+              "and would need one all-reduce of the tallies, which the single-GPU benchmark does not perform.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -42,7 +42,7 @@ extern "C" {
 #define MCX_E_DEVICE (-4)      /* HIP runtime error or device fault */
 #define MCX_E_RANGE (-5)       /* a capacity or energy range exceeded */
 #define MCX_E_CANCELLED (-6)   /* run stopped on request (mcx_cancel) */
-#define MCX_E_UNSUPPORTED (-7) /* feature not available in this build */
+#define MCX_E_UNSUPPORTED (-7) /* feature not available in this library */
 
 #define MCX_FP64 0   /* all physics and sampling in FP64 */
 #define MCX_MIXED 1  /* FP32 physics and sampling; FP64 positions, boundary
