@@ -7,6 +7,10 @@
 #ifndef MCX_ESTEP_WAVES
 #define MCX_ESTEP_WAVES 2
 #endif
+// blocks of the tally flush, which loops over the table's span
+#ifndef MCX_FLUSH_GRID
+#define MCX_FLUSH_GRID 2048
+#endif
 #include <algorithm>
 
 #include "transport_kernels.h"
@@ -79,7 +83,7 @@ hipError_t launch_clear_table(TSlot* tab, uint64_t nslot, hipStream_t s) {
 
 hipError_t launch_flush(TSlot* tab, uint64_t nslot, double* sum_q, double* sum_q2, Counters* cnt,
                         int test_mode, double* hist_led, uint64_t n_run, hipStream_t s) {
-  hipLaunchKernelGGL(k_flush<double>, dim3(8192), dim3(256), 0, s, tab, nslot, sum_q, sum_q2, cnt, test_mode,
+  hipLaunchKernelGGL(k_flush<double>, dim3(MCX_FLUSH_GRID), dim3(256), 0, s, tab, nslot, sum_q, sum_q2, cnt, test_mode,
                      hist_led, n_run);
   return hipGetLastError();
 }
