@@ -72,22 +72,67 @@ __global__ void k_flush_influence(TSlot* tab, uint64_t nslot, double* sum_q2, Co
   if (__lane_id() == 0 && dep != 0.0) unsafeAtomicAdd(&cnt->e_dep, dep);
 }
 
-// occupied entries of the (source, voxel) table, in slot order of arrival;
-// entries beyond cap are counted, not written
-__global__ void k_influence_compact(const uint64_t* ikeys, const double* iq, const double* iq2, uint64_t nslot,
-                                    uint32_t* osrc, uint32_t* ovox, double* oq, double* oq2, uint64_t cap,
-                                    unsigned long long* count) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < nslot; s += stride) {
-    const uint64_t k = ikeys[s];
-    if (k == kEmptyKey) continue;
-    const unsigned long long i = atomicAdd(count, 1ull);
-    if (i < cap) {
-      osrc[i] = uint32_t(k >> 32);
-      ovox[i] = uint32_t(k & 0xFFFFFFFFull);
-      oq[i] = iq[s];
-      oq2[i] = iq2[s];
+// occupied entries of the (source, voxel) table, in no fixed order; entries
+// beyond cap are counted, not written.  The places are handed out by one
+// counter, which serialises every atomic taken on it (~1e8 per second), so a
+// block reserves them once per tile of kCompactBlock x kCompactPer slots:
+// each thread holds its kCompactPer keys in registers, the block sums the
+// threads' counts (shuffles within a wavefront, LDS across them), thread 0
+// takes the tile's places, and each thread writes its entries from its
+// prefix on
+constexpr int kCompactBlock = 256;
+constexpr int kCompactPer = 16;
+
+__global__ __launch_bounds__(kCompactBlock) void k_influence_compact(const uint64_t* ikeys, const double* iq,
+                                                                     const double* iq2, uint64_t nslot, uint32_t* osrc,
+                                                                     uint32_t* ovox, double* oq, double* oq2,
+                                                                     uint64_t cap, unsigned long long* count) {
+  constexpr int kWaves = kCompactBlock / 64;
+  __shared__ uint32_t wave_total[kWaves];
+  __shared__ unsigned long long tile_base;
+  const uint32_t lane = __lane_id(), wave = threadIdx.x / 64;
+  const uint64_t tile = uint64_t(kCompactBlock) * kCompactPer;
+  // t0 depends on the block only: every thread runs the same tiles
+  for (uint64_t t0 = uint64_t(blockIdx.x) * tile; t0 < nslot; t0 += uint64_t(gridDim.x) * tile) {
+    uint64_t k[kCompactPer];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      const uint64_t s = t0 + uint64_t(j) * kCompactBlock + threadIdx.x;
+      k[j] = s < nslot ? ikeys[s] : kEmptyKey;
+      mine += k[j] != kEmptyKey ? 1u : 0u;
     }
+    uint32_t incl = mine;  // inclusive prefix of the counts within the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= uint32_t(o)) incl += y;
+    }
+    if (lane == 63) wave_total[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wave_total[w];
+      before += uint32_t(w) < wave ? c : 0u;
+      total += c;
+    }
+    if (threadIdx.x == 0) tile_base = total ? atomicAdd(count, (unsigned long long)total) : 0ull;
+    __syncthreads();
+    unsigned long long i = tile_base + before + (incl - mine);
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      if (k[j] == kEmptyKey) continue;
+      if (i < cap) {
+        const uint64_t s = t0 + uint64_t(j) * kCompactBlock + threadIdx.x;
+        osrc[i] = uint32_t(k[j] >> 32);
+        ovox[i] = uint32_t(k[j] & 0xFFFFFFFFull);
+        oq[i] = iq[s];
+        oq2[i] = iq2[s];
+      }
+      ++i;
+    }
+    __syncthreads();  // wave_total and tile_base are written again by the next tile
   }
 }
 
@@ -105,7 +150,7 @@ hipError_t launch_flush_influence(TSlot* tab, uint64_t nslot, double* sum_q2, Co
 hipError_t launch_influence_compact(const uint64_t* ikeys, const double* iq, const double* iq2, uint64_t nslot,
                                     uint32_t* osrc, uint32_t* ovox, double* oq, double* oq2, uint64_t cap,
                                     unsigned long long* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_influence_compact, dim3(4096), dim3(256), 0, s, ikeys, iq, iq2, nslot, osrc, ovox, oq, oq2,
+  hipLaunchKernelGGL(k_influence_compact, dim3(4096), dim3(kCompactBlock), 0, s, ikeys, iq, iq2, nslot, osrc, ovox, oq, oq2,
                      cap, count);
   return hipGetLastError();
 }
