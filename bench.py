@@ -378,7 +378,7 @@ def beamlet_comparison(mcx, W, sync, total: int, cache: str) -> dict:
     sim.run(1, 0, sim.n_hist_total)
     sync()
     t_infl = time.perf_counter() - t0
-    n_entries = sim.influence()[0].size
+    n_entries = sim.influence_count()
     sim.set_influence(False)
     sim.reset()
     sync()

@@ -350,19 +350,29 @@ class Simulator:
         Sum q^2 accumulated by later runs (see mcx_set_influence)."""
         self._check(self._L.mcx_set_influence(self._h, 1 if on else 0, log2_slots), "set_influence")
 
-    def influence(self):
-        """(source, voxel, sum_q, sum_q2) arrays of the influence table,
-        sorted by source, then voxel."""
+    def influence_count(self) -> int:
+        """Number of (source, voxel) entries in the influence table."""
         n = C.c_uint64(0)
         self._check(self._L.mcx_get_influence(self._h, None, None, None, None, 0, C.byref(n)), "get_influence")
-        k = n.value
+        return n.value
+
+    def influence(self, sort: bool = True):
+        """(source, voxel, sum_q, sum_q2) arrays of the influence table,
+        sorted by source, then voxel (sort=False: in the library's order,
+        which saves a host sort of every entry)."""
+        k = self.influence_count()
         src = np.zeros(k, dtype=np.uint32)
         vox = np.zeros(k, dtype=np.uint32)
         q = np.zeros(k)
         q2 = np.zeros(k)
         if k:
+            n = C.c_uint64(0)
             self._check(self._L.mcx_get_influence(self._h, _ptr(src), _ptr(vox), _ptr(q), _ptr(q2), k, C.byref(n)),
                         "get_influence")
+            if n.value != k:
+                raise RuntimeError(f"influence table changed between the count ({k}) and the read ({n.value})")
+        if not sort:
+            return src, vox, q, q2
         order = np.lexsort((vox, src))
         return src[order], vox[order], q[order], q2[order]
 

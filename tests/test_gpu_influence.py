@@ -93,7 +93,8 @@ def test_influence_accumulates_resets_and_reports_overflow():
 def test_influence_of_512_beamlets():
     """The 512-beamlet workload on the 256^3 noise phantom (2e6 histories,
     mixed precision, one run): every beamlet has entries, and they add up to
-    the voxel tallies."""
+    the voxel tallies; the count-only call and the unsorted read (the
+    device compaction's own order) give the same entries."""
     mcx = _mcx()
     wl = W.workload("beamlets_256", 2_000_000)
     n = sum(s["n_hist"] for s in wl["sources"])
@@ -101,8 +102,14 @@ def test_influence_of_512_beamlets():
     sim.set_influence(True, 27)
     sim.run(wl["seed"], 0, n)
     src, vox, q, q2 = sim.influence()
+    count = sim.influence_count()
+    raw = sim.influence(sort=False)
     tq, tq2 = sim.tally()
     sim.close()
+    assert count == src.size
+    order = np.lexsort((raw[1], raw[0]))
+    for a, b in zip(raw, (src, vox, q, q2)):
+        assert np.array_equal(a[order], b)
     print("influence entries", src.size, "per beamlet", src.size / 512)
     assert len(np.unique(src)) == 512
     tot = np.zeros(tq.size)
