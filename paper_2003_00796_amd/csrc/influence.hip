@@ -53,8 +53,12 @@ __global__ void k_flush_influence(TSlot* tab, uint64_t nslot, double* sum_q2, Co
     uint64_t slot = mix64(ik) & imask;
     int probe = 0;
     for (; probe < 4096; ++probe) {
-      const uint64_t o =
-          atomicCAS((unsigned long long*)&ikeys[slot], (unsigned long long)kEmptyKey, (unsigned long long)ik);
+      // a key stays in its slot until the table is cleared, so a load that
+      // finds one (this entry's or another's) needs no compare-and-swap; only
+      // a slot seen empty is claimed, and the swap returns what is there now
+      uint64_t o = __hip_atomic_load(&ikeys[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (o == kEmptyKey)
+        o = atomicCAS((unsigned long long*)&ikeys[slot], (unsigned long long)kEmptyKey, (unsigned long long)ik);
       if (o == kEmptyKey || o == ik) {
         unsafeAtomicAdd(&iq[slot], q);
         unsafeAtomicAdd(&iq2[slot], q * q);
