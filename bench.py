@@ -199,12 +199,18 @@ def progress(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_steps(sim, n, seeds, sync, doses=None):
+def run_steps(sim, n, seeds, sync, doses=None, time_last=False):
     """One timed run per seed (tallies reset before each); with `doses`, each
-    step's dose is appended to it after the timed region."""
+    step's dose is appended to it after the timed region.  With `time_last`
+    the last run records HIP events around its kernel launches, which the
+    roofline reads (the statistics cover the last run alone); the other runs
+    replay their batches of iterations as graphs, as untimed runs do (a run
+    with events launches its kernels one by one)."""
     times = []
-    for s in seeds:
+    for i, s in enumerate(seeds):
         sim.reset()
+        if time_last and i == len(seeds) - 1:
+            sim.set_timing(True)
         sync()
         t0 = time.perf_counter()
         sim.run(s, 0, n)
@@ -578,9 +584,8 @@ def main():
     mix = mcx.Simulator(mcx.MIXED, 0).setup(wl)
     mix.set_launch(args.bank, 256, 128)
     run_steps(mix, n, warm_seeds, sync)
-    mix.set_timing(True)
     doses_mix = []
-    t_mix = run_steps(mix, n, seeds, sync, doses_mix)
+    t_mix = run_steps(mix, n, seeds, sync, doses_mix, time_last=True)
     st = mix.stats()
     d_mix, s_mix = mix.dose()
     mix.close()
@@ -591,9 +596,8 @@ def main():
         f64 = mcx.Simulator(mcx.FP64, 0).setup(wl)
         f64.set_launch(args.bank, 256, 128)
         run_steps(f64, n, warm_seeds, sync)
-        f64.set_timing(True)
         doses_64 = []
-        t_64 = run_steps(f64, n, seeds, sync, doses_64)
+        t_64 = run_steps(f64, n, seeds, sync, doses_64, time_last=True)
         d_64, _ = f64.dose()
         st_64 = f64.stats()
         f64.close()
